@@ -1,0 +1,176 @@
+/*
+ * ads.h -- C-ABI of the MI355X (gfx950) alternating-direction isogeometric
+ * wave solver.
+ *
+ * Method: Los, Behnoudfar, Paszynski, Calo, "Fast isogeometric solvers for
+ * hyperbolic wave propagation problems" (arXiv:1911.08158).
+ *   - P-wave problem u'' - Laplace(u) = f on the unit cube (Section 2),
+ *     tensor-product B-splines, Newmark (beta = 1/4) implicit step whose
+ *     left-hand side M + (tau^2/4) K is replaced by the Kronecker product of
+ *     1D operators (M_d + (tau^2/4) K_d) (eq. pwave2).
+ *   - Isotropic linear elasticity (Section 5): alternating-triangular
+ *     decoupling (eq. decom, eq. pre, eq. corr) with a direction split of
+ *     every diagonal block (eq. spill), i.e. the three-level scheme eq. gen.
+ *   - Every split operator is inverted by three sets of 1D banded solves,
+ *     along x-lines, then y-lines, then z-lines (Appendix).
+ *
+ * Conventions (all functions):
+ *   - Coefficient arrays exchanged through this ABI are FP64 DEVICE arrays on
+ *     the FULL index set, n_x * n_y * n_z entries per component with
+ *     n_d = nelem[d] + p, laid out [z][y][x] (x fastest); elasticity arrays
+ *     hold the three components one after the other ([c][z][y][x]).
+ *   - Zero Dirichlet conditions: the first and last basis function of every
+ *     direction are eliminated.  Boundary entries of input arrays are ignored;
+ *     boundary entries of output arrays are written as 0.
+ *   - The library never allocates device memory.  Every device byte it uses
+ *     lives in the caller's workspace (size from ads_workspace_bytes); the
+ *     caller keeps the workspace alive until ads_destroy and the stream is
+ *     idle.  Input pointers are read during the call's enqueue only.
+ *   - Work is enqueued on the HIP stream given to ads_create and is
+ *     asynchronous unless a function says otherwise.  A NULL stream means the
+ *     default stream.
+ *   - Every function returns an ads_status; nothing throws or aborts across
+ *     the ABI.  ads_last_error() gives a thread-local message for the last
+ *     non-OK status.
+ */
+#ifndef ADS_H
+#define ADS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADS_OK = 0,
+  ADS_EINVAL = -1,   /* invalid argument (sizes, degree, tau, material, NULL) */
+  ADS_ENOMEM = -2,   /* workspace too small / capacity exceeded             */
+  ADS_EDEVICE = -3,  /* a HIP call failed                                    */
+  ADS_ESTATE = -4,   /* call out of order (e.g. ads_step before ads_factor)   */
+  ADS_ENUMERIC = -5  /* non-finite state detected                           */
+} ads_status;
+
+typedef enum { ADS_PWAVE = 0, ADS_ELASTIC = 1 } ads_problem;
+
+/* Arithmetic of the right-hand-side quadrature.  Sweeps, factors and the
+ * time update are FP64 in every mode. */
+typedef enum {
+  ADS_FP64 = 0,        /* FP64 sum-factorized quadrature                     */
+  ADS_MIXED_FP32 = 1,  /* FP32 contractions, FP64 combination and assembly   */
+  ADS_MIXED_BF16 = 2   /* reserved                                           */
+} ads_precision;
+
+typedef enum { ADS_BC_DIRICHLET0 = 0 } ads_bc;
+
+/* Problem statement (Section 2 for the P-wave, Section 5 for elasticity):
+ * unit cube, nelem[d] uniform elements per direction (x, y, z), spline
+ * degree p with open uniform knots and maximal continuity C^{p-1}, nquad
+ * Gauss points per element and direction (0 means p+1; only p+1 is
+ * supported), time step tau, density rho and Lame constants lambda, mu
+ * (elasticity only; the P-wave has unit wave speed). */
+typedef struct {
+  int32_t problem;     /* ads_problem   */
+  int32_t nelem[3];    /* >= 1 each     */
+  int32_t p;           /* 2 or 3        */
+  int32_t nquad;       /* 0 or p+1      */
+  int32_t bc;          /* ads_bc        */
+  int32_t precision;   /* ads_precision */
+  double tau;          /* > 0           */
+  double rho, lambda, mu;
+} ads_params;
+
+typedef struct ads_sim ads_sim;   /* opaque host handle owned by the library */
+
+/* Workspace bytes needed by ads_create for these parameters (host-only;
+ * ADS_EINVAL for invalid parameters). */
+ads_status ads_workspace_bytes(const ads_params* prm, size_t* bytes);
+
+/* Gauss points of direction d (0=x,1=y,2=z): nelem[d]*q physical abscissae in
+ * element-major order, written to host memory.  These are the points at which
+ * ads_project expects sampled data (host-only). */
+ads_status ads_quad_points(const ads_params* prm, int32_t d, double* host_out);
+
+/* Create a simulation.  dev_workspace: caller-owned device buffer of at least
+ * ads_workspace_bytes (256-byte aligned).  dev_u0 / dev_v0: initial
+ * displacement and velocity coefficients (full layout; NULL = zero).
+ * Uploads basis tables and mass factors; synchronizes the stream before
+ * returning.  *out receives the handle. */
+ads_status ads_create(const ads_params* prm, void* dev_workspace, size_t bytes,
+                      void* hip_stream, const double* dev_u0, const double* dev_v0,
+                      ads_sim** out);
+
+/* Isogeometric L2 projection (Appendix, last paragraph): coefficients u with
+ * M u = b, b_i = int B_i g, for data g sampled at the Gauss points
+ * (dev_vals: [(nelem_z q)][(nelem_y q)][(nelem_x q)] per component, component
+ * count 1 or 3 as the problem).  Writes full-layout coefficients to
+ * dev_coef.  dev_scratch must hold ads_project_scratch_bytes. */
+ads_status ads_project_scratch_bytes(const ads_params* prm, size_t* bytes);
+ads_status ads_project(ads_sim* sim, const double* dev_vals, double* dev_coef,
+                       void* dev_scratch, size_t scratch_bytes);
+
+/* Load F(t_k) = amp[k] * b (Section 2 uses f_{n+1} in the step n -> n+1;
+ * Section 5 uses f^n).  dev_b: load vector (full layout, per component);
+ * host_amp[k], k = 0..namp-1, amplitude at t_k = k tau (0 beyond namp;
+ * namp <= 4096). */
+ads_status ads_set_load(ads_sim* sim, const double* dev_b, const double* host_amp,
+                        int32_t namp);
+/* Point load b_{ijk} = B_i(x_s) B_j(y_s) B_k(z_s) (P-wave; a delta tested
+ * against the basis), amplitude as in ads_set_load. */
+ads_status ads_set_point_load(ads_sim* sim, const double xs[3], const double* host_amp,
+                              int32_t namp);
+
+/* Factor the 1D banded operators for the current tau (banded LU without
+ * pivoting, Appendix: O(n) per direction) and start the time stepping:
+ * P-wave u''_0 = G^{-1}(F_0 - K u_0); elasticity U^{-1} = U^0 - tau V^0 + Z^0/2
+ * with Z^0 = D^{-1} tau^2 (f^0 - Upsilon U^0).  Synchronizes the stream. */
+ads_status ads_factor(ads_sim* sim);
+
+/* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
+ads_status ads_step(ads_sim* sim, int32_t nsteps);
+
+/* Copy the state out (full layout; asynchronous on the sim's stream).
+ * P-wave: u, u', u'' (any pointer may be NULL).  Elasticity: U^n into dev_u,
+ * U^{n-1} into dev_v, dev_a ignored. */
+ads_status ads_get_state(ads_sim* sim, double* dev_u, double* dev_v, double* dev_a);
+/* Replace the state (full layout) and the step index; the sim must be
+ * re-factored (ads_factor) unless dev_a (P-wave) / dev_v = U^{n-1}
+ * (elasticity) is given, in which case stepping can continue directly.
+ * P-wave: u, u', u''; elasticity: U^n, U^{n-1}. */
+ads_status ads_set_state(ads_sim* sim, const double* dev_u, const double* dev_v,
+                         const double* dev_a, int64_t step);
+
+/* Step index (number of steps taken since the start). Synchronizes. */
+ads_status ads_get_step(ads_sim* sim, int64_t* step);
+
+/* Health check: synchronizes and returns ADS_ENUMERIC if the state holds a
+ * non-finite value (NaN/Inf), ADS_OK otherwise.  Uses the workspace's
+ * counter slot; not for use under graph capture. */
+ads_status ads_check_finite(ads_sim* sim);
+
+/* Kernel timing with HIP events recorded on the sim's stream around every
+ * kernel that ads_step enqueues (measurement support; not part of the
+ * method).  ads_profile(sim, 1) enables recording for subsequent ads_step
+ * calls; ads_profile_read synchronizes and returns, for each kernel position
+ * of one time step (in launch order), its mean duration in ms over the
+ * recorded steps (host_ms, up to cap entries) and its kind (host_kind:
+ * 0 = right-hand side, 1 = x-sweep, 2 = y-sweep, 3 = z-sweep, 4 = coupling
+ * apply), plus the per-step durations in ms (host_step_ms, up to step_cap
+ * entries; *nsteps receives the count).  Reading resets the record. */
+ads_status ads_profile(ads_sim* sim, int32_t enable);
+ads_status ads_profile_read(ads_sim* sim, double* host_ms, int32_t* host_kind, int32_t cap,
+                            int32_t* nlaunch, double* host_step_ms, int32_t step_cap,
+                            int32_t* nsteps);
+
+/* Release the host handle (and its timing events).  The caller frees the
+ * workspace after the stream is idle. */
+ads_status ads_destroy(ads_sim* sim);
+
+/* Thread-local message of the last non-OK status (never NULL). */
+const char* ads_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADS_H */

@@ -1,0 +1,870 @@
+// C-ABI implementation: simulation object, workspace planner, per-step
+// launch lists.  See include/ads.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ads.h"
+#include "common.hpp"
+#include "host_math.hpp"
+#include "launch.hpp"
+
+using namespace ads;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+ads_status fail(ads_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHECK(expr)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ADS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int kAmpCap = 4096;
+constexpr size_t kAlign = 256;
+constexpr size_t kJobArena = 96 * 1024;
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// counts bytes (the same walk sizes and carves the workspace).
+struct Carver {
+  char* base;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    used = (used + kAlign - 1) / kAlign * kAlign;
+    void* p = base ? base + used : nullptr;
+    used += bytes;
+    return p;
+  }
+  double* dbl(size_t n) { return (double*)take(n * sizeof(double)); }
+};
+
+// One kernel launch of a step (or of setup), with its device job table.
+struct Launch {
+  enum Kind { RHS_P, RHS_E, SWEEP, KRON } kind;
+  const void* d_jobs;
+  int njobs, total_tiles, max_m, p;
+  int dir = -1;   // sweeps: direction
+};
+
+struct DevFactor {
+  double *L, *U, *rd;
+  int m;
+};
+
+// Host-side mirror of the job arena: jobs are appended here, then uploaded.
+struct JobArena {
+  char* d_base = nullptr;
+  std::vector<char> host;
+  size_t cap = 0;
+  template <class T>
+  T* add(const std::vector<T>& jobs, std::string& err) {
+    size_t off = (host.size() + kAlign - 1) / kAlign * kAlign;
+    size_t bytes = jobs.size() * sizeof(T);
+    if (off + bytes > cap) {
+      err = "job arena full";
+      return nullptr;
+    }
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, jobs.data(), bytes);
+    return (T*)(d_base + off);
+  }
+};
+
+}  // namespace
+
+struct ads_sim {
+  ads_params prm;
+  hipStream_t stream = nullptr;
+  int E[3], n[3], nf[3], off[3];
+  int p, q, P, ncomp;
+  long long nfree;
+  bool elastic;
+  Tables1D tab[3];
+  Band Mf[3], Kf[3], Gf[3];   // free-block bands
+  // device
+  double* d_tab[3];
+  double* d_bandM[3];
+  double* d_bandG[3];
+  double* d_bandGT[3];
+  DevFactor fS[3], fS2[3], fM[3];  // P-wave: fS = M + eta K; elastic: fS = mu, fS2 = 2mu+lam
+  double *u, *v, *a, *R, *X, *T, *Y, *Z, *load, *amp;
+  unsigned long long* counter;
+  unsigned long long* flag;
+  JobArena arena;
+  std::vector<Launch> step_l, start_l, projM_l;
+  bool factored = false, need_start = true, have_load = false;
+  int namp = 0;
+  int tz = 0;
+  // kernel timing (measurement support)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;     // (launches + 1) events per recorded step
+  int prof_steps = 0;
+  ~ads_sim() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+bool valid_params(const ads_params* prm, std::string& why) {
+  if (!prm) {
+    why = "params is NULL";
+    return false;
+  }
+  if (prm->problem != ADS_PWAVE && prm->problem != ADS_ELASTIC) {
+    why = "problem must be ADS_PWAVE or ADS_ELASTIC";
+    return false;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (prm->nelem[d] < 1 || prm->nelem[d] > 4096) {
+      why = "nelem must be in [1, 4096]";
+      return false;
+    }
+  if (prm->p != 2 && prm->p != 3) {
+    why = "spline degree p must be 2 or 3";
+    return false;
+  }
+  if (prm->nquad != 0 && prm->nquad != prm->p + 1) {
+    why = "nquad must be 0 or p+1";
+    return false;
+  }
+  if (prm->bc != ADS_BC_DIRICHLET0) {
+    why = "only zero Dirichlet conditions are supported";
+    return false;
+  }
+  if (!(prm->tau > 0.0) || !std::isfinite(prm->tau)) {
+    why = "tau must be positive and finite";
+    return false;
+  }
+  if (prm->precision != ADS_FP64 && prm->precision != ADS_MIXED_FP32) {
+    why = "precision must be ADS_FP64 or ADS_MIXED_FP32";
+    return false;
+  }
+  if (prm->precision == ADS_MIXED_FP32 && prm->problem != ADS_PWAVE) {
+    why = "mixed precision is implemented for the P-wave only";
+    return false;
+  }
+  if (prm->problem == ADS_ELASTIC) {
+    if (!(prm->rho > 0.0) || !(prm->mu > 0.0) || !(prm->lambda + 2.0 * prm->mu / 3.0 > 0.0)) {
+      why = "elasticity needs rho > 0, mu > 0, lambda + 2 mu / 3 > 0";
+      return false;
+    }
+  }
+  for (int d = 0; d < 3; ++d)
+    if (prm->nelem[d] + prm->p - 2 > 512) {
+      why = "at most 512 free coefficients per direction";
+      return false;
+    }
+  return true;
+}
+
+void geometry(ads_sim* s) {
+  const ads_params& P = s->prm;
+  s->p = P.p;
+  s->q = P.p + 1;
+  s->P = P.p + 1;
+  s->elastic = P.problem == ADS_ELASTIC;
+  s->ncomp = s->elastic ? 3 : 1;
+  for (int d = 0; d < 3; ++d) {
+    s->E[d] = P.nelem[d];
+    s->n[d] = P.nelem[d] + P.p;
+    s->nf[d] = s->n[d] - 2;
+    s->off[d] = 1;
+  }
+  s->nfree = (long long)s->nf[0] * s->nf[1] * s->nf[2];
+}
+
+// Walks every device allocation of a simulation (sizing and carving).
+void carve(ads_sim* s, Carver& c) {
+  const long long nfr = s->nfree;
+  const int P = s->P, q = s->q, p = s->p;
+  for (int d = 0; d < 3; ++d) s->d_tab[d] = c.dbl((size_t)2 * s->E[d] * q * P + (size_t)s->E[d] * q);
+  auto fac = [&](DevFactor& f, int d) {
+    f.m = s->nf[d];
+    f.L = c.dbl((size_t)f.m * p);
+    f.U = c.dbl((size_t)f.m * p);
+    f.rd = c.dbl(f.m);
+  };
+  for (int d = 0; d < 3; ++d) {
+    fac(s->fS[d], d);
+    fac(s->fM[d], d);
+    if (s->elastic) fac(s->fS2[d], d);
+    else s->fS2[d] = DevFactor{nullptr, nullptr, nullptr, 0};
+  }
+  const int nc = s->ncomp;
+  s->u = c.dbl(nfr * nc);
+  s->v = c.dbl(nfr * nc);
+  s->R = c.dbl(nfr * nc);
+  s->X = c.dbl(nfr);
+  s->load = c.dbl(nfr * nc);
+  s->amp = c.dbl(kAmpCap);
+  if (s->elastic) {
+    s->a = nullptr;
+    s->T = c.dbl(nfr);
+    s->Y = c.dbl(nfr * 3);
+    s->Z = c.dbl(nfr * 3);
+    for (int d = 0; d < 3; ++d) {
+      size_t bw = (size_t)s->nf[d] * (2 * p + 1);
+      s->d_bandM[d] = c.dbl(bw);
+      s->d_bandG[d] = c.dbl(bw);
+      s->d_bandGT[d] = c.dbl(bw);
+    }
+  } else {
+    s->a = c.dbl(nfr);
+    s->T = s->Y = s->Z = nullptr;
+  }
+  s->counter = (unsigned long long*)c.take(64);
+  s->flag = (unsigned long long*)c.take(64);
+  s->arena.d_base = (char*)c.take(kJobArena);
+  s->arena.cap = kJobArena;
+}
+
+// --- job builders ------------------------------------------------------------
+
+SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* in, double* out, double scale) {
+  SweepJob J{};
+  J.in = in;
+  J.out = out;
+  J.f = Factor1D{f.L, f.U, f.rd, f.m};
+  J.dir = dir;
+  J.p = s->p;
+  J.nx = s->nf[0];
+  J.ny = s->nf[1];
+  J.nz = s->nf[2];
+  J.nlines = (int)(s->nfree / s->nf[dir]);
+  const int W = sweep_width_for(std::max(s->nf[0], std::max(s->nf[1], s->nf[2])));
+  J.ntiles = (J.nlines + W - 1) / W;
+  J.tile0 = 0;
+  J.epi = EPI_STORE;
+  J.scale = scale;
+  return J;
+}
+
+int max_m(const ads_sim* s) { return std::max(s->nf[0], std::max(s->nf[1], s->nf[2])); }
+
+// Three sweeps x (in -> X), y (X -> tmp), z (tmp -> out/epilogue) with one
+// factor per direction.
+bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], const double* in, double* tmp,
+                   double* out, double scale, SweepJob zlast, std::string& err) {
+  SweepJob jx = sweep_job(s, 0, f[0], in, s->X, scale);
+  SweepJob jy = sweep_job(s, 1, f[1], s->X, tmp, 1.0);
+  SweepJob jz = zlast;
+  const SweepJob base = sweep_job(s, 2, f[2], tmp, out, 1.0);
+  jz.in = base.in;
+  jz.out = out;
+  jz.f = base.f;
+  jz.dir = 2;
+  jz.p = base.p;
+  jz.nx = base.nx;
+  jz.ny = base.ny;
+  jz.nz = base.nz;
+  jz.nlines = base.nlines;
+  jz.ntiles = base.ntiles;
+  jz.tile0 = 0;
+  jz.scale = 1.0;
+  for (SweepJob* j : {&jx, &jy, &jz}) {
+    SweepJob* d = s->arena.add(std::vector<SweepJob>{*j}, err);
+    if (!d) return false;
+    L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir});
+  }
+  return true;
+}
+
+SweepJob plain_epi() {
+  SweepJob z{};
+  z.epi = EPI_STORE;
+  return z;
+}
+
+void fill_tables(const ads_sim* s, RhsJob& J) {
+  for (int d = 0; d < 3; ++d) {
+    J.tab[d] = s->d_tab[d];
+    J.E[d] = s->E[d];
+    J.nf[d] = s->nf[d];
+    J.off[d] = s->off[d];
+  }
+}
+
+// z-chunking of the RHS: enough workgroups to cover the chip at least twice.
+void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY) {
+  J.tiles[0] = (s->nf[0] + TX - 1) / TX;
+  J.tiles[1] = (s->nf[1] + TY - 1) / TY;
+  int xy = J.tiles[0] * J.tiles[1];
+  int want = std::max(1, (1024 + xy - 1) / xy);
+  int minTZ = 8;
+  int chunks = std::min(want, std::max(1, s->nf[2] / minTZ));
+  int TZ = (s->nf[2] + chunks - 1) / chunks;
+  if (s->tz > 0) TZ = s->tz;
+  J.TZ = TZ;
+  J.tiles[2] = (s->nf[2] + TZ - 1) / TZ;
+  J.tile0 = 0;
+  J.ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
+}
+
+RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift) {
+  RhsJob J{};
+  J.u = s->u;
+  J.v = cv != 0.0 ? s->v : nullptr;
+  J.a = ca != 0.0 ? s->a : nullptr;
+  J.cu = cu;
+  J.cv = cv;
+  J.ca = ca;
+  J.R = s->R;
+  J.load = s->have_load ? s->load : nullptr;
+  J.amp = s->amp;
+  J.namp = s->namp;
+  J.amp_shift = amp_shift;
+  J.counter = s->counter;
+  J.rscale = 1.0;
+  fill_tables(s, J);
+  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p));
+  return J;
+}
+
+RhsJob rhs_elastic_job(const ads_sim* s) {
+  RhsJob J{};
+  J.u = s->u;
+  J.cu = 1.0;
+  J.R = s->R;
+  J.load = s->have_load ? s->load : nullptr;
+  J.amp = s->amp;
+  J.namp = s->namp;
+  J.amp_shift = 0;
+  J.counter = s->counter;
+  const double tau = s->prm.tau;
+  J.rscale = tau * tau;
+  J.lam = s->prm.lambda;
+  J.mu = s->prm.mu;
+  fill_tables(s, J);
+  rhs_tiles(s, J, rhs_el_tile_x(s->p), rhs_el_tile_y(s->p));
+  return J;
+}
+
+KronJob kron_base(const ads_sim* s, double* out, const double* base, double alpha) {
+  KronJob K{};
+  K.out = out;
+  K.base = base;
+  K.alpha = alpha;
+  K.p = s->p;
+  K.nx = s->nf[0];
+  K.ny = s->nf[1];
+  K.nz = s->nf[2];
+  K.nterm = 0;
+  K.tile0 = 0;
+  K.ntiles = (int)((s->nfree + kron_tile_points() - 1) / kron_tile_points());
+  return K;
+}
+
+// Upsilon_ik (i != k) as two tensor-product terms acting on src.
+void kron_add_upsilon(const ads_sim* s, KronJob& K, int i, int k, const double* src, double coef) {
+  const int j = 3 - i - k;
+  KronTerm tm{}, tl{};
+  tm.src = tl.src = src;
+  tm.T[i] = s->d_bandG[i];
+  tm.T[k] = s->d_bandGT[k];
+  tm.T[j] = s->d_bandM[j];
+  tm.coef = coef * s->prm.mu;
+  tl.T[i] = s->d_bandGT[i];
+  tl.T[k] = s->d_bandG[k];
+  tl.T[j] = s->d_bandM[j];
+  tl.coef = coef * s->prm.lambda;
+  K.term[K.nterm++] = tm;
+  K.term[K.nterm++] = tl;
+}
+
+void kron_add_mass(const ads_sim* s, KronJob& K, const double* src, double coef) {
+  KronTerm t{};
+  t.src = src;
+  for (int d = 0; d < 3; ++d) t.T[d] = s->d_bandM[d];
+  t.coef = coef;
+  K.term[K.nterm++] = t;
+}
+
+bool push_kron(ads_sim* s, std::vector<Launch>& L, const KronJob& K, std::string& err) {
+  KronJob* d = s->arena.add(std::vector<KronJob>{K}, err);
+  if (!d) return false;
+  L.push_back(Launch{Launch::KRON, d, 1, K.ntiles, 0, s->p});
+  return true;
+}
+
+// Alternating-triangular solve Z = D^{-1} R (three-level form of eq. pre /
+// eq. corr with the split diagonal blocks of eq. spill); with `update` the
+// last sweep of every component also performs U^{n+1} = 2U^n - U^{n-1} + Z.
+bool add_at_solve(ads_sim* s, std::vector<Launch>& L, bool update, bool count, std::string& err) {
+  const long long nf = s->nfree;
+  const double tau = s->prm.tau, rho = s->prm.rho, h = 0.5 * tau * tau;
+  auto facs = [&](int i, DevFactor out[3]) {
+    for (int d = 0; d < 3; ++d) out[d] = (d == i) ? s->fS2[d] : s->fS[d];
+  };
+  // stage 1 (block lower): components x, y, z
+  for (int i = 0; i < 3; ++i) {
+    const double* rhs = s->R + i * nf;
+    if (i > 0) {
+      KronJob K = kron_base(s, s->T, s->R + i * nf, 1.0);
+      for (int jj = 0; jj < i; ++jj) kron_add_upsilon(s, K, i, jj, s->Y + jj * nf, -h);
+      if (!push_kron(s, L, K, err)) return false;
+      rhs = s->T;
+    }
+    DevFactor f[3];
+    facs(i, f);
+    if (!add_ads_solve(s, L, f, rhs, s->Z + i * nf /*tmp*/, s->Y + i * nf, 1.0 / rho, plain_epi(), err))
+      return false;
+  }
+  // stage 2 (block upper): components z, y, x
+  for (int i = 2; i >= 0; --i) {
+    KronJob K = kron_base(s, s->T, nullptr, 0.0);
+    kron_add_mass(s, K, s->Y + i * nf, rho);
+    for (int jj = i + 1; jj < 3; ++jj) kron_add_upsilon(s, K, i, jj, s->Z + jj * nf, -h);
+    if (!push_kron(s, L, K, err)) return false;
+    DevFactor f[3];
+    facs(i, f);
+    SweepJob z{};
+    if (update) {
+      z.epi = EPI_THREELEVEL;
+      z.e0 = s->u + i * nf;
+      z.e1 = s->v + i * nf;
+    } else {
+      z.epi = EPI_STORE;
+    }
+    if (count && i == 0) z.counter = s->counter;
+    // tmp for the y-sweep: R_i is no longer needed in stage 2
+    if (!add_ads_solve(s, L, f, s->T, s->R + i * nf, s->Z + i * nf, 1.0 / rho, z, err)) return false;
+  }
+  return true;
+}
+
+ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, hipEvent_t* evs = nullptr) {
+  if (evs) HIPCHECK(hipEventRecord(evs[0], s->stream));
+  for (size_t li = 0; li < L.size(); ++li) {
+    const Launch& l = L[li];
+    hipError_t e = hipSuccess;
+    switch (l.kind) {
+      case Launch::RHS_P:
+        e = launch_rhs_pwave(l.p, (const RhsJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        break;
+      case Launch::RHS_E:
+        e = launch_rhs_elastic(l.p, (const RhsJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        break;
+      case Launch::SWEEP:
+        e = launch_sweeps((const SweepJob*)l.d_jobs, l.njobs, l.total_tiles, l.max_m, grid_cap, s->stream);
+        break;
+      case Launch::KRON:
+        e = launch_kron((const KronJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        break;
+    }
+    if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (evs) HIPCHECK(hipEventRecord(evs[li + 1], s->stream));
+  }
+  return ADS_OK;
+}
+
+// 0 = right-hand side, 1..3 = x/y/z sweep, 4 = coupling apply
+int launch_kind_code(const Launch& l) {
+  if (l.kind == Launch::RHS_P || l.kind == Launch::RHS_E) return 0;
+  if (l.kind == Launch::KRON) return 4;
+  return 1 + l.dir;
+}
+
+ads_status upload(ads_sim* s, void* dst, const void* src, size_t bytes) {
+  HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream));
+  return ADS_OK;
+}
+
+ads_status upload_factor(ads_sim* s, const DevFactor& f, const Band& A) {
+  BandLU lu;
+  if (!band_lu(A, lu)) return fail(ADS_ENUMERIC, "banded LU met a non-positive pivot");
+  ads_status st;
+  if ((st = upload(s, f.L, lu.L.data(), lu.L.size() * 8)) != ADS_OK) return st;
+  if ((st = upload(s, f.U, lu.U.data(), lu.U.size() * 8)) != ADS_OK) return st;
+  return upload(s, f.rd, lu.rd.data(), lu.rd.size() * 8);
+}
+
+// (Re)build every job table and launch list; uploads the arena.
+ads_status build_launches(ads_sim* s) {
+  std::string err;
+  s->arena.host.clear();
+  s->step_l.clear();
+  s->start_l.clear();
+  s->projM_l.clear();
+  const double tau = s->prm.tau, eta = 0.25 * tau * tau;
+  if (!s->elastic) {
+    // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
+    RhsJob rj = rhs_pwave_job(s, 1.0, tau, eta, 1);
+    RhsJob* d = s->arena.add(std::vector<RhsJob>{rj}, err);
+    if (!d) return fail(ADS_ENOMEM, err);
+    s->step_l.push_back(Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p});
+    SweepJob z{};
+    z.epi = EPI_NEWMARK;
+    z.c0 = tau;
+    z.c1 = eta;
+    z.e0 = s->u;
+    z.e1 = s->v;
+    z.e2 = s->a;
+    z.counter = s->counter;
+    if (!add_ads_solve(s, s->step_l, s->fS, s->R, s->R, nullptr, 1.0, z, err)) return fail(ADS_ENOMEM, err);
+    // start: u''_0 = G^{-1}(F_0 - K u_0)
+    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0);
+    d = s->arena.add(std::vector<RhsJob>{r0}, err);
+    if (!d) return fail(ADS_ENOMEM, err);
+    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p});
+    if (!add_ads_solve(s, s->start_l, s->fS, s->R, s->R, s->a, 1.0, plain_epi(), err))
+      return fail(ADS_ENOMEM, err);
+  } else {
+    RhsJob rj = rhs_elastic_job(s);
+    RhsJob* d = s->arena.add(std::vector<RhsJob>{rj}, err);
+    if (!d) return fail(ADS_ENOMEM, err);
+    s->step_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p});
+    if (!add_at_solve(s, s->step_l, true, true, err)) return fail(ADS_ENOMEM, err);
+    s->start_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p});
+    if (!add_at_solve(s, s->start_l, false, false, err)) return fail(ADS_ENOMEM, err);
+  }
+  // mass solve used by the projection: R -> R (per component, offset applied at launch)
+  if (!add_ads_solve(s, s->projM_l, s->fM, s->R, s->R, s->R, 1.0, plain_epi(), err))
+    return fail(ADS_ENOMEM, err);
+  return upload(s, s->arena.d_base, s->arena.host.data(), s->arena.host.size());
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* ads_last_error(void) { return g_err.c_str(); }
+
+ads_status ads_workspace_bytes(const ads_params* prm, size_t* bytes) {
+  std::string why;
+  if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
+  if (!bytes) return fail(ADS_EINVAL, "bytes is NULL");
+  ads_sim s;
+  s.prm = *prm;
+  geometry(&s);
+  Carver c{nullptr};
+  carve(&s, c);
+  *bytes = c.used;
+  return ADS_OK;
+}
+
+ads_status ads_quad_points(const ads_params* prm, int32_t d, double* host_out) {
+  std::string why;
+  if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
+  if (d < 0 || d > 2 || !host_out) return fail(ADS_EINVAL, "bad direction or NULL output");
+  Tables1D t = make_tables(prm->nelem[d], prm->p, prm->p + 1);
+  std::memcpy(host_out, t.X.data(), t.X.size() * sizeof(double));
+  return ADS_OK;
+}
+
+ads_status ads_project_scratch_bytes(const ads_params* prm, size_t* bytes) {
+  std::string why;
+  if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
+  if (!bytes) return fail(ADS_EINVAL, "bytes is NULL");
+  const long long q = prm->p + 1;
+  const long long gz = prm->nelem[2] * q, gy = prm->nelem[1] * q;
+  const long long fx = prm->nelem[0] + prm->p - 2, fy = prm->nelem[1] + prm->p - 2;
+  *bytes = (size_t)(gz * gy * fx + gz * fy * fx) * sizeof(double) + 2 * kAlign;
+  return ADS_OK;
+}
+
+ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* stream, const double* u0,
+                      const double* v0, ads_sim** out) {
+  std::string why;
+  if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
+  if (!out) return fail(ADS_EINVAL, "out is NULL");
+  if (!ws) return fail(ADS_EINVAL, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  ads_workspace_bytes(prm, &need);
+  if (bytes < need) return fail(ADS_ENOMEM, "workspace smaller than ads_workspace_bytes");
+  static bool attrs = false;
+  if (!attrs) {
+    HIPCHECK(sweep_set_attributes());
+    attrs = true;
+  }
+  ads_sim* s = new ads_sim();
+  s->prm = *prm;
+  s->stream = (hipStream_t)stream;
+  geometry(s);
+  if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
+  Carver c{(char*)ws};
+  carve(s, c);
+  // host tables and matrices
+  for (int d = 0; d < 3; ++d) {
+    s->tab[d] = make_tables(s->E[d], s->p, s->q);
+    Band M = assemble(s->tab[d], MAT_MASS), K = assemble(s->tab[d], MAT_STIFF), G = assemble(s->tab[d], MAT_MIXED);
+    s->Mf[d] = restrict_band(M, s->off[d], s->nf[d]);
+    s->Kf[d] = restrict_band(K, s->off[d], s->nf[d]);
+    s->Gf[d] = restrict_band(G, s->off[d], s->nf[d]);
+  }
+  auto cleanup = [&](ads_status st) {
+    delete s;
+    return st;
+  };
+  ads_status st;
+  for (int d = 0; d < 3; ++d) {
+    const Tables1D& t = s->tab[d];
+    std::vector<double> buf;
+    buf.insert(buf.end(), t.N.begin(), t.N.end());
+    buf.insert(buf.end(), t.D.begin(), t.D.end());
+    buf.insert(buf.end(), t.W.begin(), t.W.end());
+    if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return cleanup(st);
+    if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return cleanup(st);
+    if (s->elastic) {
+      Band GT = s->Gf[d];
+      for (int i = 0; i < GT.n; ++i)
+        for (int j = std::max(0, i - GT.p); j <= std::min(GT.n - 1, i + GT.p); ++j) GT.at(i, j) = s->Gf[d].at(j, i);
+      if ((st = upload(s, s->d_bandM[d], s->Mf[d].a.data(), s->Mf[d].a.size() * 8)) != ADS_OK) return cleanup(st);
+      if ((st = upload(s, s->d_bandG[d], s->Gf[d].a.data(), s->Gf[d].a.size() * 8)) != ADS_OK) return cleanup(st);
+      if ((st = upload(s, s->d_bandGT[d], GT.a.data(), GT.a.size() * 8)) != ADS_OK) return cleanup(st);
+    }
+  }
+  const int nc = s->ncomp;
+  const long long nfr = s->nfree;
+  // state: u (U^n), v (u' for the P-wave; V^0 then U^{n-1} for elasticity), a
+  if (launch_full_to_free(u0, s->u, s->n, s->nf, s->off, nc, s->stream) != hipSuccess ||
+      launch_full_to_free(v0, s->v, s->n, s->nf, s->off, nc, s->stream) != hipSuccess)
+    return cleanup(fail(ADS_EDEVICE, "layout copy failed"));
+  if (s->a) HIPCHECK(launch_fill(s->a, nfr, 0.0, s->stream));
+  HIPCHECK(launch_fill(s->load, nfr * nc, 0.0, s->stream));
+  HIPCHECK(launch_fill(s->amp, kAmpCap, 0.0, s->stream));
+  HIPCHECK(launch_set_u64(s->counter, 0ull, s->stream));
+  if ((st = build_launches(s)) != ADS_OK) return cleanup(st);
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  s->need_start = true;
+  *out = s;
+  return ADS_OK;
+}
+
+ads_status ads_project(ads_sim* s, const double* vals, double* coef, void* scratch, size_t scratch_bytes) {
+  if (!s || !vals || !coef || !scratch) return fail(ADS_EINVAL, "NULL argument");
+  size_t need = 0;
+  ads_project_scratch_bytes(&s->prm, &need);
+  if (scratch_bytes < need) return fail(ADS_ENOMEM, "projection scratch too small");
+  const int q = s->q, P = s->P;
+  const long long gz = (long long)s->E[2] * q, gy = (long long)s->E[1] * q, gx = (long long)s->E[0] * q;
+  double* s1 = (double*)scratch;
+  double* s2 = s1 + ((gz * gy * s->nf[0] + 31) / 32) * 32;
+  // components last to first: component c > 0 is solved through R_0's slot
+  for (int c = s->ncomp - 1; c >= 0; --c) {
+    const double* g = vals + c * gz * gy * gx;
+    double* b = s->R + c * s->nfree;
+    HIPCHECK(launch_proj_contract(g, s1, gz * gy, s->E[0], q, P, s->nf[0], s->off[0], 1, s->d_tab[0], s->stream));
+    HIPCHECK(launch_proj_contract(s1, s2, gz, s->E[1], q, P, s->nf[1], s->off[1], s->nf[0], s->d_tab[1],
+                                  s->stream));
+    HIPCHECK(launch_proj_contract(s2, b, 1, s->E[2], q, P, s->nf[2], s->off[2],
+                                  (long long)s->nf[0] * s->nf[1], s->d_tab[2], s->stream));
+    // M u = b by three sweeps with the mass factors, in place on R_0
+    if (c > 0) HIPCHECK(hipMemcpyAsync(s->R, b, s->nfree * 8, hipMemcpyDeviceToDevice, s->stream));
+    ads_status st = enqueue(s, s->projM_l);
+    if (st != ADS_OK) return st;
+    if (c > 0) HIPCHECK(hipMemcpyAsync(b, s->R, s->nfree * 8, hipMemcpyDeviceToDevice, s->stream));
+  }
+  HIPCHECK(launch_free_to_full(s->R, coef, s->n, s->nf, s->off, s->ncomp, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_set_load(ads_sim* s, const double* b, const double* amp, int32_t namp) {
+  if (!s || !b || (namp > 0 && !amp)) return fail(ADS_EINVAL, "NULL argument");
+  if (namp < 0 || namp > kAmpCap) return fail(ADS_ENOMEM, "at most 4096 load amplitudes");
+  HIPCHECK(launch_full_to_free(b, s->load, s->n, s->nf, s->off, s->ncomp, s->stream));
+  HIPCHECK(launch_fill(s->amp, kAmpCap, 0.0, s->stream));
+  if (namp > 0) HIPCHECK(hipMemcpyAsync(s->amp, amp, namp * 8, hipMemcpyHostToDevice, s->stream));
+  s->namp = namp;
+  s->have_load = true;
+  ads_status st = build_launches(s);
+  if (st != ADS_OK) return st;
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_set_point_load(ads_sim* s, const double xs[3], const double* amp, int32_t namp) {
+  if (!s || !xs || (namp > 0 && !amp)) return fail(ADS_EINVAL, "NULL argument");
+  if (s->elastic) return fail(ADS_EINVAL, "point loads are defined for the P-wave");
+  if (namp < 0 || namp > kAmpCap) return fail(ADS_ENOMEM, "at most 4096 load amplitudes");
+  std::vector<double> v[3];
+  for (int d = 0; d < 3; ++d) {
+    double x = std::min(1.0, std::max(0.0, xs[d]));
+    std::vector<double> t = open_knots(s->E[d], s->p);
+    int e = std::min(s->E[d] - 1, (int)std::floor(x * s->E[d]));
+    double N[8], D[8];
+    basis_on_span(t, s->p, e + s->p, x, N, D);
+    v[d].assign(s->nf[d], 0.0);
+    for (int a = 0; a <= s->p; ++a) {
+      int fi = e + a - s->off[d];
+      if (fi >= 0 && fi < s->nf[d]) v[d][fi] = N[a];
+    }
+  }
+  std::vector<double> b((size_t)s->nfree);
+  for (int z = 0; z < s->nf[2]; ++z)
+    for (int y = 0; y < s->nf[1]; ++y)
+      for (int x = 0; x < s->nf[0]; ++x)
+        b[((size_t)z * s->nf[1] + y) * s->nf[0] + x] = v[2][z] * v[1][y] * v[0][x];
+  ads_status st = upload(s, s->load, b.data(), b.size() * 8);
+  if (st != ADS_OK) return st;
+  HIPCHECK(launch_fill(s->amp, kAmpCap, 0.0, s->stream));
+  if (namp > 0) HIPCHECK(hipMemcpyAsync(s->amp, amp, namp * 8, hipMemcpyHostToDevice, s->stream));
+  s->namp = namp;
+  s->have_load = true;
+  if ((st = build_launches(s)) != ADS_OK) return st;
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_factor(ads_sim* s) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  const double tau = s->prm.tau;
+  ads_status st;
+  for (int d = 0; d < 3; ++d) {
+    if (!s->elastic) {
+      Band A = axpby(1.0, s->Mf[d], 0.25 * tau * tau, s->Kf[d]);
+      if ((st = upload_factor(s, s->fS[d], A)) != ADS_OK) return st;
+    } else {
+      const double rho = s->prm.rho, mu = s->prm.mu, lam = s->prm.lambda;
+      Band A1 = axpby(1.0, s->Mf[d], tau * tau * mu / (4.0 * rho), s->Kf[d]);
+      Band A2 = axpby(1.0, s->Mf[d], tau * tau * (2.0 * mu + lam) / (4.0 * rho), s->Kf[d]);
+      if ((st = upload_factor(s, s->fS[d], A1)) != ADS_OK) return st;
+      if ((st = upload_factor(s, s->fS2[d], A2)) != ADS_OK) return st;
+    }
+  }
+  if (s->need_start) {
+    if ((st = enqueue(s, s->start_l)) != ADS_OK) return st;
+    if (s->elastic) {
+      // U^{-1} = U^0 - tau V^0 + Z^0 / 2  (v holds V^0 until the start)
+      const long long n3 = 3 * s->nfree;
+      HIPCHECK(launch_axpby(s->v, s->u, s->v, 1.0, -tau, n3, s->stream));
+      HIPCHECK(launch_axpby(s->v, s->v, s->Z, 1.0, 0.5, n3, s->stream));
+    }
+    s->need_start = false;
+  }
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  s->factored = true;
+  return ADS_OK;
+}
+
+ads_status ads_step(ads_sim* s, int32_t nsteps) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (nsteps < 0) return fail(ADS_EINVAL, "nsteps < 0");
+  if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_step before ads_factor");
+  const size_t per = s->step_l.size() + 1;
+  for (int k = 0; k < nsteps; ++k) {
+    hipEvent_t* evs = nullptr;
+    if (s->prof) {
+      size_t need = (size_t)(s->prof_steps + 1) * per;
+      while (s->ev.size() < need) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreate(&e));
+        s->ev.push_back(e);
+      }
+      evs = &s->ev[(size_t)s->prof_steps * per];
+      s->prof_steps++;
+    }
+    ads_status st = enqueue(s, s->step_l, 0, evs);
+    if (st != ADS_OK) return st;
+  }
+  return ADS_OK;
+}
+
+ads_status ads_profile(ads_sim* s, int32_t enable) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  s->prof = enable != 0;
+  s->prof_steps = 0;
+  return ADS_OK;
+}
+
+ads_status ads_profile_read(ads_sim* s, double* ms, int32_t* kind, int32_t cap, int32_t* nlaunch, double* step_ms,
+                            int32_t step_cap, int32_t* nsteps) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  const size_t L = s->step_l.size(), per = L + 1;
+  std::vector<double> sum(L, 0.0);
+  for (int k = 0; k < s->prof_steps; ++k) {
+    hipEvent_t* e = &s->ev[(size_t)k * per];
+    for (size_t i = 0; i < L; ++i) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, e[i], e[i + 1]));
+      sum[i] += t;
+    }
+    if (step_ms && k < step_cap) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, e[0], e[L]));
+      step_ms[k] = t;
+    }
+  }
+  for (size_t i = 0; i < L && (int)i < cap; ++i) {
+    if (ms) ms[i] = s->prof_steps ? sum[i] / s->prof_steps : 0.0;
+    if (kind) kind[i] = launch_kind_code(s->step_l[i]);
+  }
+  if (nlaunch) *nlaunch = (int32_t)L;
+  if (nsteps) *nsteps = s->prof_steps;
+  s->prof_steps = 0;
+  return ADS_OK;
+}
+
+ads_status ads_check_finite(ads_sim* s) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  const long long n = s->nfree * s->ncomp;
+  HIPCHECK(launch_set_u64(s->flag, 0ull, s->stream));
+  HIPCHECK(launch_nonfinite(s->u, n, s->flag, s->stream));
+  HIPCHECK(launch_nonfinite(s->v, n, s->flag, s->stream));
+  if (s->a) HIPCHECK(launch_nonfinite(s->a, n, s->flag, s->stream));
+  unsigned long long cnt = 0;
+  HIPCHECK(hipMemcpyAsync(&cnt, s->flag, 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  if (cnt) return fail(ADS_ENUMERIC, std::to_string(cnt) + " non-finite state entries");
+  return ADS_OK;
+}
+
+ads_status ads_get_state(ads_sim* s, double* u, double* v, double* a) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  const int nc = s->ncomp;
+  if (u) HIPCHECK(launch_free_to_full(s->u, u, s->n, s->nf, s->off, nc, s->stream));
+  if (v) HIPCHECK(launch_free_to_full(s->v, v, s->n, s->nf, s->off, nc, s->stream));
+  if (a && s->a) HIPCHECK(launch_free_to_full(s->a, a, s->n, s->nf, s->off, 1, s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_set_state(ads_sim* s, const double* u, const double* v, const double* a, int64_t step) {
+  if (!s || !u) return fail(ADS_EINVAL, "NULL argument");
+  if (step < 0) return fail(ADS_EINVAL, "step < 0");
+  const int nc = s->ncomp;
+  HIPCHECK(launch_full_to_free(u, s->u, s->n, s->nf, s->off, nc, s->stream));
+  HIPCHECK(launch_full_to_free(v, s->v, s->n, s->nf, s->off, nc, s->stream));
+  if (!s->elastic) {
+    if (a) HIPCHECK(launch_full_to_free(a, s->a, s->n, s->nf, s->off, 1, s->stream));
+    s->need_start = (a == nullptr);
+  } else {
+    s->need_start = (v == nullptr);
+  }
+  HIPCHECK(launch_set_u64(s->counter, (unsigned long long)step, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_get_step(ads_sim* s, int64_t* step) {
+  if (!s || !step) return fail(ADS_EINVAL, "NULL argument");
+  unsigned long long v = 0;
+  HIPCHECK(hipMemcpyAsync(&v, s->counter, 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  *step = (int64_t)v;
+  return ADS_OK;
+}
+
+ads_status ads_destroy(ads_sim* s) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  delete s;
+  return ADS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal types shared by the host side and the gfx950 kernels.
+//
+// Field layout on the device: FREE coefficients only (zero-Dirichlet
+// eliminated), nf_x * nf_y * nf_z doubles per component, [z][y][x] with x
+// fastest.  Full-index coefficient c of direction d has free index
+// c - off[d] (off = 1 for zero Dirichlet).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ads {
+
+constexpr int kMaxP = 3;          // spline degrees 2 and 3 are instantiated
+constexpr int kMaxJobs = 256;     // jobs per launch (one per simulation/component)
+
+// One 1D banded factor (banded LU without pivoting of a free-row block):
+// L[i*p + k-1] = l_{i,i-k}, U[i*p + k-1] = u_{i,i+k} (zero where the index
+// leaves the matrix), rd[i] = 1 / u_{ii}.
+struct Factor1D {
+  const double* L;
+  const double* U;
+  const double* rd;
+  int m;
+};
+
+// Epilogue applied by a sweep to every solved value x at global offset g.
+enum SweepEpi : int {
+  EPI_STORE = 0,     // out[g] = x
+  EPI_NEWMARK = 1,   // a' = x; v += tau/2 (a + a'); u += tau v + eta (a + a'); a = a'
+  EPI_THREELEVEL = 2 // out[g] = x; U^{n-1} <- U^n; U^n <- 2 U^n - U^{n-1} + x
+};
+
+// One set of line solves of a field along one direction.
+struct SweepJob {
+  const double* in;
+  double* out;
+  Factor1D f;
+  int dir;          // 0: x-lines (contiguous), 1: y-lines, 2: z-lines
+  int p;
+  int nx, ny, nz;   // free sizes of the field
+  int nlines;
+  int tile0;        // first global tile index of this job
+  int ntiles;
+  int epi;
+  double scale;     // the input is multiplied by this before the solve
+  double c0, c1;    // EPI_NEWMARK: tau, eta
+  double* e0;       // EPI_NEWMARK: u   EPI_THREELEVEL: U^n
+  double* e1;       // EPI_NEWMARK: v   EPI_THREELEVEL: U^{n-1}
+  double* e2;       // EPI_NEWMARK: a
+  unsigned long long* counter;  // incremented once by the job (end of a step)
+};
+
+// Right-hand side by sum-factorized Gauss quadrature on one field
+// (P-wave) or three fields (elasticity).
+struct RhsJob {
+  // state: P-wave w = cu*u + cv*v + ca*a (free layout); elasticity uses u
+  // as U^n (3 components, comp stride nfree) and ignores v, a.
+  const double* u;
+  const double* v;
+  const double* a;
+  double cu, cv, ca;
+  double* R;              // output (free layout, comps as input)
+  const double* load;     // load vector (free layout) or null
+  const double* amp;      // amplitude table or null
+  int namp;
+  int amp_shift;          // amplitude index = *counter + amp_shift
+  const unsigned long long* counter;
+  double rscale;          // R = rscale * (amp * load - A(w))
+  double lam, mu;         // elasticity Lame constants
+  const double* tab[3];   // per direction: N[E][q][P], D[E][q][P], W[E][q]
+  int E[3], nf[3], off[3];
+  int tiles[3];           // tiles along x, y, and z-chunks
+  int TZ;                 // owned z-coefficients per chunk
+  int tile0, ntiles;
+};
+
+// Apply of a sum of tensor products of 1D banded matrices (elasticity
+// couplings):  out = alpha*base + sum_t coef_t * (T^t_x (x) T^t_y (x) T^t_z) src_t
+struct KronTerm {
+  const double* src;
+  const double* T[3];     // banded [m][2p+1], band[i*(2p+1) + (j-i+p)]
+  double coef;
+};
+struct KronJob {
+  double* out;
+  const double* base;
+  double alpha;
+  KronTerm term[6];
+  int nterm;
+  int p;
+  int nx, ny, nz;
+  int tile0, ntiles;
+};
+
+}  // namespace ads

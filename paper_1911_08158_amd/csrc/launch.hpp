@@ -1,0 +1,37 @@
+// Kernel launchers (defined in the k_*.hip translation units).
+#pragma once
+
+#include "common.hpp"
+
+namespace ads {
+
+int sweep_width_for(int max_m);
+hipError_t launch_sweeps(const SweepJob* d_jobs, int njobs, int total_tiles, int max_m, int grid_cap,
+                         hipStream_t s);
+hipError_t sweep_set_attributes();
+
+int rhs_tile_x(int p);
+int rhs_tile_y(int p);
+hipError_t launch_rhs_pwave(int p, const RhsJob* d_jobs, int njobs, int total_tiles, int grid_cap,
+                            hipStream_t s);
+int rhs_el_tile_x(int p);
+int rhs_el_tile_y(int p);
+hipError_t launch_rhs_elastic(int p, const RhsJob* d_jobs, int njobs, int total_tiles, int grid_cap,
+                              hipStream_t s);
+
+hipError_t launch_kron(const KronJob* d_jobs, int njobs, int total_tiles, int grid_cap, hipStream_t s);
+int kron_tile_points();
+
+hipError_t launch_full_to_free(const double* full, double* fr, const int n[3], const int nf[3],
+                               const int off[3], int ncomp, hipStream_t s);
+hipError_t launch_free_to_full(const double* fr, double* full, const int n[3], const int nf[3],
+                               const int off[3], int ncomp, hipStream_t s);
+hipError_t launch_proj_contract(const double* in, double* out, long long outer, int E, int q, int P, int nf,
+                                int off, long long inner, const double* tab, hipStream_t s);
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+hipError_t launch_axpby(double* out, const double* x, const double* y, double a, double b, long long n,
+                        hipStream_t s);
+hipError_t launch_nonfinite(const double* x, long long n, unsigned long long* cnt, hipStream_t s);
+
+}  // namespace ads

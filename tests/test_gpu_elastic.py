@@ -1,0 +1,78 @@
+"""GPU parity of the elasticity (alternating-triangular) hot path against the
+CPU oracle, through the C-ABI.  Bar: relative L2 <= 1e-12 (FP64)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from runners import gpu_sim, oracle_elastic, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C4.with_(nelem=(6, 5, 7), steps=4, tau=0.02, lam=0.8, mu=0.6, rho=1.3),
+    W.C4.with_(nelem=(17, 9, 11), steps=3, tau=0.01),
+    W.C4.with_(nelem=(5, 6, 4), p=3, q=4, steps=3, tau=0.02, lam=2.0, mu=0.5, rho=0.9),
+    W.C4.with_(nelem=(1, 2, 3), steps=2, tau=0.1, init="noise"),
+    W.C4.with_(nelem=(8, 8, 8), steps=3, tau=2.0),
+], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}")
+def test_elastic_matches_oracle(cfg):
+    _cuda()
+    el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
+    sim, U0 = gpu_sim(cfg)
+    assert rel_l2(U0.cpu().numpy(), el.to_full(U0_ref)) <= TOL
+    sim.close()
+    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref))
+    sim.factor()
+    u, v, _ = sim.get_state()
+    assert rel_l2(v.cpu().numpy(), el.to_full(hist[0][1])) <= TOL   # U^{-1}
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, _ = sim.get_state()
+        eu = rel_l2(u.cpu().numpy(), el.to_full(hist[k][0]))
+        ev = rel_l2(v.cpu().numpy(), el.to_full(hist[k][1]))
+        assert max(eu, ev) <= TOL, (k, eu, ev)
+    sim.close()
+
+
+def test_elastic_c4_steps():
+    """C4 size (64^3, p=2, lambda = mu = rho = 1, tau = 5e-3): 10 steps."""
+    _cuda()
+    cfg = W.C4
+    n = 10
+    el, U0_ref, (Un, Unm1) = oracle_elastic(cfg, n)
+    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref))
+    sim.factor()
+    sim.step(n)
+    u, v, _ = sim.get_state()
+    eu = rel_l2(u.cpu().numpy(), el.to_full(Un))
+    ev = rel_l2(v.cpu().numpy(), el.to_full(Unm1))
+    print(f"C4 step {n}: rel L2 U^n {eu:.2e} U^(n-1) {ev:.2e}", flush=True)
+    assert max(eu, ev) <= TOL
+    sim.close()
+
+
+def test_elastic_energy_on_gpu():
+    _cuda()
+    cfg = W.C4.with_(nelem=(6, 6, 6), steps=20, tau=0.5)
+    from oracle import elastic
+    el = elastic.Elastic(cfg.nelem, cfg.p, cfg.q, cfg.tau)
+    sim, _ = gpu_sim(cfg)
+    sim.factor()
+    E = []
+    prev = sim.get_state()[0].cpu().numpy()
+    for k in range(cfg.steps):
+        sim.step(1)
+        cur = sim.get_state()[0].cpu().numpy()
+        E.append(el.energy(el.to_free(cur), el.to_free(prev)))
+        prev = cur
+    E = np.array(E)
+    assert np.all(np.abs(E / E[0] - 1) < 1e-10)
+    sim.close()

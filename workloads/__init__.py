@@ -44,7 +44,7 @@ class SimConfig:
     rho: float = 1.0
     lam: float = 1.0
     mu: float = 1.0
-    init: str = "bump"      # "bump" | "gauss8" | "elastic_pulse"
+    init: str = "bump"      # "bump" | "gauss8" | "elastic_pulse" | "noise" | "gauss1:<seed>"
     load: str = "none"      # "none" | "ricker_point"
     seed: int = MASTER_SEED
 
@@ -161,6 +161,13 @@ def initial_values(cfg: SimConfig, xs, ys, zs) -> np.ndarray:
         return eval_gaussian_sum(gauss8(cfg.seed), xs, ys, zs)
     if cfg.init == "elastic_pulse":
         return eval_elastic_pulse(elastic_pulse(cfg.seed), xs, ys, zs)
+    if cfg.init == "noise":
+        # seeded white noise at the points (broad spectrum; indexed by point
+        # order, so both sides see the same values at their own points)
+        rng = np.random.default_rng(cfg.seed + 3)
+        shape = (len(zs), len(ys), len(xs))
+        v = rng.uniform(-1.0, 1.0, size=((3,) if cfg.problem == "elastic" else ()) + shape)
+        return v
     if cfg.init.startswith("gauss1:"):
         # single seeded bump used by the serving mix: "gauss1:<seed>"
         s = int(cfg.init.split(":")[1])
