@@ -130,6 +130,15 @@ ads_status ads_factor(ads_sim* sim);
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 
+/* Autotuner of the right-hand-side tiling (measurement-driven, P-wave):
+ * times every tile-shape variant of the quadrature kernel on this mesh
+ * (HIP events, a few launches each; synchronizes), keeps the fastest and
+ * caches the choice per (degree, precision, mesh) for later simulations in
+ * the process.  *chosen receives the variant index, host_ms (may be NULL,
+ * up to cap entries) the mean ms per variant.  Call after ads_factor.
+ * Elasticity: no variants, returns ADS_OK with *chosen = 0. */
+ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);
+
 /* Copy the state out (full layout; asynchronous on the sim's stream).
  * P-wave: u, u', u'' (any pointer may be NULL).  Elasticity: U^n into dev_u,
  * U^{n-1} into dev_v, dev_a ignored. */
@@ -169,6 +178,55 @@ ads_status ads_destroy(ads_sim* sim);
 
 /* Thread-local message of the last non-OK status (never NULL). */
 const char* ads_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched pool (serving form; not a construct of the paper).  Many
+ * simulations of different meshes, degrees (2, 3), problems and precisions
+ * live in one caller workspace and advance together: every pool step runs
+ * ONE launch per kernel class and stage for all active simulations
+ * (persistent kernels over device job tables), replayed from a hipGraph
+ * captured once; the job tables are rewritten between replays when the
+ * batch changes.  Results are bitwise identical to running each simulation
+ * alone (per-output arithmetic does not depend on tiling or batching).
+ * Limits: at most 128 free coefficients per direction in pooled
+ * simulations; max_slots <= 256.
+ * ------------------------------------------------------------------------ */
+typedef struct ads_pool ads_pool;
+
+/* Workspace: caller-owned device buffer (256-byte aligned) from which the
+ * pool carves its job tables and every admitted simulation's workspace.
+ * use_graph = 0 enqueues the launches directly instead of replaying. */
+ads_status ads_pool_create(void* dev_workspace, size_t bytes, int32_t max_slots, void* hip_stream,
+                           int32_t use_graph, ads_pool** out);
+/* Admission by memory: carves a simulation (zero state) for prm from the
+ * pool workspace; ADS_ENOMEM when no slot or not enough contiguous bytes
+ * are free right now (try again after a retirement).  The new slot is
+ * inactive: configure it through ads_pool_sim (ads_project, ads_set_state,
+ * ads_set_load, ads_factor), then ads_pool_activate. */
+ads_status ads_pool_admit(ads_pool* pool, const ads_params* prm, int32_t* slot);
+ads_status ads_pool_sim(ads_pool* pool, int32_t slot, ads_sim** sim);
+/* Join the batch from the next pool step (the simulation must be factored). */
+ads_status ads_pool_activate(ads_pool* pool, int32_t slot);
+/* Advance every active simulation by nsteps steps (asynchronous). */
+ads_status ads_pool_step(ads_pool* pool, int32_t nsteps);
+/* Leave the batch and release the slot's memory (read the state first with
+ * ads_get_state on ads_pool_sim's handle; the release is stream-ordered). */
+ads_status ads_pool_retire(ads_pool* pool, int32_t slot);
+/* Durations (ms) of the pool steps since the last call (synchronizes). */
+ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int32_t* n);
+/* Kernel timing of pool steps (measurement support): with enable = 1 the
+ * following ads_pool_step calls enqueue the launches directly (no graph)
+ * with HIP events around each; ads_pool_profile_read synchronizes and
+ * returns the mean ms per launch position of one pool step over the
+ * recorded steps, its kind (0 = P-wave right-hand side, 5 = elasticity
+ * right-hand side, 1/2/3 = sweeps, 4 = coupling apply), degree and
+ * mixed flag (host arrays of cap entries), and resets the record. */
+ads_status ads_pool_profile(ads_pool* pool, int32_t enable);
+ads_status ads_pool_profile_read(ads_pool* pool, double* host_ms, int32_t* host_kind, int32_t* host_p,
+                                 int32_t* host_mixed, int32_t cap, int32_t* nlaunch);
+/* Active slots and workspace bytes in use / free. */
+ads_status ads_pool_info(ads_pool* pool, int32_t* active, size_t* used_bytes, size_t* free_bytes);
+ads_status ads_pool_destroy(ads_pool* pool);
 
 #ifdef __cplusplus
 }

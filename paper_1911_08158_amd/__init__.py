@@ -5,4 +5,4 @@ C-ABI in ``include/ads.h``).  This package only marshals arguments to it:
 PyTorch provides device memory and streams.  Build with
 ``python -m paper_1911_08158_amd.build``.
 """
-from .binding import AdsError, Params, Sim, lib_path, load_library, quad_points  # noqa: F401
+from .binding import AdsError, Params, Pool, PooledSim, Sim, lib_path, load_library, quad_points  # noqa: F401

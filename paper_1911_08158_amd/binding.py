@@ -98,10 +98,22 @@ def load_library():
         "ads_set_state": [c_void_p, c_void_p, c_void_p, c_void_p, c_int64],
         "ads_get_step": [c_void_p, POINTER(c_int64)],
         "ads_check_finite": [c_void_p],
+        "ads_tune": [c_void_p, POINTER(c_int32), c_void_p, c_int32],
         "ads_profile": [c_void_p, c_int32],
         "ads_profile_read": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_int32,
                              POINTER(c_int32)],
         "ads_destroy": [c_void_p],
+        "ads_pool_create": [c_void_p, c_size_t, c_int32, c_void_p, c_int32, POINTER(c_void_p)],
+        "ads_pool_admit": [c_void_p, P, POINTER(c_int32)],
+        "ads_pool_sim": [c_void_p, c_int32, POINTER(c_void_p)],
+        "ads_pool_activate": [c_void_p, c_int32],
+        "ads_pool_step": [c_void_p, c_int32],
+        "ads_pool_retire": [c_void_p, c_int32],
+        "ads_pool_step_times": [c_void_p, c_void_p, c_int32, POINTER(c_int32)],
+        "ads_pool_info": [c_void_p, POINTER(c_int32), POINTER(c_size_t), POINTER(c_size_t)],
+        "ads_pool_destroy": [c_void_p],
+        "ads_pool_profile": [c_void_p, c_int32],
+        "ads_pool_profile_read": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -159,8 +171,23 @@ class Sim:
 
     # -- helpers ----------------------------------------------------------
     def _empty_full(self):
+        # the library writes every entry (boundary ones as 0): no fill kernel
         import torch
-        return torch.zeros(self.prm.full_shape, dtype=torch.float64, device=self.device)
+        return torch.empty(self.prm.full_shape, dtype=torch.float64, device=self.device)
+
+    def _pre(self):
+        """Order the library's stream after torch's current stream (inputs)."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _post(self):
+        """Order torch's current stream after the library's stream (outputs)."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
 
     def quad_points(self, d):
         return quad_points(self.prm, d)
@@ -176,11 +203,14 @@ class Sim:
         scratch = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         out = self._empty_full()
         vals = vals.to(self.device, torch.float64).contiguous()
+        self._pre()
         _check(L.ads_project(self._h, _ptr(vals), _ptr(out), scratch.data_ptr(), n.value))
+        self._post()
         return out
 
     def set_load(self, b, amps):
         amps = np.ascontiguousarray(amps, dtype=np.float64)
+        self._pre()
         _check(load_library().ads_set_load(self._h, _ptr(b), amps.ctypes.data, int(amps.size)))
 
     def set_point_load(self, xs, amps):
@@ -197,11 +227,13 @@ class Sim:
     def get_state(self):
         u, v = self._empty_full(), self._empty_full()
         a = self._empty_full() if self.prm.comps == 1 else None
+        self._pre()
         _check(load_library().ads_get_state(self._h, _ptr(u), _ptr(v), _ptr(a)))
         self.stream.synchronize()
         return u, v, a
 
     def set_state(self, u, v=None, a=None, step=0):
+        self._pre()
         _check(load_library().ads_set_state(self._h, _ptr(u), _ptr(v), _ptr(a), int(step)))
 
     def step_index(self):
@@ -211,6 +243,14 @@ class Sim:
 
     def check_finite(self):
         _check(load_library().ads_check_finite(self._h))
+
+    def tune(self):
+        """Autotune the right-hand-side tiling on this mesh; returns the
+        chosen variant and the measured ms per variant (NaN if cached)."""
+        ch = c_int32()
+        ms = np.full(8, np.nan)
+        _check(load_library().ads_tune(self._h, byref(ch), ms.ctypes.data, 8))
+        return ch.value, ms
 
     def profile(self, enable=True):
         _check(load_library().ads_profile(self._h, 1 if enable else 0))
@@ -234,6 +274,101 @@ class Sim:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().ads_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PooledSim(Sim):
+    """A simulation living in a Pool slot (the pool owns its memory)."""
+
+    def __init__(self, pool, slot, prm):
+        self.prm = prm
+        self.device = pool.device
+        self.stream = pool.stream
+        self.slot = slot
+        h = c_void_p()
+        _check(load_library().ads_pool_sim(pool._h, slot, byref(h)))
+        self._h = h
+
+    def close(self):          # released by Pool.retire
+        self._h = c_void_p()
+
+
+class Pool:
+    """Batched serving pool: admission by memory, one graph replay per step
+    for all active simulations (include/ads.h, ads_pool_*)."""
+
+    def __init__(self, nbytes, max_slots=64, device=None, stream=None, use_graph=True):
+        import torch
+        self.device = torch.device(device if device is not None else "cuda")
+        # graph capture needs a non-default stream; default priority
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        h = c_void_p()
+        _check(load_library().ads_pool_create(ptr, int(nbytes), int(max_slots), self.stream.cuda_stream,
+                                              1 if use_graph else 0, byref(h)))
+        self._h = h
+        self.sims = {}
+
+    def admit(self, cfg=None, **kw):
+        """Returns a PooledSim, or None when memory or slots are exhausted."""
+        prm = Params.of(cfg, **kw)
+        slot = c_int32()
+        st = load_library().ads_pool_admit(self._h, byref(prm), byref(slot))
+        if st == -2:
+            return None
+        _check(st)
+        s = PooledSim(self, slot.value, prm)
+        self.sims[slot.value] = s
+        return s
+
+    def activate(self, sim):
+        _check(load_library().ads_pool_activate(self._h, sim.slot))
+
+    def step(self, n=1):
+        _check(load_library().ads_pool_step(self._h, int(n)))
+
+    def retire(self, sim):
+        _check(load_library().ads_pool_retire(self._h, sim.slot))
+        self.sims.pop(sim.slot, None)
+        sim.close()
+
+    def step_times(self, cap=1 << 16):
+        ms = np.zeros(cap)
+        n = c_int32()
+        _check(load_library().ads_pool_step_times(self._h, ms.ctypes.data, cap, byref(n)))
+        return ms[:n.value].copy()
+
+    POOL_KINDS = {0: "rhs", 5: "rhs_elastic", 1: "sweep_x", 2: "sweep_y", 3: "sweep_z", 4: "couple"}
+
+    def profile(self, enable=True):
+        _check(load_library().ads_pool_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """[(kind, p, mixed, mean ms)] per launch position of a pool step."""
+        cap = 64
+        ms = np.zeros(cap)
+        kind, pp, mx = (np.zeros(cap, dtype=np.int32) for _ in range(3))
+        n = c_int32()
+        _check(load_library().ads_pool_profile_read(self._h, ms.ctypes.data, kind.ctypes.data, pp.ctypes.data,
+                                                    mx.ctypes.data, cap, byref(n)))
+        return [(self.POOL_KINDS.get(int(kind[i]), str(kind[i])), int(pp[i]), int(mx[i]), float(ms[i]))
+                for i in range(n.value)]
+
+    def info(self):
+        a, u, f = c_int32(), c_size_t(), c_size_t()
+        _check(load_library().ads_pool_info(self._h, byref(a), byref(u), byref(f)))
+        return {"active": a.value, "used_bytes": u.value, "free_bytes": f.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ads_pool_destroy(self._h)
             self._h = c_void_p()
 
     def __del__(self):

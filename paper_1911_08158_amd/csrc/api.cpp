@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,7 @@ using namespace ads;
 namespace {
 
 thread_local std::string g_err = "no error";
+thread_local int g_force_var = -1;   // right-hand-side tile variant imposed by a pool
 
 ads_status fail(ads_status s, const std::string& msg) {
   g_err = msg;
@@ -51,12 +53,16 @@ struct Carver {
   double* dbl(size_t n) { return (double*)take(n * sizeof(double)); }
 };
 
-// One kernel launch of a step (or of setup), with its device job table.
+// One kernel launch of a step (or of setup), with its device job table
+// (LaunchHdr + jobs) and a host copy of the jobs (for batching).
 struct Launch {
   enum Kind { RHS_P, RHS_E, SWEEP, KRON } kind;
-  const void* d_jobs;
+  const LaunchHdr* d_hdr;
   int njobs, total_tiles, max_m, p;
   int dir = -1;   // sweeps: direction
+  int var = 0;    // right-hand side: tile variant
+  int mixed = 0;  // right-hand side: FP32 contractions
+  std::vector<char> host_jobs;
 };
 
 struct DevFactor {
@@ -69,19 +75,38 @@ struct JobArena {
   char* d_base = nullptr;
   std::vector<char> host;
   size_t cap = 0;
+  // Appends a header + job table (tile0 set to prefix sums); returns the
+  // device address of the header, or nullptr when the arena is full.
   template <class T>
-  T* add(const std::vector<T>& jobs, std::string& err) {
+  const LaunchHdr* add(std::vector<T> jobs, std::string& err, int* total = nullptr) {
     size_t off = (host.size() + kAlign - 1) / kAlign * kAlign;
-    size_t bytes = jobs.size() * sizeof(T);
+    size_t bytes = sizeof(LaunchHdr) + jobs.size() * sizeof(T);
     if (off + bytes > cap) {
       err = "job arena full";
       return nullptr;
     }
+    int t = 0;
+    for (T& j : jobs) {
+      j.tile0 = t;
+      t += j.ntiles;
+    }
+    LaunchHdr h{};
+    h.njobs = (int)jobs.size();
+    h.total_tiles = t;
     host.resize(off + bytes);
-    std::memcpy(host.data() + off, jobs.data(), bytes);
-    return (T*)(d_base + off);
+    std::memcpy(host.data() + off, &h, sizeof(h));
+    std::memcpy(host.data() + off + sizeof(LaunchHdr), jobs.data(), jobs.size() * sizeof(T));
+    if (total) *total = t;
+    return (const LaunchHdr*)(d_base + off);
   }
 };
+
+template <class T>
+std::vector<char> as_bytes(const T& j) {
+  std::vector<char> b(sizeof(T));
+  std::memcpy(b.data(), &j, sizeof(T));
+  return b;
+}
 
 }  // namespace
 
@@ -108,6 +133,8 @@ struct ads_sim {
   bool factored = false, need_start = true, have_load = false;
   int namp = 0;
   int tz = 0;
+  int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
+  bool mixed = false;   // FP32 contractions in the right-hand side
   // kernel timing (measurement support)
   bool prof = false;
   std::vector<hipEvent_t> ev;     // (launches + 1) events per recorded step
@@ -185,6 +212,7 @@ void geometry(ads_sim* s) {
     s->off[d] = 1;
   }
   s->nfree = (long long)s->nf[0] * s->nf[1] * s->nf[2];
+  s->mixed = P.precision == ADS_MIXED_FP32;
 }
 
 // Walks every device allocation of a simulation (sizing and carving).
@@ -276,9 +304,9 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
   jz.tile0 = 0;
   jz.scale = 1.0;
   for (SweepJob* j : {&jx, &jy, &jz}) {
-    SweepJob* d = s->arena.add(std::vector<SweepJob>{*j}, err);
+    const LaunchHdr* d = s->arena.add(std::vector<SweepJob>{*j}, err);
     if (!d) return false;
-    L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir});
+    L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir, 0, 0, as_bytes(*j)});
   }
   return true;
 }
@@ -330,7 +358,7 @@ RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_
   J.counter = s->counter;
   J.rscale = 1.0;
   fill_tables(s, J);
-  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p));
+  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p, s->rhs_var));
   return J;
 }
 
@@ -394,9 +422,9 @@ void kron_add_mass(const ads_sim* s, KronJob& K, const double* src, double coef)
 }
 
 bool push_kron(ads_sim* s, std::vector<Launch>& L, const KronJob& K, std::string& err) {
-  KronJob* d = s->arena.add(std::vector<KronJob>{K}, err);
+  const LaunchHdr* d = s->arena.add(std::vector<KronJob>{K}, err);
   if (!d) return false;
-  L.push_back(Launch{Launch::KRON, d, 1, K.ntiles, 0, s->p});
+  L.push_back(Launch{Launch::KRON, d, 1, K.ntiles, 0, s->p, -1, 0, 0, as_bytes(K)});
   return true;
 }
 
@@ -446,6 +474,8 @@ bool add_at_solve(ads_sim* s, std::vector<Launch>& L, bool update, bool count, s
   return true;
 }
 
+int grid_of(const Launch& l, int cap) { return (cap > 0 && l.total_tiles > cap) ? cap : l.total_tiles; }
+
 ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, hipEvent_t* evs = nullptr) {
   if (evs) HIPCHECK(hipEventRecord(evs[0], s->stream));
   for (size_t li = 0; li < L.size(); ++li) {
@@ -453,16 +483,16 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
     hipError_t e = hipSuccess;
     switch (l.kind) {
       case Launch::RHS_P:
-        e = launch_rhs_pwave(l.p, (const RhsJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        e = launch_rhs_pwave(l.p, l.mixed, l.var, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::RHS_E:
-        e = launch_rhs_elastic(l.p, (const RhsJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        e = launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::SWEEP:
-        e = launch_sweeps((const SweepJob*)l.d_jobs, l.njobs, l.total_tiles, l.max_m, grid_cap, s->stream);
+        e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.max_m, s->stream);
         break;
       case Launch::KRON:
-        e = launch_kron((const KronJob*)l.d_jobs, l.njobs, l.total_tiles, grid_cap, s->stream);
+        e = launch_kron(l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -503,9 +533,10 @@ ads_status build_launches(ads_sim* s) {
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
     RhsJob rj = rhs_pwave_job(s, 1.0, tau, eta, 1);
-    RhsJob* d = s->arena.add(std::vector<RhsJob>{rj}, err);
+    const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    s->step_l.push_back(Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p});
+    s->step_l.push_back(
+        Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(rj)});
     SweepJob z{};
     z.epi = EPI_NEWMARK;
     z.c0 = tau;
@@ -519,16 +550,17 @@ ads_status build_launches(ads_sim* s) {
     RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0);
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p});
+    // the start is computed in FP64 in every precision mode
+    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, s->rhs_var, 0, as_bytes(r0)});
     if (!add_ads_solve(s, s->start_l, s->fS, s->R, s->R, s->a, 1.0, plain_epi(), err))
       return fail(ADS_ENOMEM, err);
   } else {
     RhsJob rj = rhs_elastic_job(s);
-    RhsJob* d = s->arena.add(std::vector<RhsJob>{rj}, err);
+    const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    s->step_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p});
+    s->step_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, 0, 0, as_bytes(rj)});
     if (!add_at_solve(s, s->step_l, true, true, err)) return fail(ADS_ENOMEM, err);
-    s->start_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p});
+    s->start_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, 0, 0, as_bytes(rj)});
     if (!add_at_solve(s, s->start_l, false, false, err)) return fail(ADS_ENOMEM, err);
   }
   // mass solve used by the projection: R -> R (per component, offset applied at launch)
@@ -597,6 +629,8 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   s->stream = (hipStream_t)stream;
   geometry(s);
   if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
+  if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(2, std::atoi(e)));
+  if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
   Carver c{(char*)ws};
   carve(s, c);
   // host tables and matrices
@@ -776,6 +810,59 @@ ads_status ads_step(ads_sim* s, int32_t nsteps) {
   return ADS_OK;
 }
 
+ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
+  if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
+  if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
+  if (s->elastic) {
+    *chosen = 0;
+    return ADS_OK;
+  }
+  static std::map<std::string, int> cache;
+  const std::string key = std::to_string(s->p) + "/" + std::to_string(s->mixed) + "/" + std::to_string(s->nf[0]) +
+                          "x" + std::to_string(s->nf[1]) + "x" + std::to_string(s->nf[2]);
+  const int nv = rhs_num_variants(s->p);
+  int best = -1;
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    double best_ms = 1e30;
+    for (int v = 0; v < nv; ++v) {
+      s->rhs_var = v;
+      ads_status st = build_launches(s);
+      if (st != ADS_OK) return st;
+      std::vector<Launch> one(1, s->step_l[0]);
+      if ((st = enqueue(s, one)) != ADS_OK) return st;
+      HIPCHECK(hipEventRecord(e0, s->stream));
+      const int reps = 5;
+      for (int r = 0; r < reps; ++r)
+        if ((st = enqueue(s, one)) != ADS_OK) return st;
+      HIPCHECK(hipEventRecord(e1, s->stream));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      double per = ms / reps;
+      if (host_ms && v < cap) host_ms[v] = per;
+      if (per < best_ms) {
+        best_ms = per;
+        best = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cache[key] = best;
+  }
+  s->rhs_var = best;
+  ads_status st = build_launches(s);
+  if (st != ADS_OK) return st;
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  *chosen = best;
+  return ADS_OK;
+}
+
 ads_status ads_profile(ads_sim* s, int32_t enable) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   s->prof = enable != 0;
@@ -864,6 +951,375 @@ ads_status ads_get_step(ads_sim* s, int64_t* step) {
 ads_status ads_destroy(ads_sim* s) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   delete s;
+  return ADS_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched pool
+// ============================================================================
+namespace {
+
+constexpr int kPoolStages = 23;   // launches after the right-hand side (elasticity: 3 + 5 x 4)
+constexpr int kPoolMaxM = 128;    // free coefficients per direction in pooled simulations
+
+bool is_kron_stage(int k) { return k % 4 == 0; }   // stages 4, 8, 12, 16, 20
+
+struct PoolLaunch {
+  Launch::Kind kind;
+  int p, mixed, var;
+  int stage;        // 0: right-hand side class, k >= 1: k-th launch after it
+  int grid;
+  size_t off, cap;  // table offset/capacity (bytes) in the pool's table region
+  size_t job_size;
+};
+
+}  // namespace
+
+struct ads_pool {
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int max_slots = 0;
+  char* d_tab = nullptr;
+  size_t tab_bytes = 0;
+  std::vector<char> h_tab;
+  size_t arena_off = 0;
+  std::map<size_t, size_t> used;   // arena offset -> size
+  struct Slot {
+    ads_sim* sim = nullptr;
+    size_t off = 0, size = 0;
+    bool active = false;
+  };
+  std::vector<Slot> slots;
+  std::vector<PoolLaunch> seq;
+  bool dirty = true;
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> ev;
+  int nev = 0;
+  int var[2][2] = {{0, 0}, {0, 0}};
+  bool prof = false;
+  std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
+  int prof_steps = 0;
+  ~ads_pool() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pev) (void)hipEventDestroy(e);
+    for (Slot& s : slots) delete s.sim;
+  }
+};
+
+namespace {
+
+void pool_build_seq(ads_pool* P, int ncu) {
+  P->seq.clear();
+  size_t off = 0;
+  auto add = [&](Launch::Kind k, int p, int mixed, int var, int stage, int grid, size_t js) {
+    PoolLaunch L{k, p, mixed, var, stage, grid, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
+    off += (L.cap + kAlign - 1) / kAlign * kAlign;
+    P->seq.push_back(L);
+  };
+  for (int p = 2; p <= 3; ++p)
+    for (int mixed = 0; mixed <= 1; ++mixed) {
+      int var = P->var[p - 2][mixed];
+      add(Launch::RHS_P, p, mixed, var, 0, rhs_blocks_per_cu(p, mixed, var) * ncu, sizeof(RhsJob));
+    }
+  for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
+  for (int k = 1; k <= kPoolStages; ++k) {
+    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, 8 * ncu, sizeof(KronJob));
+    else add(Launch::SWEEP, 0, 0, 0, k, 2 * ncu, sizeof(SweepJob));
+  }
+  P->tab_bytes = off;
+}
+
+// Gathers the jobs of every active simulation into the merged tables.
+ads_status pool_rebuild(ads_pool* P) {
+  std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
+  for (const PoolLaunch& L : P->seq) {
+    std::vector<char> jobs;
+    int n = 0, total = 0;
+    for (ads_pool::Slot& sl : P->slots) {
+      if (!sl.active) continue;
+      const std::vector<Launch>& st = sl.sim->step_l;
+      if ((int)st.size() <= L.stage) continue;
+      const Launch& l = st[L.stage];
+      if (l.kind != L.kind) continue;
+      if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && l.var != L.var)))
+        continue;
+      std::vector<char> j = l.host_jobs;
+      // every job struct starts its tiling fields the same way: patch tile0
+      if (L.kind == Launch::SWEEP) {
+        SweepJob* s = (SweepJob*)j.data();
+        s->tile0 = total;
+        total += s->ntiles;
+      } else if (L.kind == Launch::KRON) {
+        KronJob* s = (KronJob*)j.data();
+        s->tile0 = total;
+        total += s->ntiles;
+      } else {
+        RhsJob* s = (RhsJob*)j.data();
+        s->tile0 = total;
+        total += s->ntiles;
+      }
+      jobs.insert(jobs.end(), j.begin(), j.end());
+      ++n;
+    }
+    LaunchHdr h{};
+    h.njobs = n;
+    h.total_tiles = total;
+    std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
+    if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
+  }
+  HIPCHECK(hipMemcpyAsync(P->d_tab, P->h_tab.data(), P->tab_bytes, hipMemcpyHostToDevice, P->stream));
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  P->dirty = false;
+  return ADS_OK;
+}
+
+ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
+  if (evs) HIPCHECK(hipEventRecord(evs[0], P->stream));
+  for (size_t li = 0; li < P->seq.size(); ++li) {
+    const PoolLaunch& L = P->seq[li];
+    const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+      case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, h, L.grid, P->stream); break;
+      case Launch::RHS_E: e = launch_rhs_elastic(L.p, h, L.grid, P->stream); break;
+      case Launch::SWEEP: e = launch_sweeps(h, L.grid, kPoolMaxM, P->stream); break;
+      case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;
+    }
+    if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
+    if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
+  }
+  return ADS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stream, int32_t use_graph,
+                           ads_pool** out) {
+  if (!ws || !out) return fail(ADS_EINVAL, "NULL argument");
+  if (((uintptr_t)ws) % kAlign) return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
+  if (max_slots < 1 || max_slots > 256) return fail(ADS_EINVAL, "max_slots must be in [1, 256]");
+  if (use_graph && !stream) return fail(ADS_EINVAL, "graph replay needs a non-default stream");
+  static bool attrs = false;
+  if (!attrs) {
+    HIPCHECK(sweep_set_attributes());
+    attrs = true;
+  }
+  int dev = 0, ncu = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  ads_pool* P = new ads_pool();
+  P->stream = (hipStream_t)stream;
+  P->ws = (char*)ws;
+  P->bytes = bytes;
+  P->max_slots = max_slots;
+  P->use_graph = use_graph != 0;
+  P->slots.resize(max_slots);
+  if (const char* e = std::getenv("ADS_POOL_RHS_VAR")) {
+    int v = std::max(0, std::min(2, std::atoi(e)));
+    for (auto& r : P->var) r[0] = r[1] = v;
+  }
+  pool_build_seq(P, ncu);
+  P->arena_off = (P->tab_bytes + kAlign - 1) / kAlign * kAlign;
+  if (P->arena_off >= bytes) {
+    delete P;
+    return fail(ADS_ENOMEM, "pool workspace smaller than its job tables");
+  }
+  P->d_tab = P->ws;
+  P->h_tab.assign(P->tab_bytes, 0);
+  ads_status st = pool_rebuild(P);
+  if (st != ADS_OK) {
+    delete P;
+    return st;
+  }
+  *out = P;
+  return ADS_OK;
+}
+
+ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
+  if (!P || !prm || !slot) return fail(ADS_EINVAL, "NULL argument");
+  std::string why;
+  if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
+  for (int d = 0; d < 3; ++d)
+    if (prm->nelem[d] + prm->p - 2 > kPoolMaxM) return fail(ADS_EINVAL, "pooled meshes: <= 128 free coefficients");
+  int free_slot = -1;
+  for (int i = 0; i < P->max_slots; ++i)
+    if (!P->slots[i].sim) {
+      free_slot = i;
+      break;
+    }
+  if (free_slot < 0) return fail(ADS_ENOMEM, "no free slot");
+  size_t need = 0;
+  ads_workspace_bytes(prm, &need);
+  need = (need + kAlign - 1) / kAlign * kAlign;
+  // first fit over the gaps between allocated blocks
+  size_t cur = P->arena_off, found = (size_t)-1;
+  for (auto& kv : P->used) {
+    if (kv.first >= cur + need) {
+      found = cur;
+      break;
+    }
+    cur = std::max(cur, kv.first + kv.second);
+  }
+  if (found == (size_t)-1 && cur + need <= P->bytes) found = cur;
+  if (found == (size_t)-1) return fail(ADS_ENOMEM, "not enough free pool memory");
+  ads_sim* s = nullptr;
+  g_force_var = P->var[prm->p - 2][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
+  ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
+  g_force_var = -1;
+  if (st != ADS_OK) return st;
+  P->used[found] = need;
+  P->slots[free_slot] = ads_pool::Slot{s, found, need, false};
+  *slot = free_slot;
+  return ADS_OK;
+}
+
+ads_status ads_pool_sim(ads_pool* P, int32_t slot, ads_sim** sim) {
+  if (!P || !sim || slot < 0 || slot >= P->max_slots || !P->slots[slot].sim) return fail(ADS_EINVAL, "bad slot");
+  *sim = P->slots[slot].sim;
+  return ADS_OK;
+}
+
+ads_status ads_pool_activate(ads_pool* P, int32_t slot) {
+  if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].sim) return fail(ADS_EINVAL, "bad slot");
+  ads_sim* s = P->slots[slot].sim;
+  if (!s->factored || s->need_start) return fail(ADS_ESTATE, "activate before ads_factor");
+  P->slots[slot].active = true;
+  P->dirty = true;
+  return ADS_OK;
+}
+
+ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
+  if (!P || nsteps < 0) return fail(ADS_EINVAL, "bad argument");
+  ads_status st;
+  if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
+  if (P->use_graph && !P->exec) {
+    HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    st = pool_enqueue(P);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->stream, &g);
+    if (st != ADS_OK) return st;
+    if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    P->graph = g;
+    HIPCHECK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    if (P->nev == 0) {
+      if (P->ev.empty()) {
+        hipEvent_t e0;
+        HIPCHECK(hipEventCreate(&e0));
+        P->ev.push_back(e0);
+      }
+      HIPCHECK(hipEventRecord(P->ev[0], P->stream));
+      P->nev = 1;
+    }
+    if (P->prof) {
+      const size_t per = P->seq.size() + 1;
+      while (P->pev.size() < (size_t)(P->prof_steps + 1) * per) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreate(&e));
+        P->pev.push_back(e);
+      }
+      if ((st = pool_enqueue(P, &P->pev[(size_t)P->prof_steps * per])) != ADS_OK) return st;
+      P->prof_steps++;
+    } else if (P->use_graph) {
+      HIPCHECK(hipGraphLaunch(P->exec, P->stream));
+    } else if ((st = pool_enqueue(P)) != ADS_OK) {
+      return st;
+    }
+    if ((int)P->ev.size() <= P->nev) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      P->ev.push_back(e);
+    }
+    HIPCHECK(hipEventRecord(P->ev[P->nev], P->stream));
+    P->nev++;
+  }
+  return ADS_OK;
+}
+
+ads_status ads_pool_profile(ads_pool* P, int32_t enable) {
+  if (!P) return fail(ADS_EINVAL, "NULL pool");
+  P->prof = enable != 0;
+  P->prof_steps = 0;
+  return ADS_OK;
+}
+
+ads_status ads_pool_profile_read(ads_pool* P, double* ms, int32_t* kind, int32_t* pp, int32_t* mixed, int32_t cap,
+                                 int32_t* nlaunch) {
+  if (!P) return fail(ADS_EINVAL, "NULL pool");
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  const size_t L = P->seq.size(), per = L + 1;
+  for (size_t i = 0; i < L && (int)i < cap; ++i) {
+    double sum = 0.0;
+    for (int k = 0; k < P->prof_steps; ++k) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, P->pev[k * per + i], P->pev[k * per + i + 1]));
+      sum += t;
+    }
+    const PoolLaunch& l = P->seq[i];
+    if (ms) ms[i] = P->prof_steps ? sum / P->prof_steps : 0.0;
+    if (kind) {
+      int kd = l.kind == Launch::RHS_P ? 0 : l.kind == Launch::RHS_E ? 5 : l.kind == Launch::KRON ? 4 : 1;
+      if (l.kind == Launch::SWEEP) kd = 1 + ((l.stage - 1) % 4) % 3;   // x, y, z of each solve
+      kind[i] = kd;
+    }
+    if (pp) pp[i] = l.p;
+    if (mixed) mixed[i] = l.mixed;
+  }
+  if (nlaunch) *nlaunch = (int32_t)L;
+  P->prof_steps = 0;
+  return ADS_OK;
+}
+
+ads_status ads_pool_retire(ads_pool* P, int32_t slot) {
+  if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].sim) return fail(ADS_EINVAL, "bad slot");
+  ads_pool::Slot& sl = P->slots[slot];
+  delete sl.sim;
+  P->used.erase(sl.off);
+  if (sl.active) P->dirty = true;
+  sl = ads_pool::Slot{};
+  return ADS_OK;
+}
+
+ads_status ads_pool_step_times(ads_pool* P, double* ms, int32_t cap, int32_t* n) {
+  if (!P || !n) return fail(ADS_EINVAL, "NULL argument");
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  int cnt = 0;
+  for (int k = 1; k < P->nev; ++k) {
+    float t = 0.f;
+    HIPCHECK(hipEventElapsedTime(&t, P->ev[k - 1], P->ev[k]));
+    if (ms && cnt < cap) ms[cnt] = t;
+    ++cnt;
+  }
+  *n = std::min(cnt, cap);
+  P->nev = 0;
+  return ADS_OK;
+}
+
+ads_status ads_pool_info(ads_pool* P, int32_t* active, size_t* used_bytes, size_t* free_bytes) {
+  if (!P) return fail(ADS_EINVAL, "NULL pool");
+  int a = 0;
+  for (auto& s : P->slots) a += s.active ? 1 : 0;
+  size_t u = 0;
+  for (auto& kv : P->used) u += kv.second;
+  if (active) *active = a;
+  if (used_bytes) *used_bytes = u;
+  if (free_bytes) *free_bytes = P->bytes - P->arena_off - u;
+  return ADS_OK;
+}
+
+ads_status ads_pool_destroy(ads_pool* P) {
+  if (!P) return fail(ADS_EINVAL, "NULL pool");
+  delete P;
   return ADS_OK;
 }
 

@@ -12,7 +12,18 @@
 namespace ads {
 
 constexpr int kMaxP = 3;          // spline degrees 2 and 3 are instantiated
-constexpr int kMaxJobs = 256;     // jobs per launch (one per simulation/component)
+
+// Every launch reads its job count and tile count from a device-side header
+// that precedes its job table, so that a captured graph can be replayed
+// while the tables are rewritten (batches that change between replays).
+struct alignas(256) LaunchHdr {
+  int njobs;
+  int total_tiles;
+};
+template <class Job>
+__host__ __device__ inline const Job* hdr_jobs(const LaunchHdr* h) {
+  return reinterpret_cast<const Job*>(h + 1);
+}
 
 // One 1D banded factor (banded LU without pivoting of a free-row block):
 // L[i*p + k-1] = l_{i,i-k}, U[i*p + k-1] = u_{i,i+k} (zero where the index

@@ -50,8 +50,9 @@ __device__ double kron_term(const KronTerm& T, int x, int y, int z, int nx, int 
   return sz;
 }
 
-__global__ __launch_bounds__(kKronPts) void kron_kernel(const KronJob* __restrict__ jobs, int njobs,
-                                                        int total_tiles) {
+__global__ __launch_bounds__(kKronPts) void kron_kernel(const LaunchHdr* __restrict__ hdr) {
+  const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
+  const KronJob* __restrict__ jobs = hdr_jobs<KronJob>(hdr);
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const KronJob& J = jobs[find_job_kron(jobs, njobs, tile)];
     const long long idx = (long long)(tile - J.tile0) * kKronPts + threadIdx.x;
@@ -72,11 +73,9 @@ __global__ __launch_bounds__(kKronPts) void kron_kernel(const KronJob* __restric
 
 int kron_tile_points() { return kKronPts; }
 
-hipError_t launch_kron(const KronJob* d_jobs, int njobs, int total_tiles, int grid_cap, hipStream_t s) {
-  int grid = total_tiles;
-  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kron_kernel, dim3(grid), dim3(kKronPts), 0, s, d_jobs, njobs, total_tiles);
+  hipLaunchKernelGGL(kron_kernel, dim3(grid), dim3(kKronPts), 0, s, d_hdr);
   return hipGetLastError();
 }
 

@@ -38,8 +38,9 @@ struct RhsElGeom {
 };
 
 template <int P, int Q>
-__global__ __launch_bounds__(256) void rhs_elastic_kernel(const RhsJob* __restrict__ jobs, int njobs,
-                                                          int total_tiles) {
+__global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __restrict__ hdr) {
+  const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
+  const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
   using Gm = RhsElGeom<P, Q>;
   constexpr int p = Gm::p, TX = Gm::TX, TY = Gm::TY, TXH = Gm::TXH, TYH = Gm::TYH, EY = Gm::EY,
                 R = Gm::R, NT = Gm::NT;
@@ -304,15 +305,12 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const RhsJob* __restri
 int rhs_el_tile_x(int p) { return 16 - p; }
 int rhs_el_tile_y(int p) { return p == 2 ? 6 : 3; }
 
-hipError_t launch_rhs_elastic(int p, const RhsJob* d_jobs, int njobs, int total_tiles, int grid_cap,
-                              hipStream_t s) {
-  int grid = total_tiles;
-  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (p == 2) {
-    hipLaunchKernelGGL((rhs_elastic_kernel<3, 3>), dim3(grid), dim3(256), 0, s, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL((rhs_elastic_kernel<3, 3>), dim3(grid), dim3(256), 0, s, d_hdr);
   } else if (p == 3) {
-    hipLaunchKernelGGL((rhs_elastic_kernel<4, 4>), dim3(grid), dim3(256), 0, s, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL((rhs_elastic_kernel<4, 4>), dim3(grid), dim3(256), 0, s, d_hdr);
   } else {
     return hipErrorInvalidValue;
   }

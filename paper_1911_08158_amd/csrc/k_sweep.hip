@@ -29,6 +29,8 @@ __device__ __forceinline__ int find_job_sweep(const SweepJob* jobs, int njobs, i
 template <int W>
 __device__ __forceinline__ int sidx(int i, int l) { return i * W + (l ^ (i & (W - 1))); }
 
+constexpr int kChunk = 32;   // global loads in flight per lane while staging a tile
+
 // Global offset of element i of line `line` and the element stride.
 __device__ __forceinline__ void line_geom(const SweepJob& J, int line, long long& base, long long& stride) {
   if (J.dir == 0) {
@@ -44,20 +46,45 @@ __device__ __forceinline__ void line_geom(const SweepJob& J, int line, long long
   }
 }
 
-__device__ __forceinline__ void epilogue(const SweepJob& J, long long g, double x) {
+// Epilogue on K solved values at global offsets g[k] (ok[k] false = skip);
+// all old-state loads of the batch are issued before any is used.
+constexpr int kEpi = 8;
+__device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long long* g, const double* x,
+                                               const bool* ok) {
   if (J.epi == EPI_STORE) {
-    J.out[g] = x;
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k)
+      if (ok[k]) J.out[g[k]] = x[k];
   } else if (J.epi == EPI_NEWMARK) {
-    double u = J.e0[g], v = J.e1[g], a = J.e2[g];
-    double s = a + x;
-    J.e1[g] = v + 0.5 * J.c0 * s;
-    J.e0[g] = u + J.c0 * v + J.c1 * s;
-    J.e2[g] = x;
+    double u[kEpi], v[kEpi], a[kEpi];
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k) {
+      u[k] = ok[k] ? J.e0[g[k]] : 0.0;
+      v[k] = ok[k] ? J.e1[g[k]] : 0.0;
+      a[k] = ok[k] ? J.e2[g[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k)
+      if (ok[k]) {
+        double s = a[k] + x[k];
+        J.e1[g[k]] = v[k] + 0.5 * J.c0 * s;
+        J.e0[g[k]] = u[k] + J.c0 * v[k] + J.c1 * s;
+        J.e2[g[k]] = x[k];
+      }
   } else {  // EPI_THREELEVEL
-    double un = J.e0[g], um = J.e1[g];
-    J.out[g] = x;
-    J.e1[g] = un;
-    J.e0[g] = 2.0 * un - um + x;
+    double un[kEpi], um[kEpi];
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k) {
+      un[k] = ok[k] ? J.e0[g[k]] : 0.0;
+      um[k] = ok[k] ? J.e1[g[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k)
+      if (ok[k]) {
+        J.out[g[k]] = x[k];
+        J.e1[g[k]] = un[k];
+        J.e0[g[k]] = 2.0 * un[k] - um[k] + x[k];
+      }
   }
 }
 
@@ -70,6 +97,7 @@ __device__ __forceinline__ void substitute(double* lds, int lane, int m, const F
   double h[p];
 #pragma unroll
   for (int k = 0; k < p; ++k) h[k] = 0.0;
+#pragma unroll 8
   for (int i = 0; i < m; ++i) {
     const double* Li = f.L + (long long)i * p;
     double s = lds[sidx<W>(i, lane)];
@@ -82,6 +110,7 @@ __device__ __forceinline__ void substitute(double* lds, int lane, int m, const F
   }
 #pragma unroll
   for (int k = 0; k < p; ++k) h[k] = 0.0;
+#pragma unroll 8
   for (int i = m - 1; i >= 0; --i) {
     const double* Ui = f.U + (long long)i * p;
     double s = lds[sidx<W>(i, lane)];
@@ -96,8 +125,10 @@ __device__ __forceinline__ void substitute(double* lds, int lane, int m, const F
 }
 
 template <int W>
-__global__ __launch_bounds__(W) void sweep_kernel(const SweepJob* __restrict__ jobs, int njobs, int total_tiles) {
+__global__ __launch_bounds__(W) void sweep_kernel(const LaunchHdr* __restrict__ hdr) {
   extern __shared__ double lds[];
+  const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
+  const SweepJob* __restrict__ jobs = hdr_jobs<SweepJob>(hdr);
   const int lane = threadIdx.x;
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const int jb = find_job_sweep(jobs, njobs, tile);
@@ -110,16 +141,36 @@ __global__ __launch_bounds__(W) void sweep_kernel(const SweepJob* __restrict__ j
     const bool active = lane < nl;
     long long base = 0, stride = 0;
     if (J.dir == 0) {
-      // x-lines: the nl lines of the tile are one contiguous block of nl*m
+      // x-lines: the nl lines of the tile are one contiguous block of nl*m;
+      // kChunk loads per lane are issued before any is consumed
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
-      for (int fidx = lane; fidx < tot; fidx += W) {
-        int l = fidx / m, i = fidx - l * m;
-        lds[sidx<W>(i, l)] = J.scale * J.in[gb + fidx];
+      for (int f0 = 0; f0 < tot; f0 += kChunk * W) {
+        double r[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+          int fidx = f0 + k * W + lane;
+          r[k] = fidx < tot ? J.in[gb + fidx] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+          int fidx = f0 + k * W + lane;
+          if (fidx < tot) {
+            int l = fidx / m, i = fidx - l * m;
+            lds[sidx<W>(i, l)] = J.scale * r[k];
+          }
+        }
       }
     } else if (active) {
       line_geom(J, line, base, stride);
-      for (int i = 0; i < m; ++i) lds[sidx<W>(i, lane)] = J.scale * J.in[base + i * stride];
+      for (int i0 = 0; i0 < m; i0 += kChunk) {
+        double r[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) r[k] = (i0 + k < m) ? J.in[base + (i0 + k) * stride] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+          if (i0 + k < m) lds[sidx<W>(i0 + k, lane)] = J.scale * r[k];
+      }
     }
     __syncthreads();
     if (active) {
@@ -133,12 +184,33 @@ __global__ __launch_bounds__(W) void sweep_kernel(const SweepJob* __restrict__ j
     if (J.dir == 0) {
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
-      for (int fidx = lane; fidx < tot; fidx += W) {
-        int l = fidx / m, i = fidx - l * m;
-        epilogue(J, gb + fidx, lds[sidx<W>(i, l)]);
+      for (int f0 = 0; f0 < tot; f0 += kEpi * W) {
+        long long g[kEpi];
+        double x[kEpi];
+        bool ok[kEpi];
+#pragma unroll
+        for (int k = 0; k < kEpi; ++k) {
+          int fidx = f0 + k * W + lane;
+          ok[k] = fidx < tot;
+          int l = ok[k] ? fidx / m : 0, i = ok[k] ? fidx - l * m : 0;
+          g[k] = gb + fidx;
+          x[k] = ok[k] ? lds[sidx<W>(i, l)] : 0.0;
+        }
+        epilogue_batch(J, g, x, ok);
       }
     } else if (active) {
-      for (int i = 0; i < m; ++i) epilogue(J, base + i * stride, lds[sidx<W>(i, lane)]);
+      for (int i0 = 0; i0 < m; i0 += kEpi) {
+        long long g[kEpi];
+        double x[kEpi];
+        bool ok[kEpi];
+#pragma unroll
+        for (int k = 0; k < kEpi; ++k) {
+          ok[k] = i0 + k < m;
+          g[k] = base + (long long)(i0 + k) * stride;
+          x[k] = ok[k] ? lds[sidx<W>(i0 + k, lane)] : 0.0;
+        }
+        epilogue_batch(J, g, x, ok);
+      }
     }
     if (t == 0 && lane == 0 && J.counter != nullptr) *J.counter += 1ull;
     __syncthreads();
@@ -152,19 +224,16 @@ int sweep_width_for(int max_m) {
   return 16;
 }
 
-hipError_t launch_sweeps(const SweepJob* d_jobs, int njobs, int total_tiles, int max_m, int grid_cap,
-                         hipStream_t s) {
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int max_m, hipStream_t s) {
   const int W = sweep_width_for(max_m);
   size_t lds = (size_t)W * max_m * sizeof(double);
-  int grid = total_tiles;
-  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
   if (grid <= 0) return hipSuccess;
   if (W == 64) {
-    hipLaunchKernelGGL(sweep_kernel<64>, dim3(grid), dim3(64), lds, s, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL(sweep_kernel<64>, dim3(grid), dim3(64), lds, s, d_hdr);
   } else if (W == 32) {
-    hipLaunchKernelGGL(sweep_kernel<32>, dim3(grid), dim3(32), lds, s, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL(sweep_kernel<32>, dim3(grid), dim3(32), lds, s, d_hdr);
   } else {
-    hipLaunchKernelGGL(sweep_kernel<16>, dim3(grid), dim3(16), lds, s, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL(sweep_kernel<16>, dim3(grid), dim3(16), lds, s, d_hdr);
   }
   return hipGetLastError();
 }

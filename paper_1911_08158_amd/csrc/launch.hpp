@@ -5,21 +5,22 @@
 
 namespace ads {
 
+// Launchers take the device header of a job table (LaunchHdr followed by
+// the jobs) and a grid size (all tiles, or a persistent grid that loops).
 int sweep_width_for(int max_m);
-hipError_t launch_sweeps(const SweepJob* d_jobs, int njobs, int total_tiles, int max_m, int grid_cap,
-                         hipStream_t s);
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int max_m, hipStream_t s);
 hipError_t sweep_set_attributes();
 
+int rhs_num_variants(int p);
 int rhs_tile_x(int p);
-int rhs_tile_y(int p);
-hipError_t launch_rhs_pwave(int p, const RhsJob* d_jobs, int njobs, int total_tiles, int grid_cap,
-                            hipStream_t s);
+int rhs_tile_y(int p, int var);
+int rhs_blocks_per_cu(int p, int mixed, int var);
+hipError_t launch_rhs_pwave(int p, int mixed, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int rhs_el_tile_x(int p);
 int rhs_el_tile_y(int p);
-hipError_t launch_rhs_elastic(int p, const RhsJob* d_jobs, int njobs, int total_tiles, int grid_cap,
-                              hipStream_t s);
+hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 
-hipError_t launch_kron(const KronJob* d_jobs, int njobs, int total_tiles, int grid_cap, hipStream_t s);
+hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int kron_tile_points();
 
 hipError_t launch_full_to_free(const double* full, double* fr, const int n[3], const int nf[3],

@@ -1,0 +1,53 @@
+"""Mixed-precision right-hand side (FP32 contractions, FP64 predictor,
+z-accumulation, assembly, factors, sweeps and update) against the FP64
+oracle: relative L2 error of u reported per step; target <= 1e-6 after 100
+steps on C3 (128^3 elements, p = 2)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from runners import gpu_sim, oracle_pwave, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
+                                 W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
+                         ids=["p2", "p3"])
+def test_mixed_small_meshes(cfg):
+    _cuda()
+    pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0))
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, _, _ = sim.get_state()
+        e = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
+        assert e <= 1e-6, (k, e)
+    sim.close()
+
+
+def test_mixed_c3_error_per_step():
+    """C3, 100 steps: the error against the FP64 oracle at every 10th step."""
+    _cuda()
+    cfg = W.C3
+    pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0))
+    sim.factor()
+    errs = []
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        if k % 10 == 0 or k == 1:
+            u, v, a = sim.get_state()
+            eu = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
+            ev = rel_l2(v.cpu().numpy(), pw.to_full(hist[k][1]))
+            errs.append((k, eu, ev))
+            print(f"C3 mixed step {k}: rel L2 u {eu:.3e} v {ev:.3e}", flush=True)
+    sim.close()
+    assert errs[-1][1] <= 1e-6, errs

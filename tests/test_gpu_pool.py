@@ -1,0 +1,128 @@
+"""Batched pool (serving form): every result is bitwise the same alone and in
+the mix, with simulations of different problems, meshes, degrees and
+precisions joining and leaving the batch; graph replay equals direct
+launches; admission is by workspace bytes."""
+import numpy as np
+import pytest
+
+import workloads as W
+from runners import gpu_sim, oracle_pwave, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+MIX = [
+    W.C1.with_(nelem=(20, 17, 23), tau=0.01),
+    W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01),
+    W.C1.with_(nelem=(24, 16, 20), tau=0.005, precision="mixed_fp32"),
+    W.C4.with_(nelem=(9, 8, 10), tau=0.01),
+    W.C4.with_(nelem=(6, 7, 5), p=3, q=4, tau=0.02, lam=2.0, mu=0.5),
+    W.C2.with_(nelem=(16, 18, 14), steps=100),           # P-wave p=3 with a point source
+]
+
+
+def _setup(sim, cfg):
+    import torch
+    xs = [sim.quad_points(d) for d in range(3)]
+    u0 = sim.project(torch.from_numpy(np.ascontiguousarray(W.initial_values(cfg, *xs))).to("cuda"))
+    sim.set_state(u0, None, None, 0)
+    if cfg.load == "ricker_point":
+        sim.set_point_load(W.source_point(cfg.seed), W.load_amplitudes(cfg))
+    sim.factor()
+
+
+def _alone(cfg, nsteps):
+    sim, _ = gpu_sim(cfg, precision=cfg.precision)
+    sim.factor()
+    sim.step(nsteps)
+    out = [t.cpu().numpy() for t in sim.get_state() if t is not None]
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_alone_equals_mix_with_staggered_joins(use_graph):
+    _cuda()
+    from paper_1911_08158_amd import Pool
+    nsteps = 6
+    ref = [_alone(c, nsteps) for c in MIX]
+    pool = Pool(512 << 20, max_slots=16, use_graph=use_graph)
+    sims = []
+    done = {}
+    # first half joins at step 0, second half after two pool steps
+    for c in MIX[:3]:
+        s = pool.admit(c)
+        _setup(s, c)
+        pool.activate(s)
+        sims.append((s, c, 0))
+    pool.step(2)
+    for c in MIX[3:]:
+        s = pool.admit(c)
+        _setup(s, c)
+        pool.activate(s)
+        sims.append((s, c, 2))
+    for k in range(2, 2 + nsteps):
+        pool.step(1)
+        for s, c, t0 in sims:
+            if s.slot in done:
+                continue
+            if k + 1 - t0 == nsteps:
+                done[s.slot] = [t.cpu().numpy() for t in s.get_state() if t is not None]
+                assert s.step_index() == nsteps
+                pool.retire(s)
+    assert len(done) == len(MIX)
+    for (s, c, _), r in zip(sims, ref):
+        out = done[s.slot]
+        for x, y in zip(out, r):
+            assert np.array_equal(x, y), c
+    times = pool.step_times()
+    assert len(times) == 2 + nsteps and np.all(times > 0)
+    pool.close()
+
+
+def test_pool_matches_oracle_and_mixed_error():
+    """A pooled FP64 run matches the oracle; a pooled mixed run stays within
+    1e-6 of it."""
+    _cuda()
+    from paper_1911_08158_amd import Pool
+    cfg = W.C1.with_(nelem=(18, 20, 16), tau=0.01, steps=10)
+    pw, u0, (ur, vr, ar) = oracle_pwave(cfg, cfg.steps)
+    pool = Pool(256 << 20, max_slots=4)
+    sims = []
+    for prec in ("fp64", "mixed_fp32"):
+        s = pool.admit(cfg, precision=prec)
+        import torch
+        s.set_state(torch.from_numpy(pw.to_full(u0)).cuda(), None, None, 0)
+        s.factor()
+        pool.activate(s)
+        sims.append(s)
+    pool.step(cfg.steps)
+    e64 = rel_l2(sims[0].get_state()[0].cpu().numpy(), pw.to_full(ur))
+    e32 = rel_l2(sims[1].get_state()[0].cpu().numpy(), pw.to_full(ur))
+    assert e64 <= 1e-12 and e32 <= 1e-6, (e64, e32)
+    pool.close()
+
+
+def test_admission_by_memory():
+    _cuda()
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.binding import Params, workspace_bytes
+    cfg = W.C1.with_(nelem=(48, 48, 48))
+    need = workspace_bytes(Params.of(cfg))
+    assert need > (4 << 20)
+    # job tables (< 1 MiB for 8 slots) + room for 3.5 simulations
+    pool = Pool((1 << 20) + int(3.5 * need), max_slots=8)
+    got = [pool.admit(cfg) for _ in range(4)]
+    assert all(g is not None for g in got[:3]) and got[3] is None
+    info = pool.info()
+    assert info["used_bytes"] >= 3 * need
+    pool.retire(got[1])
+    again = pool.admit(cfg)
+    assert again is not None and again.slot == got[1].slot
+    pool.close()

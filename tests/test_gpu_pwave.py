@@ -140,6 +140,38 @@ def test_checkpoint_resume_bitwise():
     sim2.close()
 
 
+@pytest.mark.parametrize("p", [2, 3])
+def test_rhs_tile_variants_bitwise_and_tuner(p, monkeypatch):
+    """Every right-hand-side tile variant (and z-chunking) computes each output
+    with the same arithmetic, so results are bitwise identical; the autotuner
+    picks one of them."""
+    _cuda()
+    cfg = W.C1.with_(nelem=(37, 41, 35), p=p, q=p + 1, tau=0.01, steps=3)
+    pw, u0, _ = oracle_pwave(cfg, 0)
+    outs = []
+    for var, tz in ((0, 0), (1, 0), (2, 0), (0, 5)):
+        monkeypatch.setenv("ADS_RHS_VAR", str(var))
+        monkeypatch.setenv("ADS_RHS_TZ", str(tz))
+        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+        sim.factor()
+        sim.step(cfg.steps)
+        outs.append([t.cpu().numpy() for t in sim.get_state()])
+        sim.close()
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+    monkeypatch.delenv("ADS_RHS_VAR")
+    monkeypatch.delenv("ADS_RHS_TZ")
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+    sim.factor()
+    chosen, ms = sim.tune()
+    assert chosen in (0, 1, 2)
+    sim.step(cfg.steps)
+    for x, y in zip([t.cpu().numpy() for t in sim.get_state()], outs[0]):
+        assert np.array_equal(x, y)
+    sim.close()
+
+
 def test_step_before_factor_is_state_error():
     _cuda()
     from paper_1911_08158_amd import AdsError, Sim

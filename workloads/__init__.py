@@ -179,6 +179,28 @@ def initial_values(cfg: SimConfig, xs, ys, zs) -> np.ndarray:
     raise ValueError(cfg.init)
 
 
+def greville_abscissae(E: int, p: int) -> np.ndarray:
+    """Averages of p consecutive interior knots of the open uniform knot
+    vector with E elements (where a spline coefficient 'sits')."""
+    t = np.concatenate([np.zeros(p + 1), np.arange(1, E) / E, np.ones(p + 1)])
+    return np.array([t[i + 1:i + p + 1].mean() for i in range(E + p)])
+
+
+def initial_coefficients(cfg: SimConfig) -> np.ndarray:
+    """Cheap initial coefficients for the serving mix: the initial function
+    sampled at the Greville abscissae (boundary coefficients set to 0, the
+    zero-Dirichlet value).  Full layout [z, y, x] or [3, z, y, x]."""
+    xs, ys, zs = (greville_abscissae(cfg.nelem[d], cfg.p) for d in range(3))
+    c = np.array(initial_values(cfg, xs, ys, zs))
+    c[..., 0, :, :] = 0
+    c[..., -1, :, :] = 0
+    c[..., :, 0, :] = 0
+    c[..., :, -1, :] = 0
+    c[..., :, :, 0] = 0
+    c[..., :, :, -1] = 0
+    return np.ascontiguousarray(c)
+
+
 # ---------------------------------------------------------------------------
 # loads
 # ---------------------------------------------------------------------------
