@@ -145,8 +145,7 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
     for s in sims:
         s.check_finite()
     pool.close()
-    ent = [(k, ms) for (k, p, mixed, ms) in prof if ms > 0.004]
-    # merge the three per-direction sweep kinds of the P-wave step
+    ent = [(k, ms) for (k, p, mixed, ms) in prof if ms > 0]     # launched classes only
     return {
         "dof_steps_per_s": cfg.dofs() * batch * steps / wall,
         "ms_per_step": wall / steps * 1e3,
@@ -186,6 +185,19 @@ def cpu_baseline(cfg, seconds):
                       f"(NumPy FP64 oracle; setup, projection and start untimed)"}
 
 
+def calibration_copy():
+    """Counter calibration for the profiled single-form runs: one
+    device-to-device copy of exactly 512 MiB (larger than the 256 MB
+    Infinity Cache).  The FETCH_SIZE / WRITE_SIZE it reads are the per-byte
+    scale of those counters."""
+    import torch
+    x = torch.empty(64 << 20, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +206,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["plain", "batched"], default=None,
+                    help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the hot path is measured on one "
@@ -202,6 +216,16 @@ def main():
 
     import workloads as W
     cfg = W.C3
+    if args.only is not None:
+        calibration_copy()
+    if args.only == "plain":
+        print(json.dumps({"form": "plain_fp64", **measure_plain(cfg.with_(precision="fp64"), args.steps,
+                                                                args.warmup)}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps({"form": "batched_mixed", **measure_batched(cfg.with_(precision="mixed_fp32"), args.batch,
+                                                                     args.steps, args.warmup)}), flush=True)
+        return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
     rhs = next(k for k in batched["kernels"] if k["kernel"] == "rhs")

@@ -218,7 +218,8 @@ ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int
  * following ads_pool_step calls enqueue the launches directly (no graph)
  * with HIP events around each; ads_pool_profile_read synchronizes and
  * returns the mean ms per launch position of one pool step over the
- * recorded steps, its kind (0 = P-wave right-hand side, 5 = elasticity
+ * recorded steps (-1 for a class with no simulation in the batch, which is
+ * not launched), its kind (0 = P-wave right-hand side, 5 = elasticity
  * right-hand side, 1/2/3 = sweeps, 4 = coupling apply), degree and
  * mixed flag (host arrays of cap entries), and resets the record. */
 ads_status ads_pool_profile(ads_pool* pool, int32_t enable);

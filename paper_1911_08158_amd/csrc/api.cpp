@@ -133,6 +133,7 @@ struct ads_sim {
   bool factored = false, need_start = true, have_load = false;
   int namp = 0;
   int tz = 0;
+  int ncu = 0;          // compute units of the device (tiling of the right-hand side)
   int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
   bool mixed = false;   // FP32 contractions in the right-hand side
   // kernel timing (measurement support)
@@ -326,23 +327,64 @@ void fill_tables(const ads_sim* s, RhsJob& J) {
   }
 }
 
-// z-chunking of the RHS: enough workgroups to cover the chip at least twice.
-void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY) {
-  J.tiles[0] = (s->nf[0] + TX - 1) / TX;
-  J.tiles[1] = (s->nf[1] + TY - 1) / TY;
-  int xy = J.tiles[0] * J.tiles[1];
-  int want = std::max(1, (1024 + xy - 1) / xy);
-  int minTZ = 8;
-  int chunks = std::min(want, std::max(1, s->nf[2] / minTZ));
-  int TZ = (s->nf[2] + chunks - 1) / chunks;
-  if (s->tz > 0) TZ = s->tz;
+// Number of z-chunks k for right-hand-side jobs sharing one launch: a tile
+// of job j marches over ceil(nfz_j / k) + p element layers, and `resident`
+// workgroups take the sum_j xy_j * k tiles in rounds, so the launch lasts
+// about rounds(k) * max_j (ceil(nfz_j / k) + p) layer-steps; k minimizes it
+// (the fewest chunks among equals, i.e. the least z-halo work).
+int best_zchunks(const std::vector<std::pair<long long, int>>& xy_nfz, int p, long long resident) {
+  long long xy = 0;
+  int nfz = 1;
+  for (const auto& e : xy_nfz) {
+    xy += e.first;
+    nfz = std::max(nfz, e.second);
+  }
+  resident = std::max(1ll, resident);
+  int best = 1;
+  long long best_cost = -1;
+  for (int k = 1; k <= nfz; ++k) {
+    int layers = 0;
+    for (const auto& e : xy_nfz) layers = std::max(layers, (e.second + k - 1) / k + p);
+    const long long rounds = (xy * k + resident - 1) / resident;
+    const long long cost = rounds * layers;
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = k;
+    }
+  }
+  return best;
+}
+
+void set_zchunks(RhsJob& J, int nfz, int k) {
+  const int TZ = (nfz + k - 1) / k;
   J.TZ = TZ;
-  J.tiles[2] = (s->nf[2] + TZ - 1) / TZ;
-  J.tile0 = 0;
+  J.tiles[2] = (nfz + TZ - 1) / TZ;
   J.ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
 }
 
-RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift) {
+// Tiling of one right-hand-side job.  resident > 0: z-chunks chosen for that
+// many resident workgroups; otherwise enough tiles to cover the chip twice.
+void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident = 0) {
+  J.tiles[0] = (s->nf[0] + TX - 1) / TX;
+  J.tiles[1] = (s->nf[1] + TY - 1) / TY;
+  const int xy = J.tiles[0] * J.tiles[1];
+  J.tile0 = 0;
+  if (s->tz > 0) {   // fixed z-tile depth
+    J.TZ = s->tz;
+    J.tiles[2] = (s->nf[2] + s->tz - 1) / s->tz;
+    J.ntiles = xy * J.tiles[2];
+    return;
+  }
+  if (resident > 0) {
+    set_zchunks(J, s->nf[2], best_zchunks({{xy, s->nf[2]}}, s->p, resident));
+    return;
+  }
+  const int want = std::max(1, (1024 + xy - 1) / xy);
+  const int chunks = std::min(want, std::max(1, s->nf[2] / 8));
+  set_zchunks(J, s->nf[2], chunks);
+}
+
+RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift, int mixed, int var) {
   RhsJob J{};
   J.u = s->u;
   J.v = cv != 0.0 ? s->v : nullptr;
@@ -358,7 +400,8 @@ RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_
   J.counter = s->counter;
   J.rscale = 1.0;
   fill_tables(s, J);
-  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p, s->rhs_var));
+  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p, mixed, var),
+            (long long)rhs_blocks_per_cu(s->p, mixed, var) * s->ncu);
   return J;
 }
 
@@ -532,7 +575,7 @@ ads_status build_launches(ads_sim* s) {
   const double tau = s->prm.tau, eta = 0.25 * tau * tau;
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
-    RhsJob rj = rhs_pwave_job(s, 1.0, tau, eta, 1);
+    RhsJob rj = rhs_pwave_job(s, 1.0, tau, eta, 1, s->mixed ? 1 : 0, s->rhs_var);
     const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
     if (!d) return fail(ADS_ENOMEM, err);
     s->step_l.push_back(
@@ -547,11 +590,11 @@ ads_status build_launches(ads_sim* s) {
     z.counter = s->counter;
     if (!add_ads_solve(s, s->step_l, s->fS, s->R, s->R, nullptr, 1.0, z, err)) return fail(ADS_ENOMEM, err);
     // start: u''_0 = G^{-1}(F_0 - K u_0)
-    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0);
+    // the start is computed in FP64 (tile variant 0) in every precision mode
+    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, 0);
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    // the start is computed in FP64 in every precision mode
-    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, s->rhs_var, 0, as_bytes(r0)});
+    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, 0, 0, as_bytes(r0)});
     if (!add_ads_solve(s, s->start_l, s->fS, s->R, s->R, s->a, 1.0, plain_epi(), err))
       return fail(ADS_ENOMEM, err);
   } else {
@@ -624,10 +667,14 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
     HIPCHECK(sweep_set_attributes());
     attrs = true;
   }
+  int dev = 0, ncu = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   ads_sim* s = new ads_sim();
   s->prm = *prm;
   s->stream = (hipStream_t)stream;
   geometry(s);
+  s->ncu = ncu;
   if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
   if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(2, std::atoi(e)));
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
@@ -1004,6 +1051,8 @@ struct ads_pool {
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;
+  std::vector<char> nonempty;      // launch classes with jobs in the current batch
+  std::vector<char> captured;      // ... when the graph was captured
   ~ads_pool() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1031,7 +1080,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
     if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, 8 * ncu, sizeof(KronJob));
-    else add(Launch::SWEEP, 0, 0, 0, k, 2 * ncu, sizeof(SweepJob));
+    else add(Launch::SWEEP, 0, 0, 0, k, sweep_blocks_per_cu(kPoolMaxM) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
 }
@@ -1039,9 +1088,11 @@ void pool_build_seq(ads_pool* P, int ncu) {
 // Gathers the jobs of every active simulation into the merged tables.
 ads_status pool_rebuild(ads_pool* P) {
   std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
-  for (const PoolLaunch& L : P->seq) {
-    std::vector<char> jobs;
-    int n = 0, total = 0;
+  P->nonempty.assign(P->seq.size(), 0);
+  for (size_t li = 0; li < P->seq.size(); ++li) {
+    const PoolLaunch& L = P->seq[li];
+    std::vector<std::vector<char>> sel;
+    bool fixed_tz = false;
     for (ads_pool::Slot& sl : P->slots) {
       if (!sl.active) continue;
       const std::vector<Launch>& st = sl.sim->step_l;
@@ -1050,7 +1101,26 @@ ads_status pool_rebuild(ads_pool* P) {
       if (l.kind != L.kind) continue;
       if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && l.var != L.var)))
         continue;
-      std::vector<char> j = l.host_jobs;
+      sel.push_back(l.host_jobs);
+      fixed_tz = fixed_tz || sl.sim->tz > 0;
+    }
+    // P-wave right-hand sides: z-chunks chosen for the whole batch on the
+    // persistent grid of this launch
+    if (L.kind == Launch::RHS_P && !sel.empty() && !fixed_tz) {
+      std::vector<std::pair<long long, int>> xy_nfz;
+      for (const auto& j : sel) {
+        const RhsJob* r = (const RhsJob*)j.data();
+        xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nf[2]});
+      }
+      const int k = best_zchunks(xy_nfz, L.p, L.grid);
+      for (auto& j : sel) {
+        RhsJob* r = (RhsJob*)j.data();
+        set_zchunks(*r, r->nf[2], k);
+      }
+    }
+    std::vector<char> jobs;
+    int n = 0, total = 0;
+    for (std::vector<char>& j : sel) {
       // every job struct starts its tiling fields the same way: patch tile0
       if (L.kind == Launch::SWEEP) {
         SweepJob* s = (SweepJob*)j.data();
@@ -1071,6 +1141,7 @@ ads_status pool_rebuild(ads_pool* P) {
     LaunchHdr h{};
     h.njobs = n;
     h.total_tiles = total;
+    P->nonempty[li] = n > 0;
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
@@ -1084,6 +1155,10 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
   if (evs) HIPCHECK(hipEventRecord(evs[0], P->stream));
   for (size_t li = 0; li < P->seq.size(); ++li) {
     const PoolLaunch& L = P->seq[li];
+    if (!P->nonempty[li]) {   // no simulation of this class in the batch
+      if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
+      continue;
+    }
     const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
     hipError_t e = hipSuccess;
     switch (L.kind) {
@@ -1201,7 +1276,17 @@ ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
   if (!P || nsteps < 0) return fail(ADS_EINVAL, "bad argument");
   ads_status st;
   if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
+  // the graph holds the non-empty launch classes; re-capture only when that
+  // set changes (tables alone change between replays without re-capture)
+  if (P->exec && P->captured != P->nonempty) {
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    (void)hipGraphExecDestroy(P->exec);
+    (void)hipGraphDestroy(P->graph);
+    P->exec = nullptr;
+    P->graph = nullptr;
+  }
   if (P->use_graph && !P->exec) {
+    P->captured = P->nonempty;
     HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
     st = pool_enqueue(P);
     hipGraph_t g = nullptr;
@@ -1266,7 +1351,7 @@ ads_status ads_pool_profile_read(ads_pool* P, double* ms, int32_t* kind, int32_t
       sum += t;
     }
     const PoolLaunch& l = P->seq[i];
-    if (ms) ms[i] = P->prof_steps ? sum / P->prof_steps : 0.0;
+    if (ms) ms[i] = (i < P->nonempty.size() && !P->nonempty[i]) ? -1.0 : (P->prof_steps ? sum / P->prof_steps : 0.0);
     if (kind) {
       int kd = l.kind == Launch::RHS_P ? 0 : l.kind == Launch::RHS_E ? 5 : l.kind == Launch::KRON ? 4 : 1;
       if (l.kind == Launch::SWEEP) kd = 1 + ((l.stage - 1) % 4) % 3;   // x, y, z of each solve

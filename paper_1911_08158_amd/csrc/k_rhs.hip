@@ -10,18 +10,25 @@
 // Tiling on gfx950 (owner computes, no atomics, deterministic):
 //   * a workgroup owns TX x TY coefficient columns and a z-range of TZ
 //     coefficients, and marches over the element layers touching the range;
-//   * per element layer the predictor w is formed once (FP64) into an LDS
-//     ring of p+1 coefficient layers (halo p on each side in x and y);
-//   * per z Gauss point: (S12) z- and y-contraction from the ring to the
-//     y Gauss rows of the tile's y-elements (values, y- and z-derivatives),
-//     (S34) x-forward, quadrature weight and x-backward with one lane per
-//     x-element (16-lane DPP rows, one Gauss row each) and a row-shift
-//     add that assembles each coefficient from its p+1 elements, (S5)
-//     y-backward and z-backward into FP64 accumulators of the owned column
-//     (p+1 z-layers in flight);
-//   * the Gauss-row buffer is double-buffered: two barriers per z Gauss
-//     point;
+//   * the predictor w is formed once per coefficient (FP64) into an LDS ring
+//     of p+1 coefficient layers (halo p on each side in x and y), the next
+//     layer's global loads in flight while the current one is processed;
+//   * per element layer (Z): the z-contraction of every ring column at all q
+//     z Gauss points (value and z-derivative), once per column;
+//   * per z Gauss point: (Y) y-contraction to the y Gauss rows of the tile's
+//     y-elements (value, y- and z-derivative); (X) x-forward, x-weights and
+//     x-backward with one lane per x-element (16-lane DPP rows, one Gauss row
+//     each) and a row-shift Horner sum that assembles each coefficient from
+//     its p+1 elements; (B) y-backward (y-weights folded into per-thread
+//     tables) and z-backward (z-weights folded into the z tables) into FP64
+//     accumulators of the owned column (p+1 z-layers in flight);
+//   * the Gauss-row buffer is double-buffered: two barriers per z Gauss point
+//     and one per element layer;
 //   * a z-layer is written once its last contributing element is done.
+// Derivative tables satisfy sum_a D_a = 0 on every element (partition of
+// unity), so the forward derivative contractions use differences against
+// the first coefficient and the backward x-derivative slot 0 is minus the
+// sum of the others.
 // T is the contraction type: double (FP64 mode) or float (mixed mode: FP32
 // contractions, FP64 predictor, FP64 z-accumulation and assembly).
 #include "common.hpp"
@@ -37,18 +44,34 @@ __device__ __forceinline__ int find_job_rhs(const RhsJob* jobs, int njobs, int t
   return lo;
 }
 
-// Row shift within 16-lane DPP rows: lane i receives lane i-K (0 if none).
-template <int K>
-__device__ __forceinline__ double row_shr(double x) {
+// Row shift within 16-lane DPP rows: lane i receives lane i-1; lane 0 of
+// each row reads 0 (bound_ctrl), so no "old" value has to be set up.
+__device__ __forceinline__ double row_shr1(double x) {
   long long b = __double_as_longlong(x);
   int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x110 + K, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x110 + K, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int K>
-__device__ __forceinline__ float row_shr(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + K, 0xF, 0xF, false));
+__device__ __forceinline__ float row_shr1(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xF, 0xF, true));
+}
+
+// sum_a o[a] of lane i-a, as a Horner chain of one-lane shifts
+template <int P, typename T>
+__device__ __forceinline__ T horner_shift(const T (&o)[P]) {
+  T t = o[P - 1];
+#pragma unroll
+  for (int a = P - 2; a >= 0; --a) t = o[a] + row_shr1(t);
+  return t;
+}
+
+// Completes this wave's LDS writes before its lanes read each other's
+// values (LDS operations of one wave execute in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T, int P, int Q, int TY_, int NT_>
@@ -59,45 +82,86 @@ struct RhsGeom {
   static constexpr int TY = TY_;        // owned y-coefficients
   static constexpr int TXH = TX + 2 * p;
   static constexpr int TYH = TY + 2 * p;
+  static constexpr int NC = TYH * TXH;  // coefficient positions of one layer
   static constexpr int EY = TY + p;     // y-elements touching the owned columns
   static constexpr int R = EY * Q;      // y Gauss rows
   static constexpr int NT = NT_;
-  static constexpr int NRG = NT / G;    // Gauss-row groups
-  static constexpr size_t lds_elems = (size_t)P * TYH * TXH + 2ull * 3 * R * TXH + 2ull * EY * Q * P + EY * Q;
+  static constexpr int NW = NT / 64;    // waves
+  static constexpr int WE = 4;          // y-elements per wave
+  static constexpr int WR = WE + p;     // coefficient rows a wave's y-elements touch
+  static constexpr int NZW = WR * TXH;  // z-stage items of one wave
+  static constexpr int NZ = (NZW + 63) / 64;
+  static constexpr int NF = (NC + NT - 1) / NT;   // predictor loads per thread
+  // Gauss-row buffer: row r, column x at (r & 1) * H + (r >> 1) * TXH + x;
+  // H = 16 (mod 32) puts the two rows read by one half-wave on disjoint
+  // LDS banks
+  static constexpr int HR = (R / 2) * TXH;
+  static constexpr int H = HR + ((16 - HR % 32) + 32) % 32;
+  static constexpr int SBC = 2 * H;     // one component plane
+  static constexpr int TS = 2 * Q * P + (sizeof(T) == 4 ? (4 - (2 * Q * P) % 4) % 4 : 0);
+  // LDS: ring [P][NC], zc [NW][Q][2][NZW], sb [2][3][SBC], ty [EY][TS]
+  static constexpr size_t lds_elems =
+      (size_t)P * NC + (size_t)NW * Q * 2 * NZW + 6ull * SBC + (size_t)EY * TS;
   static constexpr size_t lds_bytes = lds_elems * sizeof(T);
+  static_assert(EY == WE * NW, "every wave owns WE y-elements");
+  static_assert((WE * Q) % 4 == 0, "a wave's Gauss rows split over its four row groups");
+  static_assert(R % 2 == 0, "rows come in even/odd pairs");
+  static_assert(TX * TY <= NT, "every owned column needs a thread");
+  static_assert(lds_bytes <= 160 * 1024, "LDS budget of one workgroup");
 };
 
-template <int K, int P, typename T>
-__device__ __forceinline__ T shift_sum(const T (&o)[P]) {
-  if constexpr (K >= P) {
-    return T(0);
-  } else {
-    return row_shr<K>(o[K]) + shift_sum<K + 1, P, T>(o);
-  }
-}
-
+// FP32: at least four waves per SIMD (at most 128 VGPRs)
 template <typename T, int P, int Q, int TY_, int NT_>
-__global__ __launch_bounds__(NT_) void rhs_pwave_kernel(const LaunchHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_pwave_kernel(
+    const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
   using Gm = RhsGeom<T, P, Q, TY_, NT_>;
-  constexpr int p = Gm::p, TX = Gm::TX, TY = Gm::TY, TXH = Gm::TXH, TYH = Gm::TYH, EY = Gm::EY,
-                R = Gm::R, NT = Gm::NT, NRG = Gm::NRG;
+  constexpr int p = Gm::p, TX = Gm::TX, TY = Gm::TY, TXH = Gm::TXH, TYH = Gm::TYH, NC = Gm::NC, EY = Gm::EY,
+                NT = Gm::NT, NW = Gm::NW, WE = Gm::WE, NZW = Gm::NZW, NZ = Gm::NZ,
+                NF = Gm::NF, H = Gm::H, SBC = Gm::SBC, TS = Gm::TS;
+  constexpr int NRW = WE * Q / 4;       // Gauss rows per row group
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* ring = reinterpret_cast<T*>(smem_raw);            // [P][TYH][TXH]
-  T* Sb = ring + P * TYH * TXH;                         // [2][3][R][TXH]
-  T* tyN = Sb + 2 * 3 * R * TXH;                        // [EY][Q][P]
-  T* tyD = tyN + EY * Q * P;                            // [EY][Q][P]
-  T* tyW = tyD + EY * Q * P;                            // [EY][Q]
-  auto RING = [&](int s, int y, int x) -> T& { return ring[(s * TYH + y) * TXH + x]; };
-  auto SB = [&](int b, int c, int r, int x) -> T& { return Sb[((b * 3 + c) * R + r) * TXH + x]; };
+  T* ring = reinterpret_cast<T*>(smem_raw);   // [P][NC]
+  T* zcall = ring + P * NC;                    // [NW][Q][2][NZW]
+  T* sb = zcall + NW * Q * 2 * NZW;            // [2][3][SBC]
+  T* tyl = sb + 6 * SBC;                       // [EY][TS]: N[Q][P] then D[Q][P]
+  auto rowpos = [](int r) { return (r & 1) * H + (r >> 1) * TXH; };
+  // position of row r0 + k from that of row r0 (par = r0 & 1)
+  auto rowstep = [](int pos0, int par, int k) {
+    const int even = (k & 1) * H + (k >> 1) * TXH;
+    const int odd = (k & 1) ? ((k + 1) >> 1) * TXH - H : (k >> 1) * TXH;
+    return pos0 + (par ? odd : even);
+  };
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int j = lane & 15;                 // x-element slot within the Gauss row group
-  const int rg = tid >> 4;                 // Gauss row group
+  const int lane = tid & 63, wv = tid >> 6;
+  const int j = lane & 15;                // x-element slot within the Gauss row group
+  const int grp = lane >> 4;              // row group within the wave
   const bool own = tid < TX * TY;
   const int cxo = tid % TX, cyo = tid / TX;
+  T* zc = zcall + wv * (Q * 2 * NZW);     // this wave's z-contracted rows
+  // y-stage, full pass: lane = (wave y-element el, column cxl < 16), all
+  // Gauss points; extra pass: the p columns 16.. as (el, column, gy) items
+  constexpr int NYX = p * WE * Q;
+  static_assert(WE * 16 == 64 && NYX <= 64, "y-stage lane mapping");
+  const int yel = lane >> 4;
+  const int yr0 = (wv * WE + yel) * Q;
+  const int ysb = rowpos(yr0) + j, ypar = yr0 & 1, yty = (wv * WE + yel) * TS, yzc = yel * TXH + j;
+  const bool xok = lane < NYX;
+  int xsb, xty, xzc;
+  {
+    const int gy = lane % Q, rest = lane / Q;
+    const int el = rest / p, cx = 16 + rest % p;
+    xsb = rowpos((wv * WE + el) * Q + gy) + cx;
+    xty = (wv * WE + el) * TS + gy * P;
+    xzc = el * TXH + cx;
+  }
+  // x-stage rows of this row group: wave rows 4i + grp (same parity as
+  // grp, so row i sits 2i rows of TXH further on)
+  const int xrow0 = rowpos(wv * WE * Q + grp);
+  // b-stage rows of the owned column: cyo*Q + (p - b)*Q + gy
+  const int brow0 = rowpos(cyo * Q) + cxo, bpar = (cyo * Q) & 1;
 
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const RhsJob& J = jobs[find_job_rhs(jobs, njobs, tile)];
@@ -112,95 +176,111 @@ __global__ __launch_bounds__(NT_) void rhs_pwave_kernel(const LaunchHdr* __restr
     const int X0 = ox + tx * TX, Y0 = oy + ty * TY, Z0 = oz + tz * J.TZ;
     const int Zend = min(Z0 + J.TZ, oz + nfz);
     const long long sxy = (long long)nfx * nfy;
+    const double* __restrict__ U = J.u;
+    const double* __restrict__ V = J.v;
+    const double* __restrict__ A = J.a;
+    const double cu = J.cu, cv = J.cv, ca = J.ca;
 
-    // y tables of the tile's y-elements (zero outside the mesh)
+    // forward y tables of the tile's y-elements (zero outside the mesh)
     const double* tyg = J.tab[1];
     for (int k = tid; k < EY * Q * P; k += NT) {
-      int eyl = k / (Q * P), rest = k - eyl * (Q * P);
-      int ey = Y0 - p + eyl;
-      bool v = ey >= 0 && ey < Ey;
-      tyN[k] = v ? (T)tyg[(long long)ey * Q * P + rest] : T(0);
-      tyD[k] = v ? (T)tyg[(long long)Ey * Q * P + (long long)ey * Q * P + rest] : T(0);
+      const int eyl = k / (Q * P), rest = k - eyl * (Q * P);
+      const int ey = Y0 - p + eyl;
+      const bool v = ey >= 0 && ey < Ey;
+      tyl[eyl * TS + rest] = v ? (T)tyg[(long long)ey * Q * P + rest] : T(0);
+      tyl[eyl * TS + Q * P + rest] = v ? (T)tyg[(long long)(Ey + ey) * Q * P + rest] : T(0);
     }
-    for (int k = tid; k < EY * Q; k += NT) {
-      int eyl = k / Q, g = k - eyl * Q;
-      int ey = Y0 - p + eyl;
-      tyW[k] = (ey >= 0 && ey < Ey) ? (T)tyg[2ll * Ey * Q * P + (long long)ey * Q + g] : T(0);
+    // backward y tables of the owned column, y-weights folded in:
+    // slot b of y-element cyo + p - b at Gauss point gy
+    T bN[P][Q], bD[P][Q];
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      const int ey = Y0 + cyo - b;
+      const bool v = own && ey >= 0 && ey < Ey;
+#pragma unroll
+      for (int gy = 0; gy < Q; ++gy) {
+        const double w = v ? tyg[2ll * Ey * Q * P + (long long)ey * Q + gy] : 0.0;
+        bN[b][gy] = v ? (T)(w * tyg[((long long)ey * Q + gy) * P + b]) : T(0);
+        bD[b][gy] = v ? (T)(w * tyg[((long long)(Ey + ey) * Q + gy) * P + b]) : T(0);
+      }
     }
-    // x tables of this lane's x-element, kept in registers
+    // x tables of this lane's x-element, kept in registers: forward N, D;
+    // backward ones with the x-weights folded in (FP32), or the weights
+    // alone, applied to the point values (FP64: fewer registers)
+    constexpr bool kFoldX = sizeof(T) == 4;
+    constexpr int QW = kFoldX ? Q : 1, QX = kFoldX ? 1 : Q;
     const int ex = X0 - p + j;
     const bool exv = ex >= 0 && ex < Ex;
-    T xN[Q][P], xD[Q][P], xW[Q];
+    T xN[Q][P], xD[Q][P], xNw[QW][P], xDw[QW][P], xW[QX];
     {
       const double* txg = J.tab[0];
 #pragma unroll
       for (int g = 0; g < Q; ++g) {
+        const double w = exv ? txg[2ll * Ex * Q * P + (long long)ex * Q + g] : 0.0;
+        if constexpr (!kFoldX) xW[g] = (T)w;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-          xN[g][a] = exv ? (T)txg[((long long)ex * Q + g) * P + a] : T(0);
-          xD[g][a] = exv ? (T)txg[(long long)Ex * Q * P + ((long long)ex * Q + g) * P + a] : T(0);
+          const double n = exv ? txg[((long long)ex * Q + g) * P + a] : 0.0;
+          const double d = exv ? txg[((long long)(Ex + ex) * Q + g) * P + a] : 0.0;
+          xN[g][a] = (T)n;
+          xD[g][a] = (T)d;
+          if constexpr (kFoldX) {
+            xNw[g][a] = (T)(w * n);
+            xDw[g][a] = (T)(w * d);
+          }
         }
-        xW[g] = exv ? (T)txg[2ll * Ex * Q * P + (long long)ex * Q + g] : T(0);
       }
     }
+    // backward x table entries at Gauss point gx
+    auto bxN = [&](int gx, int a) -> T { if constexpr (kFoldX) return xNw[gx][a]; else return xN[gx][a]; };
+    auto bxD = [&](int gx, int a) -> T { if constexpr (kFoldX) return xDw[gx][a]; else return xD[gx][a]; };
     double ampv = 0.0;
     if (J.load != nullptr && J.amp != nullptr) {
       long long ai = (long long)(*J.counter) + J.amp_shift;
       ampv = (ai >= 0 && ai < J.namp) ? J.amp[ai] : 0.0;
     }
 
-    auto load_layer = [&](int cz) {
-      const int slot = cz % P;
-      const bool zv = cz >= oz && cz < oz + nfz;
-      for (int k = tid; k < TYH * TXH; k += NT) {
-        int cyl = k / TXH, cxl = k - cyl * TXH;
-        int cy = Y0 - p + cyl, cx = X0 - p + cxl;
-        double w = 0.0;
-        if (zv && cy >= oy && cy < oy + nfy && cx >= ox && cx < ox + nfx) {
-          long long gi = (long long)(cz - oz) * sxy + (long long)(cy - oy) * nfx + (cx - ox);
-          w = J.cu * J.u[gi];
-          if (J.v != nullptr) w = fma(J.cv, J.v[gi], w);
-          if (J.a != nullptr) w = fma(J.ca, J.a[gi], w);
-        }
-        RING(slot, cyl, cxl) = (T)w;
-      }
-    };
-    // next-layer prefetch: global loads issued one layer ahead, written to
-    // the ring after the last z Gauss point of the current layer
-    constexpr int NPF = (TYH * TXH + NT - 1) / NT;
-    double pf[NPF];
+    // predictor loads: ring position k = tid + i*NT, global row offset per tile
+    long long prow[NF];
+    bool pval[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int k = tid + i * NT;
+      const int cyl = k / TXH, cxl = k - cyl * TXH;
+      const int cy = Y0 - p + cyl, cx = X0 - p + cxl;
+      pval[i] = k < NC && cy >= oy && cy < oy + nfy && cx >= ox && cx < ox + nfx;
+      prow[i] = (long long)(cy - oy) * nfx + (cx - ox);
+    }
+    double pf[NF];
     auto prefetch_layer = [&](int cz) {
       const bool zv = cz >= oz && cz < oz + nfz;
+      const long long zo = (long long)(cz - oz) * sxy;
 #pragma unroll
-      for (int i = 0; i < NPF; ++i) {
-        const int k = tid + i * NT;
+      for (int i = 0; i < NF; ++i) {
         double w = 0.0;
-        if (k < TYH * TXH) {
-          int cyl = k / TXH, cxl = k - cyl * TXH;
-          int cy = Y0 - p + cyl, cx = X0 - p + cxl;
-          if (zv && cy >= oy && cy < oy + nfy && cx >= ox && cx < ox + nfx) {
-            long long gi = (long long)(cz - oz) * sxy + (long long)(cy - oy) * nfx + (cx - ox);
-            w = J.cu * J.u[gi];
-            if (J.v != nullptr) w = fma(J.cv, J.v[gi], w);
-            if (J.a != nullptr) w = fma(J.ca, J.a[gi], w);
-          }
+        if (zv && pval[i]) {
+          const long long gi = zo + prow[i];
+          w = cu * U[gi];
+          if (V != nullptr) w = fma(cv, V[gi], w);
+          if (A != nullptr) w = fma(ca, A[gi], w);
         }
         pf[i] = w;
       }
     };
     auto commit_layer = [&](int cz) {
-      const int slot = cz % P;
+      T* dst = ring + (cz % P) * NC;
 #pragma unroll
-      for (int i = 0; i < NPF; ++i) {
+      for (int i = 0; i < NF; ++i) {
         const int k = tid + i * NT;
-        if (k < TYH * TXH) ring[slot * TYH * TXH + k] = (T)pf[i];
+        if (k < NC) dst[k] = (T)pf[i];
       }
     };
+    const long long obase = (long long)(Y0 + cyo - oy) * nfx + (X0 + cxo - ox);
+    const bool ocol = own && Y0 + cyo < oy + nfy && X0 + cxo < ox + nfx;
     auto store_out = [&](int cz, double accv) {
-      const int cy = Y0 + cyo, cx = X0 + cxo;
-      if (cz >= Z0 && cz < Zend && cy < oy + nfy && cx < ox + nfx) {
-        long long gi = (long long)(cz - oz) * sxy + (long long)(cy - oy) * nfx + (cx - ox);
-        double f = (J.load != nullptr) ? ampv * J.load[gi] : 0.0;
+      if (ocol && cz >= Z0 && cz < Zend) {
+        const long long gi = (long long)(cz - oz) * sxy + obase;
+        const double f = (J.load != nullptr) ? ampv * J.load[gi] : 0.0;
         J.R[gi] = J.rscale * (f - accv);
       }
     };
@@ -211,148 +291,241 @@ __global__ __launch_bounds__(NT_) void rhs_pwave_kernel(const LaunchHdr* __restr
 
     const int ez0 = max(0, Z0 - p);
     const int ez1 = min(Ez - 1, Zend - 1);
-    for (int cz = ez0; cz <= ez0 + p; ++cz) load_layer(cz);
+    for (int cz = ez0; cz <= ez0 + p; ++cz) {
+      prefetch_layer(cz);
+      commit_layer(cz);
+    }
     __syncthreads();
 
     const double* tzg = J.tab[2];
     int buf = 0;
     for (int ez = ez0; ez <= ez1; ++ez) {
       if (ez < ez1) prefetch_layer(ez + P);
-      for (int gz = 0; gz < Q; ++gz) {
-        T nz[P], dz[P];
+      // (Z) z-contraction of this wave's coefficient rows at every z Gauss
+      // point (value, z-derivative)
+      {
+        T nz[Q][P], dz[Q][P];
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          nz[a] = (T)tzg[((long long)ez * Q + gz) * P + a];
-          dz[a] = (T)tzg[(long long)Ez * Q * P + ((long long)ez * Q + gz) * P + a];
+        for (int g = 0; g < Q; ++g)
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            nz[g][a] = (T)tzg[((long long)ez * Q + g) * P + a];
+            dz[g][a] = (T)tzg[((long long)(Ez + ez) * Q + g) * P + a];
+          }
+        const T* rs[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a) rs[a] = ring + ((ez + a) % P) * NC + wv * WE * TXH;
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          const int k = lane + 64 * i;
+          if (k < NZW) {
+            T r[P];
+#pragma unroll
+            for (int a = 0; a < P; ++a) r[a] = rs[a][k];
+            T dr[P];
+#pragma unroll
+            for (int a = 1; a < P; ++a) dr[a] = r[a] - r[0];
+#pragma unroll
+            for (int g = 0; g < Q; ++g) {
+              T v = nz[g][0] * r[0], d = dz[g][1] * dr[1];
+#pragma unroll
+              for (int a = 1; a < P; ++a) v = fma(nz[g][a], r[a], v);
+#pragma unroll
+              for (int a = 2; a < P; ++a) d = fma(dz[g][a], dr[a], d);
+              zc[(2 * g) * NZW + k] = v;
+              zc[(2 * g + 1) * NZW + k] = d;
+            }
+          }
         }
-        const T wz = (T)tzg[2ll * Ez * Q * P + (long long)ez * Q + gz];
-        // S12: z- then y-contraction, straight from the coefficient ring
-        for (int k = tid; k < EY * TXH; k += NT) {
-          const int eyl = k / TXH, cxl = k - eyl * TXH;
+      }
+      wave_sync();
+#pragma unroll 1
+      for (int gz = 0; gz < Q; ++gz) {
+        T* sbb = sb + buf * 3 * SBC;
+        // (Y) y-contraction of this wave's y-elements: value, y-derivative,
+        // z-derivative per y Gauss row
+        {
+          const T* z0 = zc + (2 * gz) * NZW + yzc;
+          const T* z1 = z0 + NZW;
           T av[P], bv[P];
 #pragma unroll
           for (int b = 0; b < P; ++b) {
-            const T r0 = RING(ez % P, eyl + b, cxl);
-            T A = T(0), B = T(0);
-#pragma unroll
-            for (int a = 0; a < P; ++a) {
-              const T r = RING((ez + a) % P, eyl + b, cxl);
-              A = fma(nz[a], r, A);
-              B = fma(dz[a], r - r0, B);     // sum_a dz[a] = 0: contract differences
-            }
-            av[b] = A;
-            bv[b] = B;
+            av[b] = z0[b * TXH];
+            bv[b] = z1[b * TXH];
           }
-          const T* tN = tyN + eyl * Q * P;
-          const T* tD = tyD + eyl * Q * P;
+          T da[P];
+#pragma unroll
+          for (int b = 1; b < P; ++b) da[b] = av[b] - av[0];
+          const T* tN = tyl + yty;
+          const T* tD = tN + Q * P;
 #pragma unroll
           for (int gy = 0; gy < Q; ++gy) {
-            T c = T(0), dyv = T(0), dzv = T(0);
+            T c = tN[gy * P] * av[0], dzv = tN[gy * P] * bv[0], dyv = tD[gy * P + 1] * da[1];
 #pragma unroll
-            for (int b = 0; b < P; ++b) {
+            for (int b = 1; b < P; ++b) {
               c = fma(tN[gy * P + b], av[b], c);
-              dyv = fma(tD[gy * P + b], av[b] - av[0], dyv);
               dzv = fma(tN[gy * P + b], bv[b], dzv);
             }
-            SB(buf, 0, eyl * Q + gy, cxl) = c;
-            SB(buf, 1, eyl * Q + gy, cxl) = dyv;
-            SB(buf, 2, eyl * Q + gy, cxl) = dzv;
+#pragma unroll
+            for (int b = 2; b < P; ++b) dyv = fma(tD[gy * P + b], da[b], dyv);
+            T* o = sbb + rowstep(ysb, ypar, gy);
+            o[0] = c;
+            o[SBC] = dyv;
+            o[2 * SBC] = dzv;
           }
         }
-        __syncthreads();
-        // S34: x-forward, weights, x-backward; lanes are x-elements
-        for (int r = rg; r < R; r += NRG) {
-          const T wyz = tyW[r] * wz;
+        if (xok) {
+          const T* z0 = zc + (2 * gz) * NZW + xzc;
+          const T* z1 = z0 + NZW;
+          T av[P], bv[P];
+#pragma unroll
+          for (int b = 0; b < P; ++b) {
+            av[b] = z0[b * TXH];
+            bv[b] = z1[b * TXH];
+          }
+          const T* tN = tyl + xty;
+          const T* tD = tN + Q * P;
+          T c = tN[0] * av[0], dzv = tN[0] * bv[0], dyv = tD[1] * (av[1] - av[0]);
+#pragma unroll
+          for (int b = 1; b < P; ++b) {
+            c = fma(tN[b], av[b], c);
+            dzv = fma(tN[b], bv[b], dzv);
+          }
+#pragma unroll
+          for (int b = 2; b < P; ++b) dyv = fma(tD[b], av[b] - av[0], dyv);
+          T* o = sbb + xsb;
+          o[0] = c;
+          o[SBC] = dyv;
+          o[2 * SBC] = dzv;
+        }
+        wave_sync();
+        // (X) x-forward, x-weights, x-backward on this wave's rows; lanes
+        // are x-elements
+#pragma unroll
+        for (int i = 0; i < NRW; ++i) {
+          T* row = sbb + xrow0 + 2 * i * TXH;
           T c0[P], c1[P], c2[P];
 #pragma unroll
           for (int a = 0; a < P; ++a) {
-            c0[a] = SB(buf, 0, r, j + a);
-            c1[a] = SB(buf, 1, r, j + a);
-            c2[a] = SB(buf, 2, r, j + a);
+            c0[a] = row[j + a];
+            c1[a] = row[SBC + j + a];
+            c2[a] = row[2 * SBC + j + a];
           }
+          T d0[P];
+#pragma unroll
+          for (int a = 1; a < P; ++a) d0[a] = c0[a] - c0[0];
           T o0[P], o1[P], o2[P];
 #pragma unroll
-          for (int a = 0; a < P; ++a) o0[a] = o1[a] = o2[a] = T(0);
-#pragma unroll
           for (int gx = 0; gx < Q; ++gx) {
-            T gX = T(0), gY = T(0), gZ = T(0);
+            T gX = xD[gx][1] * d0[1], gY = xN[gx][0] * c1[0], gZ = xN[gx][0] * c2[0];
 #pragma unroll
-            for (int a = 0; a < P; ++a) {
-              gX = fma(xD[gx][a], c0[a] - c0[0], gX);
+            for (int a = 2; a < P; ++a) gX = fma(xD[gx][a], d0[a], gX);
+#pragma unroll
+            for (int a = 1; a < P; ++a) {
               gY = fma(xN[gx][a], c1[a], gY);
               gZ = fma(xN[gx][a], c2[a], gZ);
             }
-            const T w = xW[gx] * wyz;
-            gX *= w;
-            gY *= w;
-            gZ *= w;
+            if constexpr (!kFoldX) {
+              gX *= xW[gx];
+              gY *= xW[gx];
+              gZ *= xW[gx];
+            }
+            if (gx == 0) {
 #pragma unroll
-            for (int a = 0; a < P; ++a) {
-              o0[a] = fma(xD[gx][a], gX, o0[a]);
-              o1[a] = fma(xN[gx][a], gY, o1[a]);
-              o2[a] = fma(xN[gx][a], gZ, o2[a]);
+              for (int a = 0; a < P; ++a) {
+                o0[a] = bxD(0, a) * gX;
+                o1[a] = bxN(0, a) * gY;
+                o2[a] = bxN(0, a) * gZ;
+              }
+            } else {
+#pragma unroll
+              for (int a = 1; a < P; ++a) o0[a] = fma(bxD(gx, a), gX, o0[a]);
+#pragma unroll
+              for (int a = 0; a < P; ++a) {
+                o1[a] = fma(bxN(gx, a), gY, o1[a]);
+                o2[a] = fma(bxN(gx, a), gZ, o2[a]);
+              }
             }
           }
+          // backward derivative tables sum to zero: slot 0 from the others
+          {
+            T s = o0[1];
+#pragma unroll
+            for (int a = 2; a < P; ++a) s += o0[a];
+            o0[0] = -s;
+          }
           // coefficient c = ex collects slot a of element ex - a (lane j - a)
-          const T r0v = o0[0] + shift_sum<1, P, T>(o0);
-          const T r1v = o1[0] + shift_sum<1, P, T>(o1);
-          const T r2v = o2[0] + shift_sum<1, P, T>(o2);
+          const T r0v = horner_shift<P, T>(o0);
+          const T r1v = horner_shift<P, T>(o1);
+          const T r2v = horner_shift<P, T>(o2);
           if (j >= p) {
-            SB(buf, 0, r, j - p) = r0v;
-            SB(buf, 1, r, j - p) = r1v;
-            SB(buf, 2, r, j - p) = r2v;
+            row[j - p] = r0v;
+            row[SBC + j - p] = r1v;
+            row[2 * SBC + j - p] = r2v;
           }
         }
-        // refill the ring slot of layer ez once every z Gauss point has read it
+        // refill the ring slot of layer ez (its z stage is done in every
+        // wave: they all passed the barrier of an earlier Gauss point)
         if (gz == Q - 1 && ez < ez1) commit_layer(ez + P);
         __syncthreads();
-        // S5: y-backward and z-backward into the owned column's accumulators
+        // (B) y-backward and z-backward into the owned column's accumulators
         if (own) {
+          // backward z tables at this Gauss point, z-weight folded in
+          double nzw[P], dzw[P];
+          {
+            const double w = tzg[2ll * Ez * Q * P + (long long)ez * Q + gz];
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+              nzw[a] = w * tzg[((long long)ez * Q + gz) * P + a];
+              dzw[a] = w * tzg[((long long)(Ez + ez) * Q + gz) * P + a];
+            }
+          }
           T Ap = T(0), Bp = T(0);
 #pragma unroll
           for (int b = 0; b < P; ++b) {
-            const int eyl = cyo + p - b;
-            const T* tN = tyN + eyl * Q * P;
-            const T* tD = tyD + eyl * Q * P;
 #pragma unroll
             for (int gy = 0; gy < Q; ++gy) {
-              const int rr = eyl * Q + gy;
-              Ap = fma(tN[gy * P + b], SB(buf, 0, rr, cxo), Ap);
-              Ap = fma(tD[gy * P + b], SB(buf, 1, rr, cxo), Ap);
-              Bp = fma(tN[gy * P + b], SB(buf, 2, rr, cxo), Bp);
+              const T* e = sbb + rowstep(brow0, bpar, (p - b) * Q + gy);
+              Ap = fma(bN[b][gy], e[0], Ap);
+              Ap = fma(bD[b][gy], e[SBC], Ap);
+              Bp = fma(bN[b][gy], e[2 * SBC], Bp);
             }
           }
 #pragma unroll
-          for (int a = 0; a < P; ++a)
-            acc[a] = fma((double)nz[a], (double)Ap, fma((double)dz[a], (double)Bp, acc[a]));
+          for (int a = 0; a < P; ++a) acc[a] = fma(nzw[a], (double)Ap, fma(dzw[a], (double)Bp, acc[a]));
         }
         buf ^= 1;
       }
-      if (own) store_out(ez, acc[0]);
+      store_out(ez, acc[0]);
 #pragma unroll
       for (int a = 0; a < P - 1; ++a) acc[a] = acc[a + 1];
       acc[P - 1] = 0.0;
     }
-    if (own) {
 #pragma unroll
-      for (int a = 0; a < P - 1; ++a) store_out(ez1 + 1 + a, acc[a]);
-    }
+    for (int a = 0; a < P - 1; ++a) store_out(ez1 + 1 + a, acc[a]);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// variants (tile height, workgroup size) per degree and arithmetic
+// variants (tile height, workgroup size) per degree and arithmetic; variant
+// 0 is the same for both arithmetics.  The autotuner in api.cpp times them
+// on the real mesh.
 struct RhsVariant {
   int TY, NT;
 };
-// index: variant id; the autotuner in api.cpp times them on the real mesh
-static const RhsVariant kVarP2[] = {{14, 256}, {30, 512}, {46, 768}};
-static const RhsVariant kVarP3[] = {{13, 256}, {29, 512}, {21, 384}};
+static const RhsVariant kVarP2F[] = {{14, 256}, {30, 512}, {46, 768}};
+static const RhsVariant kVarP2D[] = {{14, 256}, {30, 512}, {22, 384}};
+static const RhsVariant kVarP3F[] = {{13, 256}, {29, 512}, {21, 384}};
+static const RhsVariant kVarP3D[] = {{13, 256}, {21, 384}, {9, 192}};
 
 int rhs_num_variants(int) { return 3; }
 int rhs_tile_x(int p) { return 16 - p; }
-int rhs_tile_y(int p, int var) { return p == 2 ? kVarP2[var].TY : kVarP3[var].TY; }
+int rhs_tile_y(int p, int mixed, int var) {
+  if (var < 0 || var > 2) var = 0;
+  if (p == 2) return mixed ? kVarP2F[var].TY : kVarP2D[var].TY;
+  return mixed ? kVarP3F[var].TY : kVarP3D[var].TY;
+}
 
 // op 0: launch; op 1: *out = resident workgroups per CU (persistent grids)
 template <typename T, int P, int TY, int NT>
@@ -372,19 +545,33 @@ static hipError_t launch_one(const LaunchHdr* d_hdr, int grid, hipStream_t s, in
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_t(int p, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
+static hipError_t launch_f(int p, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
   if (p == 2) {
     switch (var) {
-      case 0: return launch_one<T, 3, 14, 256>(d_hdr, grid, s, op, out);
-      case 1: return launch_one<T, 3, 30, 512>(d_hdr, grid, s, op, out);
-      default: return launch_one<T, 3, 46, 768>(d_hdr, grid, s, op, out);
+      case 0: return launch_one<float, 3, 14, 256>(d_hdr, grid, s, op, out);
+      case 1: return launch_one<float, 3, 30, 512>(d_hdr, grid, s, op, out);
+      default: return launch_one<float, 3, 46, 768>(d_hdr, grid, s, op, out);
     }
   }
   switch (var) {
-    case 0: return launch_one<T, 4, 13, 256>(d_hdr, grid, s, op, out);
-    case 1: return launch_one<T, 4, 29, 512>(d_hdr, grid, s, op, out);
-    default: return launch_one<T, 4, 21, 384>(d_hdr, grid, s, op, out);
+    case 0: return launch_one<float, 4, 13, 256>(d_hdr, grid, s, op, out);
+    case 1: return launch_one<float, 4, 29, 512>(d_hdr, grid, s, op, out);
+    default: return launch_one<float, 4, 21, 384>(d_hdr, grid, s, op, out);
+  }
+}
+
+static hipError_t launch_d(int p, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
+  if (p == 2) {
+    switch (var) {
+      case 0: return launch_one<double, 3, 14, 256>(d_hdr, grid, s, op, out);
+      case 1: return launch_one<double, 3, 30, 512>(d_hdr, grid, s, op, out);
+      default: return launch_one<double, 3, 22, 384>(d_hdr, grid, s, op, out);
+    }
+  }
+  switch (var) {
+    case 0: return launch_one<double, 4, 13, 256>(d_hdr, grid, s, op, out);
+    case 1: return launch_one<double, 4, 21, 384>(d_hdr, grid, s, op, out);
+    default: return launch_one<double, 4, 9, 192>(d_hdr, grid, s, op, out);
   }
 }
 
@@ -392,14 +579,13 @@ hipError_t launch_rhs_pwave(int p, int mixed, int var, const LaunchHdr* d_hdr, i
   if (grid <= 0) return hipSuccess;
   if (p != 2 && p != 3) return hipErrorInvalidValue;
   if (var < 0 || var > 2) var = 0;
-  return mixed ? launch_t<float>(p, var, d_hdr, grid, s, 0, nullptr)
-               : launch_t<double>(p, var, d_hdr, grid, s, 0, nullptr);
+  return mixed ? launch_f(p, var, d_hdr, grid, s, 0, nullptr) : launch_d(p, var, d_hdr, grid, s, 0, nullptr);
 }
 
 int rhs_blocks_per_cu(int p, int mixed, int var) {
   int n = 1;
-  if (mixed) launch_t<float>(p, var, nullptr, 0, nullptr, 1, &n);
-  else launch_t<double>(p, var, nullptr, 0, nullptr, 1, &n);
+  if (mixed) launch_f(p, var, nullptr, 0, nullptr, 1, &n);
+  else launch_d(p, var, nullptr, 0, nullptr, 1, &n);
   return n < 1 ? 1 : n;
 }
 

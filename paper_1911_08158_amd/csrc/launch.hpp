@@ -10,10 +10,11 @@ namespace ads {
 int sweep_width_for(int max_m);
 hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int max_m, hipStream_t s);
 hipError_t sweep_set_attributes();
+int sweep_blocks_per_cu(int max_m);
 
 int rhs_num_variants(int p);
 int rhs_tile_x(int p);
-int rhs_tile_y(int p, int var);
+int rhs_tile_y(int p, int mixed, int var);
 int rhs_blocks_per_cu(int p, int mixed, int var);
 hipError_t launch_rhs_pwave(int p, int mixed, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int rhs_el_tile_x(int p);
