@@ -45,6 +45,33 @@ def rhs_flops_per_element(p, q=None):
 
 SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_z": 56}   # per free DOF (z fused with Newmark update)
 
+# HBM traffic of one batched right-hand-side launch (4 simulations), from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same counters
+# read for a 512 MiB device copy (profiles/rhs_pwave128_p2_batch4_hbm_traffic.md).
+# Valid only for the kernel source it was measured on: reported as null
+# once the right-hand-side sources hash differently.
+RHS_TRAFFIC = {
+    "sources": ["paper_1911_08158_amd/csrc/k_rhs.hip", "paper_1911_08158_amd/csrc/common.hpp"],
+    "sha256": "bfabc7cca70e0b78d2c3bbbefbd916e80ce1245e3fa4f4c5828997ff6981c6bc",
+    "fetch_kib": 312897.0, "fetch_scale": 2.0,
+    "write_kib": 75776.0, "write_scale": 1.0,
+    "batch": 4,
+}
+
+
+def rhs_traffic(batch):
+    import hashlib
+    t = RHS_TRAFFIC
+    if batch != t["batch"]:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
+
 
 def gpu_info():
     import torch
@@ -230,7 +257,8 @@ def main():
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
     rhs = next(k for k in batched["kernels"] if k["kernel"] == "rhs")
     roof = {"bound": "alu", "achieved": rhs["tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(rhs["tflops"] / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(rhs["tflops"] / FP32_PEAK_TFLOPS, 4), "traffic": rhs_traffic(args.batch),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
             "kernel": "rhs_pwave_kernel<float,3,3,..> (FP32 contractions, batched)",
             "per_launch": f"{rhs_flops_per_element(cfg.p)} flops/element x {int(np.prod(cfg.nelem))} elements "
                           f"x {args.batch} simulations"}

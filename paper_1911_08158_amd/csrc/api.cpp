@@ -63,6 +63,7 @@ struct Launch {
   int var = 0;    // right-hand side: tile variant
   int mixed = 0;  // right-hand side: FP32 contractions
   std::vector<char> host_jobs;
+  int w = 4;      // sweeps: lines per wave tile
 };
 
 struct DevFactor {
@@ -263,6 +264,8 @@ void carve(ads_sim* s, Carver& c) {
 
 // --- job builders ------------------------------------------------------------
 
+int max_m(const ads_sim* s) { return std::max(s->nf[0], std::max(s->nf[1], s->nf[2])); }
+
 SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* in, double* out, double scale) {
   SweepJob J{};
   J.in = in;
@@ -274,15 +277,12 @@ SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* 
   J.ny = s->nf[1];
   J.nz = s->nf[2];
   J.nlines = (int)(s->nfree / s->nf[dir]);
-  const int W = sweep_width_for(std::max(s->nf[0], std::max(s->nf[1], s->nf[2])));
-  J.ntiles = (J.nlines + W - 1) / W;
+  J.ntiles = sweep_groups(J.nlines, sweep_width_for(J.nlines, max_m(s), s->ncu));
   J.tile0 = 0;
   J.epi = EPI_STORE;
   J.scale = scale;
   return J;
 }
-
-int max_m(const ads_sim* s) { return std::max(s->nf[0], std::max(s->nf[1], s->nf[2])); }
 
 // Three sweeps x (in -> X), y (X -> tmp), z (tmp -> out/epilogue) with one
 // factor per direction.
@@ -308,6 +308,7 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
     const LaunchHdr* d = s->arena.add(std::vector<SweepJob>{*j}, err);
     if (!d) return false;
     L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir, 0, 0, as_bytes(*j)});
+    L.back().w = sweep_width_for(j->nlines, max_m(s), s->ncu);
   }
   return true;
 }
@@ -532,7 +533,7 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
         e = launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::SWEEP:
-        e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.max_m, s->stream);
+        e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.w, l.max_m, s->stream);
         break;
       case Launch::KRON:
         e = launch_kron(l.d_hdr, grid_of(l, grid_cap), s->stream);
@@ -1018,6 +1019,7 @@ struct PoolLaunch {
   int p, mixed, var;
   int stage;        // 0: right-hand side class, k >= 1: k-th launch after it
   int grid;
+  int w;            // sweeps: lines per wave tile (chosen per batch)
   size_t off, cap;  // table offset/capacity (bytes) in the pool's table region
   size_t job_size;
 };
@@ -1051,8 +1053,10 @@ struct ads_pool {
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;
-  std::vector<char> nonempty;      // launch classes with jobs in the current batch
-  std::vector<char> captured;      // ... when the graph was captured
+  std::vector<int> nonempty;       // per launch class: 0 = no jobs in the batch, else its
+                                   // launch shape (sweeps: tile width)
+  std::vector<int> captured;       // ... when the graph was captured
+  int ncu = 0;
   ~ads_pool() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1068,7 +1072,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   P->seq.clear();
   size_t off = 0;
   auto add = [&](Launch::Kind k, int p, int mixed, int var, int stage, int grid, size_t js) {
-    PoolLaunch L{k, p, mixed, var, stage, grid, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
+    PoolLaunch L{k, p, mixed, var, stage, grid, 4, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
     off += (L.cap + kAlign - 1) / kAlign * kAlign;
     P->seq.push_back(L);
   };
@@ -1080,7 +1084,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
     if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, 8 * ncu, sizeof(KronJob));
-    else add(Launch::SWEEP, 0, 0, 0, k, sweep_blocks_per_cu(kPoolMaxM) * ncu, sizeof(SweepJob));
+    else add(Launch::SWEEP, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
 }
@@ -1090,7 +1094,7 @@ ads_status pool_rebuild(ads_pool* P) {
   std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
   P->nonempty.assign(P->seq.size(), 0);
   for (size_t li = 0; li < P->seq.size(); ++li) {
-    const PoolLaunch& L = P->seq[li];
+    PoolLaunch& L = P->seq[li];
     std::vector<std::vector<char>> sel;
     bool fixed_tz = false;
     for (ads_pool::Slot& sl : P->slots) {
@@ -1118,6 +1122,17 @@ ads_status pool_rebuild(ads_pool* P) {
         set_zchunks(*r, r->nf[2], k);
       }
     }
+    // sweeps: tile width and persistent grid for the batch's line count
+    if (L.kind == Launch::SWEEP && !sel.empty()) {
+      long long lines = 0;
+      for (const auto& j : sel) lines += ((const SweepJob*)j.data())->nlines;
+      L.w = sweep_width_for(lines, kPoolMaxM, P->ncu);
+      L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM) * P->ncu;
+      for (auto& j : sel) {
+        SweepJob* r = (SweepJob*)j.data();
+        r->ntiles = sweep_groups(r->nlines, L.w);
+      }
+    }
     std::vector<char> jobs;
     int n = 0, total = 0;
     for (std::vector<char>& j : sel) {
@@ -1141,7 +1156,7 @@ ads_status pool_rebuild(ads_pool* P) {
     LaunchHdr h{};
     h.njobs = n;
     h.total_tiles = total;
-    P->nonempty[li] = n > 0;
+    P->nonempty[li] = n == 0 ? 0 : (L.kind == Launch::SWEEP ? L.w : 1);
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
@@ -1164,7 +1179,7 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
     switch (L.kind) {
       case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, h, L.grid, P->stream); break;
       case Launch::RHS_E: e = launch_rhs_elastic(L.p, h, L.grid, P->stream); break;
-      case Launch::SWEEP: e = launch_sweeps(h, L.grid, kPoolMaxM, P->stream); break;
+      case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, P->stream); break;
       case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
@@ -1202,6 +1217,7 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
     int v = std::max(0, std::min(2, std::atoi(e)));
     for (auto& r : P->var) r[0] = r[1] = v;
   }
+  P->ncu = ncu;
   pool_build_seq(P, ncu);
   P->arena_off = (P->tab_bytes + kAlign - 1) / kAlign * kAlign;
   if (P->arena_off >= bytes) {

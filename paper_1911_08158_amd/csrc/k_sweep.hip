@@ -2,18 +2,19 @@
 // of one direction (Appendix: the x-, y- and z-problems are 1D banded
 // systems with one right-hand side per line; the factor is shared).
 //
-// Mapping on gfx950: a block is one wave64 and a tile is W lines (W = 16 by
-// default, 32 or 64 selectable).  All 64 lanes stage the tile into LDS
-// [i][line] with an XOR swizzle: x-lines (contiguous in memory) as one flat
-// cooperative block, y- and z-lines with 64/W lanes per line so that each
-// load instruction reads 64/W rows of W consecutive x.  The first W lanes
-// then run the substitution, one line each, with the factor rows staged in
-// LDS behind the tile and read as broadcasts.  Small tiles give several
-// waves per CU that overlap one another's load, solve and store phases; the
-// tile loads are issued kChunk at a time per lane before any is consumed.
-// The forward result overwrites the tile in LDS, the backward result
-// overwrites it again, then all 64 lanes write it out (optionally fused with
-// the Newmark or three-level time update).
+// Mapping on gfx950: a workgroup is four wave64s and takes a group of 4W
+// consecutive lines of one job; each wave owns a tile of W lines (W = 16,
+// or 8 / 4 for launches with few lines).  The wave
+// stages its tile in LDS [i][line] with an XOR swizzle: x-lines (contiguous
+// in memory) as one flat cooperative block, y- and z-lines with 64/W lanes
+// per line so that each load reads 64/W rows of W consecutive x.  The first
+// W lanes then run the substitution, one line each, reading the factor rows
+// as LDS broadcasts; all 64 lanes write the result (optionally fused with
+// the Newmark or three-level time update).  The factor rows are staged
+// once per workgroup and again only when a group belongs to another job,
+// so inside a job the four waves never wait for each other: one wave's
+// loads, substitution and stores overlap the others'.
+#include <algorithm>
 #include <cstdlib>
 
 #include "common.hpp"
@@ -29,10 +30,20 @@ __device__ __forceinline__ int find_job_sweep(const SweepJob* jobs, int njobs, i
   return lo;
 }
 
+// Completes this wave's LDS writes before its lanes read each other's
+// values (LDS operations of one wave execute in order).
+__device__ __forceinline__ void wave_sync_sw() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int W>
 __device__ __forceinline__ int sidx(int i, int l) { return i * W + (l ^ (i & (W - 1))); }
 
-constexpr int kChunk = 32;   // global loads in flight per lane while staging a tile
+constexpr int kChunk = 8;    // global loads in flight per lane while staging a tile
+constexpr int kWaves = 4;    // waves per workgroup (one tile each)
+constexpr int kNT = 64 * kWaves;
 
 // Global offset of element i of line `line` and the element stride.
 __device__ __forceinline__ void line_geom(const SweepJob& J, int line, long long& base, long long& stride) {
@@ -51,7 +62,7 @@ __device__ __forceinline__ void line_geom(const SweepJob& J, int line, long long
 
 // Epilogue on K solved values at global offsets g[k] (ok[k] false = skip);
 // all old-state loads of the batch are issued before any is used.
-constexpr int kEpi = 8;
+constexpr int kEpi = 4;
 __device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long long* g, const double* x,
                                                const bool* ok) {
   if (J.epi == EPI_STORE) {
@@ -95,9 +106,9 @@ __device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long lon
 // line held in LDS.  The dependency chain per step is a single FMA on the
 // most recent value; the older terms are folded in first.
 template <int W, int P>
-__device__ __forceinline__ void substitute(double* lds, int lane, int m, const double* fl) {
+__device__ __forceinline__ void substitute(double* tl, int lane, int m, const double* fl) {
   constexpr int p = P;
-  // factor rows staged in LDS behind the tile: L[m*p], U[m*p], rd[m]
+  // factor rows: L[m*p], U[m*p], rd[m]
   const double* Lf = fl;
   const double* Uf = fl + m * p;
   const double* rdf = fl + 2 * m * p;
@@ -107,53 +118,62 @@ __device__ __forceinline__ void substitute(double* lds, int lane, int m, const d
 #pragma unroll 8
   for (int i = 0; i < m; ++i) {
     const double* Li = Lf + i * p;
-    double s = lds[sidx<W>(i, lane)];
+    double s = tl[sidx<W>(i, lane)];
 #pragma unroll
     for (int k = p - 1; k >= 0; --k) s = fma(-Li[k], h[k], s);
 #pragma unroll
     for (int k = p - 1; k > 0; --k) h[k] = h[k - 1];
     h[0] = s;
-    lds[sidx<W>(i, lane)] = s;
+    tl[sidx<W>(i, lane)] = s;
   }
 #pragma unroll
   for (int k = 0; k < p; ++k) h[k] = 0.0;
 #pragma unroll 8
   for (int i = m - 1; i >= 0; --i) {
     const double* Ui = Uf + i * p;
-    double s = lds[sidx<W>(i, lane)];
+    double s = tl[sidx<W>(i, lane)];
 #pragma unroll
     for (int k = p - 1; k >= 0; --k) s = fma(-Ui[k], h[k], s);
     s *= rdf[i];
 #pragma unroll
     for (int k = p - 1; k > 0; --k) h[k] = h[k - 1];
     h[0] = s;
-    lds[sidx<W>(i, lane)] = s;
+    tl[sidx<W>(i, lane)] = s;
   }
 }
 
-constexpr int kNT = 64;   // threads per block: one wave64
-
-// A tile is W lines (W divides 64).  All 64 lanes of the block stage the
-// tile: x-lines cooperatively as one contiguous block, y/z-lines with 64/W
-// lanes per line (consecutive lanes = consecutive lines = consecutive x, so
-// each instruction reads 64/W rows of W contiguous doubles).  The first W
-// lanes run the substitution, one line each.  Small W gives many small
-// waves (several per CU) that overlap each other's load, solve and store.
+// Job tiling: SweepJob.tile0 / ntiles count groups of 4W lines; the header's
+// total_tiles is the number of groups of the launch.
 template <int W>
-__global__ __launch_bounds__(kNT) void sweep_kernel(const LaunchHdr* __restrict__ hdr) {
-  static_assert(kNT % W == 0, "W must divide the wave size");
-  constexpr int RL = kNT / W;   // lanes per line in the cooperative y/z access
+__global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restrict__ hdr, int max_m) {
+  static_assert(64 % W == 0, "W must divide the wave size");
+  constexpr int RL = 64 / W;   // lanes per line in the cooperative y/z access
   extern __shared__ double lds[];
-  const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
+  const int njobs = hdr->njobs, total_groups = hdr->total_tiles;
   const SweepJob* __restrict__ jobs = hdr_jobs<SweepJob>(hdr);
   const int tid = threadIdx.x;
-  const int ll = tid % W, lq = tid / W;   // cooperative y/z access: line ll, row phase lq
-  for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    const int jb = find_job_sweep(jobs, njobs, tile);
+  const int lane = tid & 63, wv = tid >> 6;
+  const int ll = lane % W, lq = lane / W;   // cooperative y/z access: line ll, row phase lq
+  double* fl = lds;                                             // factor rows
+  double* tl = lds + (2 * kMaxP + 1) * max_m + wv * W * max_m;  // this wave's tile
+  int staged = -1;                                              // job whose factor is in LDS
+  for (int grp = blockIdx.x; grp < total_groups; grp += gridDim.x) {
+    const int jb = find_job_sweep(jobs, njobs, grp);
     const SweepJob& J = jobs[jb];
-    const int t = tile - J.tile0;
     const int m = J.f.m;
-    const int line0 = t * W;
+    if (jb != staged) {   // uniform over the workgroup
+      __syncthreads();    // no wave still reads the previous factor
+      const int mp = m * J.p;
+      for (int k = tid; k < mp; k += kNT) {
+        fl[k] = J.f.L[k];
+        fl[mp + k] = J.f.U[k];
+      }
+      for (int k = tid; k < m; k += kNT) fl[2 * mp + k] = J.f.rd[k];
+      __syncthreads();
+      staged = jb;
+    }
+    const int line0 = ((grp - J.tile0) * kWaves + wv) * W;
+    if (line0 >= J.nlines) continue;   // the job's last group may be partial
     const int nl = min(W, J.nlines - line0);
     const bool lact = ll < nl;
     long long base = 0, stride = 0;
@@ -162,19 +182,19 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(const LaunchHdr* __restrict_
       // x-lines: the nl lines of the tile are one contiguous block of nl*m
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
-      for (int f0 = 0; f0 < tot; f0 += kChunk * kNT) {
+      for (int f0 = 0; f0 < tot; f0 += kChunk * 64) {
         double r[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          int fidx = f0 + k * kNT + tid;
+          const int fidx = f0 + k * 64 + lane;
           r[k] = fidx < tot ? J.in[gb + fidx] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          int fidx = f0 + k * kNT + tid;
+          const int fidx = f0 + k * 64 + lane;
           if (fidx < tot) {
-            int l = fidx / m, i = fidx - l * m;
-            lds[sidx<W>(i, l)] = J.scale * r[k];
+            const int l = fidx / m, i = fidx - l * m;
+            tl[sidx<W>(i, l)] = J.scale * r[k];
           }
         }
       }
@@ -183,49 +203,39 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(const LaunchHdr* __restrict_
         double r[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          int i = i0 + k * RL;
+          const int i = i0 + k * RL;
           r[k] = i < m ? J.in[base + (long long)i * stride] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          int i = i0 + k * RL;
-          if (i < m) lds[sidx<W>(i, ll)] = J.scale * r[k];
+          const int i = i0 + k * RL;
+          if (i < m) tl[sidx<W>(i, ll)] = J.scale * r[k];
         }
       }
     }
-    // stage the factor rows behind the tile (read as LDS broadcasts)
-    double* fl = lds + W * m;
-    {
-      const int mp = m * J.p;
-      for (int k = tid; k < mp; k += kNT) {
-        fl[k] = J.f.L[k];
-        fl[mp + k] = J.f.U[k];
-      }
-      for (int k = tid; k < m; k += kNT) fl[2 * mp + k] = J.f.rd[k];
-    }
-    __syncthreads();
-    if (tid < nl) {
+    wave_sync_sw();
+    if (lane < nl) {
       switch (J.p) {
-        case 1: substitute<W, 1>(lds, tid, m, fl); break;
-        case 2: substitute<W, 2>(lds, tid, m, fl); break;
-        default: substitute<W, 3>(lds, tid, m, fl); break;
+        case 1: substitute<W, 1>(tl, lane, m, fl); break;
+        case 2: substitute<W, 2>(tl, lane, m, fl); break;
+        default: substitute<W, 3>(tl, lane, m, fl); break;
       }
     }
-    __syncthreads();
+    wave_sync_sw();
     if (J.dir == 0) {
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
-      for (int f0 = 0; f0 < tot; f0 += kEpi * kNT) {
+      for (int f0 = 0; f0 < tot; f0 += kEpi * 64) {
         long long g[kEpi];
         double x[kEpi];
         bool ok[kEpi];
 #pragma unroll
         for (int k = 0; k < kEpi; ++k) {
-          int fidx = f0 + k * kNT + tid;
+          const int fidx = f0 + k * 64 + lane;
           ok[k] = fidx < tot;
-          int l = ok[k] ? fidx / m : 0, i = ok[k] ? fidx - l * m : 0;
+          const int l = ok[k] ? fidx / m : 0, i = ok[k] ? fidx - l * m : 0;
           g[k] = gb + fidx;
-          x[k] = ok[k] ? lds[sidx<W>(i, l)] : 0.0;
+          x[k] = ok[k] ? tl[sidx<W>(i, l)] : 0.0;
         }
         epilogue_batch(J, g, x, ok);
       }
@@ -236,68 +246,87 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(const LaunchHdr* __restrict_
         bool ok[kEpi];
 #pragma unroll
         for (int k = 0; k < kEpi; ++k) {
-          int i = i0 + k * RL;
+          const int i = i0 + k * RL;
           ok[k] = i < m;
           g[k] = base + (long long)i * stride;
-          x[k] = ok[k] ? lds[sidx<W>(i, ll)] : 0.0;
+          x[k] = ok[k] ? tl[sidx<W>(i, ll)] : 0.0;
         }
         epilogue_batch(J, g, x, ok);
       }
     }
-    if (t == 0 && tid == 0 && J.counter != nullptr) *J.counter += 1ull;
-    __syncthreads();
+    if (line0 == 0 && lane == 0 && J.counter != nullptr) *J.counter += 1ull;
+    // the next tile of this wave overwrites the tile region: every lane's
+    // epilogue reads of it come first
+    wave_sync_sw();
   }
 }
 
-// Lines per tile (16, 32 or 64; ADS_SWEEP_W overrides the default 16).
-int sweep_width() {
-  static int w = [] {
-    const char* e = std::getenv("ADS_SWEEP_W");
-    int v = e ? std::atoi(e) : 16;
-    return (v == 32 || v == 64) ? v : 16;
-  }();
-  return w;
+// Dynamic LDS of a workgroup: the factor rows (2p+1 <= 7 per line position)
+// and kWaves tiles of W lines x max_m.
+static size_t sweep_lds_bytes(int W, int max_m) {
+  return (size_t)(2 * kMaxP + 1 + kWaves * W) * max_m * sizeof(double);
 }
-int sweep_width_for(int) { return sweep_width(); }
 
-// Dynamic LDS: the tile (W lines x m) + the factor rows (2p+1 <= 7 per
-// line position).
-static size_t sweep_lds_bytes(int W, int max_m) { return (size_t)(W + 2 * kMaxP + 1) * max_m * sizeof(double); }
-
-// Resident sweep blocks per CU for lines of at most max_m unknowns (the
-// persistent grid of a merged launch is this times the CU count).
-int sweep_blocks_per_cu(int max_m) {
-  const int W = sweep_width();
+// Resident workgroups per CU for lines of at most max_m unknowns.
+static int sweep_resident(int W, int max_m) {
   const size_t lds = sweep_lds_bytes(W, max_m);
   int n = 0;
   hipError_t e;
-  if (W == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<64>, kNT, lds);
-  else if (W == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<32>, kNT, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<16>, kNT, lds);
-  return (e == hipSuccess && n > 0) ? n : 2;
+  if (W == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<16>, kNT, lds);
+  else if (W == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<8>, kNT, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<4>, kNT, lds);
+  const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds, 1));
+  if (e != hipSuccess || n <= 0) n = by_lds;
+  return std::max(1, std::min(n, by_lds));
 }
 
-hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int max_m, hipStream_t s) {
-  const int W = sweep_width();
+// Tile width for a launch over `lines` lines of at most max_m unknowns on
+// ncu CUs.  Measured on 128-long lines: W = 16 (rows of 128 contiguous
+// bytes in the y/z access) beats 8 and 4 both for one 128^3 simulation and
+// for a batch of four, so it is the default; narrower tiles remain for
+// launches with too few lines to give every CU a group (ADS_SWEEP_W = 4, 8
+// or 16 overrides).
+int sweep_width_for(long long lines, int max_m, int ncu) {
+  static const int forced = [] {
+    const char* e = std::getenv("ADS_SWEEP_W");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 4 || v == 8 || v == 16) ? v : 0;
+  }();
+  (void)max_m;
+  if (forced) return forced;
+  for (int W : {16, 8}) {
+    if (lines >= (long long)ncu * kWaves * W) return W;
+  }
+  return 4;
+}
+
+// Groups of 4W lines in a job of `lines` lines.
+int sweep_groups(long long lines, int W) { return (int)((lines + (long long)kWaves * W - 1) / (kWaves * W)); }
+
+int sweep_blocks_per_cu(int W, int max_m) { return sweep_resident(W, max_m); }
+
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hipStream_t s) {
   const size_t lds = sweep_lds_bytes(W, max_m);
   if (grid <= 0) return hipSuccess;
-  if (W == 64) {
-    hipLaunchKernelGGL(sweep_kernel<64>, dim3(grid), dim3(kNT), lds, s, d_hdr);
-  } else if (W == 32) {
-    hipLaunchKernelGGL(sweep_kernel<32>, dim3(grid), dim3(kNT), lds, s, d_hdr);
+  if (W == 16) {
+    hipLaunchKernelGGL(sweep_kernel<16>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
+  } else if (W == 8) {
+    hipLaunchKernelGGL(sweep_kernel<8>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
+  } else if (W == 4) {
+    hipLaunchKernelGGL(sweep_kernel<4>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
   } else {
-    hipLaunchKernelGGL(sweep_kernel<16>, dim3(grid), dim3(kNT), lds, s, d_hdr);
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t sweep_set_attributes() {
   hipError_t e;
-  e = hipFuncSetAttribute((const void*)sweep_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  e = hipFuncSetAttribute((const void*)sweep_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)sweep_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  e = hipFuncSetAttribute((const void*)sweep_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)sweep_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return hipFuncSetAttribute((const void*)sweep_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 }  // namespace ads

@@ -7,10 +7,13 @@ namespace ads {
 
 // Launchers take the device header of a job table (LaunchHdr followed by
 // the jobs) and a grid size (all tiles, or a persistent grid that loops).
-int sweep_width_for(int max_m);
-hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int max_m, hipStream_t s);
+// Sweeps: a workgroup takes groups of 4W lines (one W-line tile per wave);
+// job tile counts are in groups.
+int sweep_width_for(long long lines, int max_m, int ncu);
+int sweep_groups(long long lines, int W);
+int sweep_blocks_per_cu(int W, int max_m);
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hipStream_t s);
 hipError_t sweep_set_attributes();
-int sweep_blocks_per_cu(int max_m);
 
 int rhs_num_variants(int p);
 int rhs_tile_x(int p);
