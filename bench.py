@@ -184,6 +184,74 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
     }
 
 
+def measure_elastic(cfg, steps, warmup):
+    """Elasticity (alternating-triangular step), one FP64 simulation."""
+    import torch
+    from paper_1911_08158_amd import Sim
+    sim = Sim(cfg, device="cuda:0", precision="fp64")
+    setup_sim(sim, cfg)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, kinds, step_ms = sim.profile_read(steps)
+    sim.check_finite()
+    sim.close()
+    per = {}
+    for k, m in zip(kinds, ms):
+        per[k] = round(per.get(k, 0.0) + float(m), 5)
+    return {
+        "workload": f"elasticity {cfg.nelem[0]}^3 elements p={cfg.p} (3 x {cfg.n[0]}^3 DOFs) tau={cfg.tau}, FP64",
+        "dof_steps_per_s": cfg.dofs() * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "ms_per_step_by_kind": per,
+        "step_ms_p99": float(np.percentile(step_ms, 99)),
+    }
+
+
+def measure_serving(nreq, pool_gib, max_slots):
+    """The serving mix through one pool: first closed loop (every request
+    queued at t = 0) for the saturation request rate, then Poisson arrivals
+    at 0.8 of it.  Initial states are the seeded data sampled at the
+    Greville abscissae (no per-request projection)."""
+    import torch
+
+    import workloads as W
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.serve import serve
+
+    def setup(sim, cfg):
+        sim.set_state(torch.from_numpy(W.initial_coefficients(cfg)).to("cuda:0"), None, None, 0)
+        sim.factor()
+
+    def steps_of(req):
+        return req.cfg.steps
+
+    def dofs_of(req):
+        return req.cfg.dofs()
+
+    pool = Pool(int(pool_gib * (1 << 30)), max_slots=max_slots, device="cuda:0")
+    base = W.serving_mix(nreq)
+    closed = [W.Request(r.rid, 0.0, r.cfg) for r in base]
+    _, st_closed = serve(pool, closed, setup, steps_of, dofs_of)
+    sat = nreq / st_closed["wall_s"]
+    arrivals = W.serving_mix(nreq, rate=0.8 * sat)
+    _, st = serve(pool, arrivals, setup, steps_of, dofs_of)
+    pool.close()
+    npw = sum(1 for r in base if r.cfg.problem == "pwave")
+    return {
+        "workload": f"{nreq} requests: P-wave (mixed) / elasticity (FP64) {npw}/{nreq - npw}, "
+                    "E_d in {32,48,64,96} per direction, p in {2,3}, tau in {1e-3,5e-3}, 50 steps",
+        "pool_gib": pool_gib, "max_slots": max_slots,
+        "saturation_requests_per_s": sat,
+        "closed_loop": st_closed,
+        "poisson_0p8": st,
+    }
+
+
 def cpu_baseline(cfg, seconds):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     setup and the start are untimed; steps are timed until ``seconds``
@@ -233,7 +301,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched"], default=None,
+    ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic"], default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -252,6 +322,12 @@ def main():
     if args.only == "batched":
         print(json.dumps({"form": "batched_mixed", **measure_batched(cfg.with_(precision="mixed_fp32"), args.batch,
                                                                      args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "serve":
+        print(json.dumps({"form": "serving", **measure_serving(args.requests, 16, 64)}), flush=True)
+        return
+    if args.only == "elastic":
+        print(json.dumps({"form": "elastic", **measure_elastic(W.C4, args.steps, args.warmup)}), flush=True)
         return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
@@ -289,6 +365,9 @@ def main():
                                     "unit": "TFLOP/s", "frac": round(rhs64["tflops"] / FP64_PEAK_TFLOPS, 4)},
         "gpu": gpu_info(),
     }
+    out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup)
+    if not args.no_serving:
+        out["serving"] = measure_serving(args.requests, 16, 64)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -363,6 +363,12 @@ void set_zchunks(RhsJob& J, int nfz, int k) {
   J.ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
 }
 
+void set_kron_zchunks(KronJob& K, int k) {
+  K.TZ = (K.nz + k - 1) / k;
+  K.tiles[2] = (K.nz + K.TZ - 1) / K.TZ;
+  K.ntiles = K.tiles[0] * K.tiles[1] * K.tiles[2];
+}
+
 // Tiling of one right-hand-side job.  resident > 0: z-chunks chosen for that
 // many resident workgroups; otherwise enough tiles to cover the chip twice.
 void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident = 0) {
@@ -436,7 +442,11 @@ KronJob kron_base(const ads_sim* s, double* out, const double* base, double alph
   K.nz = s->nf[2];
   K.nterm = 0;
   K.tile0 = 0;
-  K.ntiles = (int)((s->nfree + kron_tile_points() - 1) / kron_tile_points());
+  K.tiles[0] = (K.nx + kron_tile_x() - 1) / kron_tile_x();
+  K.tiles[1] = (K.ny + kron_tile_y() - 1) / kron_tile_y();
+  // a tile walks TZ + 2p source layers
+  set_kron_zchunks(K, best_zchunks({{(long long)K.tiles[0] * K.tiles[1], K.nz}}, 2 * K.p,
+                                   (long long)kron_blocks_per_cu() * s->ncu));
   return K;
 }
 
@@ -1083,7 +1093,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
     }
   for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
-    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, 8 * ncu, sizeof(KronJob));
+    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
     else add(Launch::SWEEP, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
@@ -1121,6 +1131,18 @@ ads_status pool_rebuild(ads_pool* P) {
         RhsJob* r = (RhsJob*)j.data();
         set_zchunks(*r, r->nf[2], k);
       }
+    }
+    // couplings: z-chunks chosen for the whole batch on the persistent grid
+    if (L.kind == Launch::KRON && !sel.empty()) {
+      std::vector<std::pair<long long, int>> xy_nfz;
+      int pmax = 2;
+      for (const auto& j : sel) {
+        const KronJob* r = (const KronJob*)j.data();
+        xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nz});
+        pmax = std::max(pmax, r->p);
+      }
+      const int k = best_zchunks(xy_nfz, 2 * pmax, L.grid);
+      for (auto& j : sel) set_kron_zchunks(*(KronJob*)j.data(), k);
     }
     // sweeps: tile width and persistent grid for the batch's line count
     if (L.kind == Launch::SWEEP && !sel.empty()) {

@@ -101,6 +101,8 @@ struct KronJob {
   int nterm;
   int p;
   int nx, ny, nz;
+  int TZ;           // output z-layers per tile
+  int tiles[3];     // tiles per direction (x, y: column tiles; z: chunks)
   int tile0, ntiles;
 };
 

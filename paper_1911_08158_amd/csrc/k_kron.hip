@@ -5,13 +5,23 @@
 //
 //   out = alpha * base + sum_t coef_t * (T^t_x (x) T^t_y (x) T^t_z) src_t
 //
-// One thread per output coefficient; the (2p+1)^3 stencil is evaluated by
-// sum factorization in registers (x-rows, then y, then z).
+// Sum factorization on gfx950: a workgroup owns a KTX x KTY column tile and
+// a z-range of outputs and walks the source layers that reach the range.
+// Per source layer and term it stages the layer (with a p-halo in x and y)
+// in LDS, applies the x-band (LDS -> LDS), then the y-band (one thread per
+// owned column) and scatters the result through the z-band into 2p+1
+// register accumulators (outputs zs-p .. zs+p); the oldest accumulator is
+// complete after each layer and is written out.  The next layer's global
+// loads are in flight while the current one is contracted.  The band rows
+// of every term for the tile's columns are staged once per tile.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ads {
 
-constexpr int kKronPts = 256;
+constexpr int KTX = 32, KTY = 8, KNT = KTX * KTY;
+constexpr int kKronMaxTerms = 6;   // KronJob::term
 
 __device__ __forceinline__ int find_job_kron(const KronJob* jobs, int njobs, int tile) {
   int lo = 0, hi = njobs - 1;
@@ -23,59 +33,149 @@ __device__ __forceinline__ int find_job_kron(const KronJob* jobs, int njobs, int
 }
 
 template <int p>
-__device__ double kron_term(const KronTerm& T, int x, int y, int z, int nx, int ny, int nz) {
-  constexpr int B = 2 * p + 1;
-  const double* Tx = T.T[0] + (long long)x * B;
-  const double* Ty = T.T[1] + (long long)y * B;
-  const double* Tz = T.T[2] + (long long)z * B;
-  double sz = 0.0;
-  for (int c = -p; c <= p; ++c) {
-    int zz = z + c;
-    if (zz < 0 || zz >= nz) continue;
-    double sy = 0.0;
-    for (int b = -p; b <= p; ++b) {
-      int yy = y + b;
-      if (yy < 0 || yy >= ny) continue;
-      const double* row = T.src + ((long long)zz * ny + yy) * nx;
-      double sx = 0.0;
-#pragma unroll
-      for (int a = -p; a <= p; ++a) {
-        int xx = x + a;
-        if (xx >= 0 && xx < nx) sx = fma(Tx[a + p], row[xx], sx);
-      }
-      sy = fma(Ty[b + p], sx, sy);
+struct KronGeom {
+  static constexpr int B = 2 * p + 1;
+  static constexpr int SX = KTX + 2 * p, SY = KTY + 2 * p;
+  static constexpr int NS = (SY * SX + KNT - 1) / KNT;   // layer loads per thread
+  static constexpr int NX = (SY * KTX + KNT - 1) / KNT;  // x-band items per thread
+  // LDS: S [SY][SX], X [SY][KTX], band rows [terms][KTX + KTY][B]
+  static constexpr size_t lds_elems = (size_t)SY * SX + SY * KTX + (size_t)kKronMaxTerms * (KTX + KTY) * B;
+};
+
+template <int p>
+__device__ void kron_tile(const KronJob& J, int t, double* lds) {
+  using Gm = KronGeom<p>;
+  constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NX = Gm::NX;
+  double* S = lds;
+  double* X = S + SY * SX;
+  double* Tb = X + SY * KTX;
+  const int tid = threadIdx.x, lx = tid % KTX, ly = tid / KTX;
+  const int tx = t % J.tiles[0], t2 = t / J.tiles[0];
+  const int ty = t2 % J.tiles[1], tz = t2 / J.tiles[1];
+  const int nx = J.nx, ny = J.ny, nz = J.nz, nt = J.nterm;
+  const int X0 = tx * KTX, Y0 = ty * KTY, Z0 = tz * J.TZ, Z1 = min(Z0 + J.TZ, nz);
+  // band rows of every term for the tile's x and y indices (zero outside)
+  for (int k = tid; k < nt * (KTX + KTY) * B; k += KNT) {
+    const int term = k / ((KTX + KTY) * B), r = k - term * ((KTX + KTY) * B);
+    const int row = r / B, c = r - row * B;
+    double v = 0.0;
+    if (row < KTX) {
+      const int x = X0 + row;
+      if (x < nx) v = J.term[term].T[0][(long long)x * B + c];
+    } else {
+      const int y = Y0 + row - KTX;
+      if (y < ny) v = J.term[term].T[1][(long long)y * B + c];
     }
-    sz = fma(Tz[c + p], sy, sz);
+    Tb[k] = v;
   }
-  return sz;
+  // source-layer loads of this thread: positions k = tid + i*KNT of [SY][SX]
+  long long soff[NS];
+  bool sval[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int k = tid + i * KNT;
+    const int yy = k / SX, xx = k - yy * SX;
+    const int x = X0 - p + xx, y = Y0 - p + yy;
+    sval[i] = k < SY * SX && x >= 0 && x < nx && y >= 0 && y < ny;
+    soff[i] = (long long)y * nx + x;
+  }
+  const long long sxy = (long long)nx * ny;
+  double pf[NS];
+  auto prefetch = [&](int zs, int term) {
+    const double* src = J.term[term].src + (long long)zs * sxy;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pf[i] = sval[i] ? src[soff[i]] : 0.0;
+  };
+  const bool ocol = X0 + lx < nx && Y0 + ly < ny;
+  const long long obase = (long long)(Y0 + ly) * nx + X0 + lx;
+  auto store = [&](int z, double v) {
+    if (ocol && z >= Z0 && z < Z1) {
+      const long long g = (long long)z * sxy + obase;
+      J.out[g] = (J.base != nullptr) ? fma(J.alpha, J.base[g], v) : v;
+    }
+  };
+  double acc[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) acc[k] = 0.0;
+  // window: acc[k] is output z = zs - p + k
+  const int zs0 = max(0, Z0 - p), zs1 = min(nz - 1, Z1 - 1 + p);
+  prefetch(zs0, 0);
+  for (int zs = zs0; zs <= zs1; ++zs) {
+    for (int term = 0; term < nt; ++term) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int k = tid + i * KNT;
+        if (k < SY * SX) S[k] = pf[i];
+      }
+      __syncthreads();
+      // next (layer, term) in flight during the contractions
+      if (term + 1 < nt) prefetch(zs, term + 1);
+      else if (zs < zs1) prefetch(zs + 1, 0);
+      const double* tbx = Tb + term * ((KTX + KTY) * B);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        const int k = tid + i * KNT;
+        if (k < SY * KTX) {
+          const int yy = k / KTX, xo = k - yy * KTX;
+          const double* srow = S + yy * SX + xo;
+          double s = tbx[xo * B] * srow[0];
+#pragma unroll
+          for (int a = 1; a < B; ++a) s = fma(tbx[xo * B + a], srow[a], s);
+          X[k] = s;
+        }
+      }
+      __syncthreads();
+      const double* tby = tbx + KTX * B + ly * B;
+      double sy = tby[0] * X[ly * KTX + lx];
+#pragma unroll
+      for (int b = 1; b < B; ++b) sy = fma(tby[b], X[(ly + b) * KTX + lx], sy);
+      sy *= J.term[term].coef;
+      const double* Tz = J.term[term].T[2];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int z = zs - p + k;
+        if (z >= 0 && z < nz) acc[k] = fma(Tz[(long long)z * B + (2 * p - k)], sy, acc[k]);
+      }
+    }
+    // output zs - p has all its source layers
+    store(zs - p, acc[0]);
+#pragma unroll
+    for (int k = 0; k < B - 1; ++k) acc[k] = acc[k + 1];
+    acc[B - 1] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < B - 1; ++k) store(zs1 + 1 - p + k, acc[k]);
+  __syncthreads();   // LDS is reused by the next tile
 }
 
-__global__ __launch_bounds__(kKronPts) void kron_kernel(const LaunchHdr* __restrict__ hdr) {
+// Jobs of both degrees may share a launch: the degree is taken per tile.
+__global__ __launch_bounds__(KNT) void kron_kernel(const LaunchHdr* __restrict__ hdr) {
+  extern __shared__ double lds[];
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const KronJob* __restrict__ jobs = hdr_jobs<KronJob>(hdr);
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const KronJob& J = jobs[find_job_kron(jobs, njobs, tile)];
-    const long long idx = (long long)(tile - J.tile0) * kKronPts + threadIdx.x;
-    const long long n = (long long)J.nx * J.ny * J.nz;
-    if (idx >= n) continue;
-    const int x = (int)(idx % J.nx);
-    const long long r = idx / J.nx;
-    const int y = (int)(r % J.ny), z = (int)(r / J.ny);
-    double s = (J.base != nullptr) ? J.alpha * J.base[idx] : 0.0;
-    for (int t = 0; t < J.nterm; ++t) {
-      double v = (J.p == 2) ? kron_term<2>(J.term[t], x, y, z, J.nx, J.ny, J.nz)
-                            : kron_term<3>(J.term[t], x, y, z, J.nx, J.ny, J.nz);
-      s = fma(J.term[t].coef, v, s);
-    }
-    J.out[idx] = s;
+    if (J.p == 2) kron_tile<2>(J, tile - J.tile0, lds);
+    else kron_tile<3>(J, tile - J.tile0, lds);
   }
 }
 
-int kron_tile_points() { return kKronPts; }
+int kron_tile_x() { return KTX; }
+int kron_tile_y() { return KTY; }
+
+// LDS of the larger degree (a launch may mix degrees)
+static size_t kron_lds_bytes() { return std::max(KronGeom<2>::lds_elems, KronGeom<3>::lds_elems) * sizeof(double); }
+
+int kron_blocks_per_cu() {
+  int n = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kron_kernel, KNT, kron_lds_bytes());
+  return (e == hipSuccess && n > 0) ? n : 2;
+}
 
 hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kron_kernel, dim3(grid), dim3(kKronPts), 0, s, d_hdr);
+  hipLaunchKernelGGL(kron_kernel, dim3(grid), dim3(KNT), kron_lds_bytes(), s, d_hdr);
   return hipGetLastError();
 }
 

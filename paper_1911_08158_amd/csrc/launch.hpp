@@ -25,7 +25,9 @@ int rhs_el_tile_y(int p);
 hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 
 hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s);
-int kron_tile_points();
+int kron_tile_x();
+int kron_tile_y();
+int kron_blocks_per_cu();
 
 hipError_t launch_full_to_free(const double* full, double* fr, const int n[3], const int nf[3],
                                const int off[3], int ncomp, hipStream_t s);
