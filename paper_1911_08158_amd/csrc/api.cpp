@@ -221,7 +221,8 @@ void geometry(ads_sim* s) {
 void carve(ads_sim* s, Carver& c) {
   const long long nfr = s->nfree;
   const int P = s->P, q = s->q, p = s->p;
-  for (int d = 0; d < 3; ++d) s->d_tab[d] = c.dbl((size_t)2 * s->E[d] * q * P + (size_t)s->E[d] * q);
+  // per direction: N, D [E][q][P], W [E][q], then W*N, W*D [E][q][P]
+  for (int d = 0; d < 3; ++d) s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q);
   auto fac = [&](DevFactor& f, int d) {
     f.m = s->nf[d];
     f.L = c.dbl((size_t)f.m * p);
@@ -710,6 +711,8 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
     buf.insert(buf.end(), t.N.begin(), t.N.end());
     buf.insert(buf.end(), t.D.begin(), t.D.end());
     buf.insert(buf.end(), t.W.begin(), t.W.end());
+    for (const std::vector<double>* v : {&t.N, &t.D})
+      for (size_t k = 0; k < v->size(); ++k) buf.push_back(t.W[k / s->P] * (*v)[k]);
     if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return cleanup(st);
     if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return cleanup(st);
     if (s->elastic) {

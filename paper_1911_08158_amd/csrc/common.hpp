@@ -79,7 +79,7 @@ struct RhsJob {
   const unsigned long long* counter;
   double rscale;          // R = rscale * (amp * load - A(w))
   double lam, mu;         // elasticity Lame constants
-  const double* tab[3];   // per direction: N[E][q][P], D[E][q][P], W[E][q]
+  const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P]
   int E[3], nf[3], off[3];
   int tiles[3];           // tiles along x, y, and z-chunks
   int TZ;                 // owned z-coefficients per chunk

@@ -470,15 +470,13 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_p
         __syncthreads();
         // (B) y-backward and z-backward into the owned column's accumulators
         if (own) {
-          // backward z tables at this Gauss point, z-weight folded in
+          // backward z tables at this Gauss point (weighted tables W*N, W*D)
+          const double* tw = tzg + (2ll * Ez * Q * P + (long long)Ez * Q) + ((long long)ez * Q + gz) * P;
           double nzw[P], dzw[P];
-          {
-            const double w = tzg[2ll * Ez * Q * P + (long long)ez * Q + gz];
 #pragma unroll
-            for (int a = 0; a < P; ++a) {
-              nzw[a] = w * tzg[((long long)ez * Q + gz) * P + a];
-              dzw[a] = w * tzg[((long long)(Ez + ez) * Q + gz) * P + a];
-            }
+          for (int a = 0; a < P; ++a) {
+            nzw[a] = tw[a];
+            dzw[a] = tw[(long long)Ez * Q * P + a];
           }
           T Ap = T(0), Bp = T(0);
 #pragma unroll
