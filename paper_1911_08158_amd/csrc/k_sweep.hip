@@ -5,7 +5,7 @@
 // Mapping on gfx950: a workgroup is four wave64s and takes a group of 4W
 // consecutive lines of one job; each wave owns a tile of W lines (W = 16,
 // or 8 / 4 for launches with few lines).  The wave
-// stages its tile in LDS [i][line] with an XOR swizzle: x-lines (contiguous
+// stages its tile in LDS [i][line] (rows padded to W+1): x-lines (contiguous
 // in memory) as one flat cooperative block, y- and z-lines with 64/W lanes
 // per line so that each load reads 64/W rows of W consecutive x.  The first
 // W lanes then run the substitution, one line each, reading the factor rows
@@ -38,10 +38,14 @@ __device__ __forceinline__ void wave_sync_sw() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Tile layout in LDS: row i (one value per line) at i*(W+1): the padding
+// makes both the row reads of the substitution (W consecutive values) and
+// the column writes of the x-line staging (stride W+1) free of bank
+// conflicts, and every access an immediate offset from one base.
 template <int W>
-__device__ __forceinline__ int sidx(int i, int l) { return i * W + (l ^ (i & (W - 1))); }
+__device__ __forceinline__ int sidx(int i, int l) { return i * (W + 1) + l; }
 
-constexpr int kChunk = 8;    // global loads in flight per lane while staging a tile
+constexpr int kChunk = 16;   // global loads in flight per lane while staging a tile
 constexpr int kWaves = 4;    // waves per workgroup (one tile each)
 constexpr int kNT = 64 * kWaves;
 
@@ -104,48 +108,96 @@ __device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long lon
 
 // Forward (L, unit diagonal) then backward (U) substitution on one lane's
 // line held in LDS.  The dependency chain per step is a single FMA on the
-// most recent value; the older terms are folded in first.
+// most recent value; the older terms are folded in first.  Rows go in
+// blocks of kSB: the block's values and factor rows are read into registers
+// first (one LDS wait per block), the chain runs in registers, the results
+// are written back.
+constexpr int kSB = 8;
+
 template <int W, int P>
 __device__ __forceinline__ void substitute(double* tl, int lane, int m, const double* fl) {
-  constexpr int p = P;
+  constexpr int TP = W + 1;
   // factor rows: L[m*p], U[m*p], rd[m]
   const double* Lf = fl;
-  const double* Uf = fl + m * p;
-  const double* rdf = fl + 2 * m * p;
-  double h[p];
+  const double* Uf = fl + m * P;
+  const double* rdf = fl + 2 * m * P;
+  const int nb = m / kSB;          // full blocks; rows nb*kSB .. m-1 are the tail
+  double h[P];
 #pragma unroll
-  for (int k = 0; k < p; ++k) h[k] = 0.0;
-#pragma unroll 8
-  for (int i = 0; i < m; ++i) {
-    const double* Li = Lf + i * p;
-    double s = tl[sidx<W>(i, lane)];
+  for (int k = 0; k < P; ++k) h[k] = 0.0;
+  double* col = tl + lane;
+  for (int b = 0; b < nb; ++b) {
+    double* rb = col + b * kSB * TP;
+    const double* Lb = Lf + b * kSB * P;
+    double v[kSB], f[kSB][P];
 #pragma unroll
-    for (int k = p - 1; k >= 0; --k) s = fma(-Li[k], h[k], s);
+    for (int k = 0; k < kSB; ++k) {
+      v[k] = rb[k * TP];
 #pragma unroll
-    for (int k = p - 1; k > 0; --k) h[k] = h[k - 1];
+      for (int j = 0; j < P; ++j) f[k][j] = Lb[k * P + j];
+    }
+#pragma unroll
+    for (int k = 0; k < kSB; ++k) {
+      double s = v[k];
+#pragma unroll
+      for (int j = P - 1; j >= 0; --j) s = fma(-f[k][j], h[j], s);
+#pragma unroll
+      for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+      h[0] = s;
+      rb[k * TP] = s;
+    }
+  }
+  for (int i = nb * kSB; i < m; ++i) {
+    double s = col[i * TP];
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) s = fma(-Lf[i * P + j], h[j], s);
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
     h[0] = s;
-    tl[sidx<W>(i, lane)] = s;
+    col[i * TP] = s;
   }
 #pragma unroll
-  for (int k = 0; k < p; ++k) h[k] = 0.0;
-#pragma unroll 8
-  for (int i = m - 1; i >= 0; --i) {
-    const double* Ui = Uf + i * p;
-    double s = tl[sidx<W>(i, lane)];
+  for (int k = 0; k < P; ++k) h[k] = 0.0;
+  for (int i = m - 1; i >= nb * kSB; --i) {
+    double s = col[i * TP];
 #pragma unroll
-    for (int k = p - 1; k >= 0; --k) s = fma(-Ui[k], h[k], s);
+    for (int j = P - 1; j >= 0; --j) s = fma(-Uf[i * P + j], h[j], s);
     s *= rdf[i];
 #pragma unroll
-    for (int k = p - 1; k > 0; --k) h[k] = h[k - 1];
+    for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
     h[0] = s;
-    tl[sidx<W>(i, lane)] = s;
+    col[i * TP] = s;
+  }
+  for (int b = nb - 1; b >= 0; --b) {
+    double* rb = col + b * kSB * TP;
+    const double* Ub = Uf + b * kSB * P;
+    const double* rdb = rdf + b * kSB;
+    double v[kSB], f[kSB][P], r[kSB];
+#pragma unroll
+    for (int k = 0; k < kSB; ++k) {
+      v[k] = rb[k * TP];
+      r[k] = rdb[k];
+#pragma unroll
+      for (int j = 0; j < P; ++j) f[k][j] = Ub[k * P + j];
+    }
+#pragma unroll
+    for (int k = kSB - 1; k >= 0; --k) {
+      double s = v[k];
+#pragma unroll
+      for (int j = P - 1; j >= 0; --j) s = fma(-f[k][j], h[j], s);
+      s *= r[k];
+#pragma unroll
+      for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+      h[0] = s;
+      rb[k * TP] = s;
+    }
   }
 }
 
 // Job tiling: SweepJob.tile0 / ntiles count groups of 4W lines; the header's
 // total_tiles is the number of groups of the launch.
 template <int W>
-__global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restrict__ hdr, int max_m) {
+__global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restrict__ hdr, int max_m) {
   static_assert(64 % W == 0, "W must divide the wave size");
   constexpr int RL = 64 / W;   // lanes per line in the cooperative y/z access
   extern __shared__ double lds[];
@@ -155,7 +207,7 @@ __global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restri
   const int lane = tid & 63, wv = tid >> 6;
   const int ll = lane % W, lq = lane / W;   // cooperative y/z access: line ll, row phase lq
   double* fl = lds;                                             // factor rows
-  double* tl = lds + (2 * kMaxP + 1) * max_m + wv * W * max_m;  // this wave's tile
+  double* tl = lds + (2 * kMaxP + 1) * max_m + wv * (W + 1) * max_m;  // this wave's tile
   int staged = -1;                                              // job whose factor is in LDS
   for (int grp = blockIdx.x; grp < total_groups; grp += gridDim.x) {
     const int jb = find_job_sweep(jobs, njobs, grp);
@@ -182,49 +234,49 @@ __global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restri
       // x-lines: the nl lines of the tile are one contiguous block of nl*m
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
+      int l = lane / m, i = lane - l * m;   // (line, row) of flat index f0 + lane
       for (int f0 = 0; f0 < tot; f0 += kChunk * 64) {
-        double r[kChunk];
+        double c[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
           const int fidx = f0 + k * 64 + lane;
-          r[k] = fidx < tot ? J.in[gb + fidx] : 0.0;
+          c[k] = fidx < tot ? J.in[gb + fidx] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          const int fidx = f0 + k * 64 + lane;
-          if (fidx < tot) {
-            const int l = fidx / m, i = fidx - l * m;
-            tl[sidx<W>(i, l)] = J.scale * r[k];
+          if (f0 + k * 64 + lane < tot) tl[sidx<W>(i, l)] = J.scale * c[k];
+          i += 64;
+          while (i >= m) {   // at most once for m >= 64
+            i -= m;
+            ++l;
           }
         }
       }
     } else if (lact) {
       for (int i0 = lq; i0 < m; i0 += kChunk * RL) {
-        double r[kChunk];
+        double c[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
           const int i = i0 + k * RL;
-          r[k] = i < m ? J.in[base + (long long)i * stride] : 0.0;
+          c[k] = i < m ? J.in[base + (long long)i * stride] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
           const int i = i0 + k * RL;
-          if (i < m) tl[sidx<W>(i, ll)] = J.scale * r[k];
+          if (i < m) tl[sidx<W>(i, ll)] = J.scale * c[k];
         }
       }
     }
     wave_sync_sw();
     if (lane < nl) {
-      switch (J.p) {
-        case 1: substitute<W, 1>(tl, lane, m, fl); break;
-        case 2: substitute<W, 2>(tl, lane, m, fl); break;
-        default: substitute<W, 3>(tl, lane, m, fl); break;
-      }
+      if (J.p == 2) substitute<W, 2>(tl, lane, m, fl);
+      else substitute<W, 3>(tl, lane, m, fl);
     }
     wave_sync_sw();
     if (J.dir == 0) {
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
+      int l = lane / m, i = lane - l * m;   // (line, row) of flat index f0 + lane
       for (int f0 = 0; f0 < tot; f0 += kEpi * 64) {
         long long g[kEpi];
         double x[kEpi];
@@ -233,9 +285,13 @@ __global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restri
         for (int k = 0; k < kEpi; ++k) {
           const int fidx = f0 + k * 64 + lane;
           ok[k] = fidx < tot;
-          const int l = ok[k] ? fidx / m : 0, i = ok[k] ? fidx - l * m : 0;
           g[k] = gb + fidx;
           x[k] = ok[k] ? tl[sidx<W>(i, l)] : 0.0;
+          i += 64;
+          while (i >= m) {
+            i -= m;
+            ++l;
+          }
         }
         epilogue_batch(J, g, x, ok);
       }
@@ -262,9 +318,9 @@ __global__ __launch_bounds__(kNT, 4) void sweep_kernel(const LaunchHdr* __restri
 }
 
 // Dynamic LDS of a workgroup: the factor rows (2p+1 <= 7 per line position)
-// and kWaves tiles of W lines x max_m.
+// and kWaves tiles of max_m rows of pitch W + 1.
 static size_t sweep_lds_bytes(int W, int max_m) {
-  return (size_t)(2 * kMaxP + 1 + kWaves * W) * max_m * sizeof(double);
+  return (size_t)(2 * kMaxP + 1 + kWaves * (W + 1)) * max_m * sizeof(double);
 }
 
 // Resident workgroups per CU for lines of at most max_m unknowns.
