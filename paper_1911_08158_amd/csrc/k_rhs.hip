@@ -512,7 +512,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_p
 struct RhsVariant {
   int TY, NT;
 };
-static const RhsVariant kVarP2F[] = {{14, 256}, {30, 512}, {46, 768}};
+static const RhsVariant kVarP2F[] = {{14, 256}, {26, 448}, {46, 768}};
 static const RhsVariant kVarP2D[] = {{14, 256}, {30, 512}, {22, 384}};
 static const RhsVariant kVarP3F[] = {{13, 256}, {29, 512}, {21, 384}};
 static const RhsVariant kVarP3D[] = {{13, 256}, {21, 384}, {9, 192}};
@@ -547,7 +547,7 @@ static hipError_t launch_f(int p, int var, const LaunchHdr* d_hdr, int grid, hip
   if (p == 2) {
     switch (var) {
       case 0: return launch_one<float, 3, 14, 256>(d_hdr, grid, s, op, out);
-      case 1: return launch_one<float, 3, 30, 512>(d_hdr, grid, s, op, out);
+      case 1: return launch_one<float, 3, 26, 448>(d_hdr, grid, s, op, out);
       default: return launch_one<float, 3, 46, 768>(d_hdr, grid, s, op, out);
     }
   }
