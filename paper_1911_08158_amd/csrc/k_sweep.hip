@@ -340,20 +340,21 @@ static int sweep_resident(int W, int max_m) {
 // ncu CUs.  Measured on 128-long lines: W = 16 (rows of 128 contiguous
 // bytes in the y/z access) beats 8 and 4 both for one 128^3 simulation and
 // for a batch of four, so it is the default; narrower tiles remain for
-// launches with too few lines to give every CU a group (ADS_SWEEP_W = 4, 8
-// or 16 overrides).
+// launches with too few lines to give every CU a group, and for lines too
+// long for four 16-line tiles in LDS (ADS_SWEEP_W = 4, 8 or 16 overrides
+// where it fits).
 int sweep_width_for(long long lines, int max_m, int ncu) {
   static const int forced = [] {
     const char* e = std::getenv("ADS_SWEEP_W");
     const int v = e ? std::atoi(e) : 0;
     return (v == 4 || v == 8 || v == 16) ? v : 0;
   }();
-  (void)max_m;
-  if (forced) return forced;
+  auto fits = [&](int W) { return sweep_lds_bytes(W, max_m) <= (size_t)160 * 1024; };
+  if (forced && fits(forced)) return forced;
   for (int W : {16, 8}) {
-    if (lines >= (long long)ncu * kWaves * W) return W;
+    if (fits(W) && lines >= (long long)ncu * kWaves * W) return W;
   }
-  return 4;
+  return 4;   // fits for lines up to 758 long (the library accepts up to 512)
 }
 
 // Groups of 4W lines in a job of `lines` lines.

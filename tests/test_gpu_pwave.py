@@ -25,6 +25,8 @@ def _cuda():
     W.C1.with_(nelem=(140, 3, 2), steps=3, init="noise"),       # x-lines longer than 128
     W.C1.with_(nelem=(2, 150, 3), p=3, q=4, steps=3, init="noise"),   # y-lines longer than 128
     W.C1.with_(nelem=(3, 2, 260), steps=2, init="noise"),       # z-lines longer than 256 (16-lane tiles)
+    W.C1.with_(nelem=(300, 128, 128), steps=2, init="noise"),   # many lines too long for 16-line LDS tiles
+    W.C1.with_(nelem=(512, 4, 3), steps=2, init="noise"),       # the longest lines accepted
     W.C1.with_(tau=50.0, steps=5),                               # stiff: tau^2 lambda >> 1
 ], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}")
 def test_pwave_run_matches_oracle(cfg):
