@@ -16,9 +16,14 @@ def rel_l2(x, ref):
 
 
 # ---------------------------------------------------------------- oracle side
+def oracle_bc(cfg: W.SimConfig) -> str:
+    """The oracle's name of the configuration's boundary condition."""
+    return {"dirichlet": "dirichlet", "natural": "neumann"}[cfg.bc]
+
+
 def oracle_pwave(cfg: W.SimConfig, nsteps: int, history: bool = False):
     from oracle import pwave
-    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau)
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
     xs = [pw.quad_points(d) for d in range(3)]
     u0 = pw.project(W.initial_values(cfg, *xs))
     b = amps = None
@@ -31,12 +36,12 @@ def oracle_pwave(cfg: W.SimConfig, nsteps: int, history: bool = False):
 
 def oracle_elastic(cfg: W.SimConfig, nsteps: int, history: bool = False):
     from oracle import elastic
-    el = elastic.Elastic(cfg.nelem, cfg.p, cfg.q, cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu)
+    el = elastic.Elastic(cfg.nelem, cfg.p, cfg.q, cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, bc=oracle_bc(cfg))
     xs = [el.b1[d].x for d in range(3)]
     vals = W.initial_values(cfg, *xs)
     from oracle import pwave
     # component-wise L2 projection with the same 1D structure
-    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau)
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
     U0 = np.stack([pw.project(vals[c]) for c in range(3)])
     res = el.run(U0, None, nsteps, history=history)
     return el, U0, res

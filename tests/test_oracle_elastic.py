@@ -125,10 +125,11 @@ def test_split_at_solve_against_dense(tau):
     np.testing.assert_allclose(Z, ref, atol=1e-11 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
 @pytest.mark.parametrize("tau", [5e-3, 5e-2, 0.5])
-def test_energy_conserved(tau):
+def test_energy_conserved(tau, bc):
     """P13 (iii): with f = 0 the three-level energy is constant."""
-    el = elastic.Elastic((4, 3, 3), 2, tau=tau, **PARS)
+    el = elastic.Elastic((4, 3, 3), 2, tau=tau, bc=bc, **PARS)
     U0 = np.random.default_rng(2).normal(size=(3,) + el.free_shape)
     (_, hist) = el.run(U0, nsteps=30, history=True)
     E = np.array([el.energy(hist[k + 1][0], hist[k][0]) for k in range(len(hist) - 1)])
@@ -154,3 +155,21 @@ def test_temporal_order_semidiscrete_exact():
         errs.append(np.linalg.norm(Un - exact) / np.linalg.norm(exact))
     r = np.array(errs[:-1]) / np.array(errs[1:])
     assert np.all(np.abs(r - 4.0) < 0.35), (errs, r)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_traction_free_rigid_motion_at_rest(p):
+    """Traction-free conditions (Section 5): a rigid displacement (translation
+    plus rotation, linear fields through Greville coefficients) has zero
+    strain, so the three-level scheme keeps it exactly at rest."""
+    el = elastic.Elastic((3, 4, 2), p, tau=0.05, bc="neumann", **PARS)
+    nz, ny, nx = el.free_shape
+    xi = [bspline.greville(el.b1[d].knots, p) for d in range(3)]
+    X = np.broadcast_to(xi[0][None, None, :], (nz, ny, nx))
+    Y = np.broadcast_to(xi[1][None, :, None], (nz, ny, nx))
+    Z = np.broadcast_to(xi[2][:, None, None], (nz, ny, nx))
+    U0 = np.stack([0.3 - 0.7 * Y + 0.2 * Z, -0.1 + 0.7 * X - 0.4 * Z, 0.5 - 0.2 * X + 0.4 * Y])
+    (_, hist) = el.run(U0, nsteps=6, history=True)
+    for Un, Unm1 in hist:
+        np.testing.assert_allclose(Un, U0, atol=1e-12)
+        np.testing.assert_allclose(Unm1, U0, atol=1e-12)

@@ -31,12 +31,14 @@ def _mode(pw, k):
     return np.array(lam), phi
 
 
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
 @pytest.mark.parametrize("tau", [1e-2, 0.3, 10.0])
 @pytest.mark.parametrize("p", [2, 3])
-def test_eigenmode_recursion(tau, p):
+def test_eigenmode_recursion(tau, p, bc):
     """P8: on a separable eigenmode the 3D scheme reduces to the scalar
-    recursion with s = sum lam_d and g = prod(1 + eta lam_d)."""
-    pw = pwave.PWave((5, 4, 6), p, tau=tau)
+    recursion with s = sum lam_d and g = prod(1 + eta lam_d) (with natural
+    conditions the z-factor of mode (1, 2, 0) is the constant, lam_z = 0)."""
+    pw = pwave.PWave((5, 4, 6), p, tau=tau, bc=bc)
     lam, phi = _mode(pw, (1, 2, 0))
     s, eta = lam.sum(), pw.eta
     g = np.prod(1 + eta * lam)
@@ -56,11 +58,12 @@ def test_eigenmode_recursion(tau, p):
         np.testing.assert_allclose(aa, a * phi, atol=1e-11 * max(1, abs(a)))
 
 
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
 @pytest.mark.parametrize("tau", [1e-2, 1.0, 100.0])
-def test_energy_conserved(tau):
+def test_energy_conserved(tau, bc):
     """P9: with F = 0 the energy 1/2 v^T (G - eta K) v + 1/2 u^T K u is constant
     for n >= 1 (unconditional stability), and the plain energy stays below it."""
-    pw = pwave.PWave((6, 5, 4), 2, tau=tau)
+    pw = pwave.PWave((6, 5, 4), 2, tau=tau, bc=bc)
     u0 = np.random.default_rng(11).normal(size=pw.free_shape)
     (_, hist) = pw.run(u0, nsteps=40, history=True)
     E = np.array([pw.energy(u, v) for (u, v, a) in hist[1:]])
@@ -221,3 +224,18 @@ def test_literal_scheme_wave_speed():
     X = np.stack([np.cos(th * n), np.sin(th * n)], 1)
     coef = np.linalg.lstsq(X, c, rcond=None)[0]
     np.testing.assert_allclose(X @ coef, c, atol=1e-10)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_natural_bc_constant_field_at_rest(p):
+    """With natural (zero normal derivative) conditions the constant function
+    (all coefficients 1, partition of unity) is in the null space of K: the
+    scheme keeps it at rest exactly, u = 1, u' = u'' = 0 for every step."""
+    pw = pwave.PWave((4, 3, 5), p, tau=0.05, bc="neumann")
+    assert pw.free_shape == tuple(n + p for n in (5, 3, 4))
+    (_, hist) = pw.run(np.ones(pw.free_shape), nsteps=8, history=True)
+    # rounding of K 1 = 0 is amplified by |M^-1 K| ~ 1/h^2 in u''; a wrong row
+    # sum would give O(1) values
+    for u, v, a in hist:
+        np.testing.assert_allclose(u, 1.0, atol=1e-12)
+        assert np.abs(v).max() < 1e-11 and np.abs(a).max() < 1e-10

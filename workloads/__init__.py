@@ -47,6 +47,7 @@ class SimConfig:
     init: str = "bump"      # "bump" | "gauss8" | "elastic_pulse" | "noise" | "gauss1:<seed>"
     load: str = "none"      # "none" | "ricker_point"
     seed: int = MASTER_SEED
+    bc: str = "dirichlet"   # "dirichlet" (zero) | "natural" (zero normal derivative / traction-free)
 
     @property
     def n(self):
@@ -192,6 +193,8 @@ def initial_coefficients(cfg: SimConfig) -> np.ndarray:
     zero-Dirichlet value).  Full layout [z, y, x] or [3, z, y, x]."""
     xs, ys, zs = (greville_abscissae(cfg.nelem[d], cfg.p) for d in range(3))
     c = np.array(initial_values(cfg, xs, ys, zs))
+    if cfg.bc != "dirichlet":
+        return np.ascontiguousarray(c)
     c[..., 0, :, :] = 0
     c[..., -1, :, :] = 0
     c[..., :, 0, :] = 0
