@@ -19,9 +19,11 @@
  *     the FULL index set, n_x * n_y * n_z entries per component with
  *     n_d = nelem[d] + p, laid out [z][y][x] (x fastest); elasticity arrays
  *     hold the three components one after the other ([c][z][y][x]).
- *   - Zero Dirichlet conditions: the first and last basis function of every
- *     direction are eliminated.  Boundary entries of input arrays are ignored;
- *     boundary entries of output arrays are written as 0.
+ *   - Boundary conditions (ads_params.bc): with ADS_BC_DIRICHLET0 the first
+ *     and last basis function of every direction are eliminated; boundary
+ *     entries of input arrays are ignored and boundary entries of output
+ *     arrays are written as 0.  With ADS_BC_NATURAL no function is
+ *     eliminated and every entry is a degree of freedom.
  *   - The library never allocates device memory.  Every device byte it uses
  *     lives in the caller's workspace (size from ads_workspace_bytes); the
  *     caller keeps the workspace alive until ads_destroy and the stream is
@@ -62,7 +64,12 @@ typedef enum {
   ADS_MIXED_BF16 = 2   /* reserved                                           */
 } ads_precision;
 
-typedef enum { ADS_BC_DIRICHLET0 = 0 } ads_bc;
+/* Boundary conditions on all six faces.  ADS_BC_NATURAL is the homogeneous
+ * natural condition of the weak forms: zero normal derivative for the
+ * P-wave (Section 2) and zero traction, sigma n = 0, for elasticity (the
+ * traction-free condition of Section 5); the 1D mass, stiffness and mixed
+ * matrices are then used on the full index set. */
+typedef enum { ADS_BC_DIRICHLET0 = 0, ADS_BC_NATURAL = 1 } ads_bc;
 
 /* Problem statement (Section 2 for the P-wave, Section 5 for elasticity):
  * unit cube, nelem[d] uniform elements per direction (x, y, z), spline

@@ -17,6 +17,7 @@ _LIB = None
 
 ADS_PWAVE, ADS_ELASTIC = 0, 1
 ADS_FP64, ADS_MIXED_FP32, ADS_MIXED_BF16 = 0, 1, 2
+ADS_BC_DIRICHLET0, ADS_BC_NATURAL = 0, 1
 STATUS = {0: "ADS_OK", -1: "ADS_EINVAL", -2: "ADS_ENOMEM", -3: "ADS_EDEVICE", -4: "ADS_ESTATE",
           -5: "ADS_ENUMERIC"}
 PRECISION = {"fp64": ADS_FP64, "mixed_fp32": ADS_MIXED_FP32, "mixed_bf16": ADS_MIXED_BF16}
@@ -39,7 +40,7 @@ class Params(ctypes.Structure):
         p, tau and optionally q, precision, rho, lam, mu (or keywords)."""
         d = {}
         if cfg is not None:
-            for k in ("problem", "nelem", "p", "q", "tau", "precision", "rho", "lam", "mu"):
+            for k in ("problem", "nelem", "p", "q", "tau", "precision", "rho", "lam", "mu", "bc"):
                 if hasattr(cfg, k):
                     d[k] = getattr(cfg, k)
         d.update(kw)
@@ -52,7 +53,9 @@ class Params(ctypes.Structure):
             ne = (ne,) * 3
         q = d.get("q", 0) or 0
         p = int(d["p"])
-        return cls(int(prob), (c_int32 * 3)(*[int(e) for e in ne]), p, int(q) if q != p + 1 else 0, 0,
+        bc = d.get("bc", "dirichlet")
+        bc = {"dirichlet": ADS_BC_DIRICHLET0, "natural": ADS_BC_NATURAL, "neumann": ADS_BC_NATURAL}.get(bc, bc)
+        return cls(int(prob), (c_int32 * 3)(*[int(e) for e in ne]), p, int(q) if q != p + 1 else 0, int(bc),
                    int(prec), float(d["tau"]), float(d.get("rho", 1.0)), float(d.get("lam", 1.0)),
                    float(d.get("mu", 1.0)))
 

@@ -148,6 +148,10 @@ struct ads_sim {
 
 namespace {
 
+// Free coefficients of direction d: all n = nelem + p of them with natural
+// conditions, the n - 2 interior ones with zero Dirichlet conditions.
+int free_count(const ads_params& P, int d) { return P.nelem[d] + P.p - (P.bc == ADS_BC_NATURAL ? 0 : 2); }
+
 bool valid_params(const ads_params* prm, std::string& why) {
   if (!prm) {
     why = "params is NULL";
@@ -170,8 +174,8 @@ bool valid_params(const ads_params* prm, std::string& why) {
     why = "nquad must be 0 or p+1";
     return false;
   }
-  if (prm->bc != ADS_BC_DIRICHLET0) {
-    why = "only zero Dirichlet conditions are supported";
+  if (prm->bc != ADS_BC_DIRICHLET0 && prm->bc != ADS_BC_NATURAL) {
+    why = "bc must be ADS_BC_DIRICHLET0 or ADS_BC_NATURAL";
     return false;
   }
   if (!(prm->tau > 0.0) || !std::isfinite(prm->tau)) {
@@ -193,7 +197,7 @@ bool valid_params(const ads_params* prm, std::string& why) {
     }
   }
   for (int d = 0; d < 3; ++d)
-    if (prm->nelem[d] + prm->p - 2 > 512) {
+    if (free_count(*prm, d) > 512) {
       why = "at most 512 free coefficients per direction";
       return false;
     }
@@ -210,8 +214,8 @@ void geometry(ads_sim* s) {
   for (int d = 0; d < 3; ++d) {
     s->E[d] = P.nelem[d];
     s->n[d] = P.nelem[d] + P.p;
-    s->nf[d] = s->n[d] - 2;
-    s->off[d] = 1;
+    s->nf[d] = free_count(P, d);
+    s->off[d] = P.bc == ADS_BC_NATURAL ? 0 : 1;
   }
   s->nfree = (long long)s->nf[0] * s->nf[1] * s->nf[2];
   s->mixed = P.precision == ADS_MIXED_FP32;
@@ -1268,7 +1272,7 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   std::string why;
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
   for (int d = 0; d < 3; ++d)
-    if (prm->nelem[d] + prm->p - 2 > kPoolMaxM) return fail(ADS_EINVAL, "pooled meshes: <= 128 free coefficients");
+    if (free_count(*prm, d) > kPoolMaxM) return fail(ADS_EINVAL, "pooled meshes: <= 128 free coefficients");
   int free_slot = -1;
   for (int i = 0; i < P->max_slots; ++i)
     if (!P->slots[i].sim) {

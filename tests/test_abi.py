@@ -39,7 +39,8 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(p=1), dict(p=4), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
                                  dict(problem="elastic", mu=0.0), dict(problem="elastic", rho=-1.0),
                                  dict(problem="elastic", precision="mixed_fp32"),
-                                 dict(nelem=(600, 4, 4))])
+                                 dict(nelem=(600, 4, 4)), dict(bc=2), dict(bc=-1),
+                                 dict(nelem=(511, 4, 4), bc="natural")])
 def test_invalid_params_rejected(lib, bad):
     from paper_1911_08158_amd import binding
     with pytest.raises(binding.AdsError) as e:
@@ -57,6 +58,17 @@ def test_workspace_scales_linearly(lib):
     assert 6 * 8 * nf2 < b2 < 12 * 8 * nf2
     be = binding.workspace_bytes(_params(problem="elastic", nelem=(30, 30, 30)))
     assert be > 2.5 * b1
+
+
+def test_natural_bc_keeps_every_coefficient(lib):
+    """Natural conditions eliminate no basis function: the fields hold
+    (E + p)^3 coefficients instead of (E + p - 2)^3."""
+    from paper_1911_08158_amd import binding
+    bd = binding.workspace_bytes(_params(nelem=(40, 40, 40)))
+    bn = binding.workspace_bytes(_params(nelem=(40, 40, 40), bc="natural"))
+    grow = 6 * 8 * (42 ** 3 - 40 ** 3)
+    assert 0.8 * grow < bn - bd < 1.5 * grow
+    assert binding.workspace_bytes(_params(nelem=(510, 4, 4), bc="natural")) > 0   # 512 coefficients
 
 
 @pytest.mark.parametrize("p", [2, 3])

@@ -22,7 +22,9 @@ def _cuda():
     W.C4.with_(nelem=(5, 6, 4), p=3, q=4, steps=3, tau=0.02, lam=2.0, mu=0.5, rho=0.9),
     W.C4.with_(nelem=(1, 2, 3), steps=2, tau=0.1, init="noise"),
     W.C4.with_(nelem=(8, 8, 8), steps=3, tau=2.0),
-], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}")
+    W.C4.with_(nelem=(7, 5, 6), steps=4, tau=0.02, lam=0.8, mu=0.6, rho=1.3, bc="natural"),   # traction-free
+    W.C4.with_(nelem=(4, 6, 5), p=3, q=4, steps=3, tau=0.02, lam=2.0, mu=0.5, bc="natural"),
+], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
 def test_elastic_matches_oracle(cfg):
     _cuda()
     el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
