@@ -134,6 +134,17 @@ ads_status ads_set_point_load(ads_sim* sim, const double xs[3], const double* ho
  * with Z^0 = D^{-1} tau^2 (f^0 - Upsilon U^0).  Synchronizes the stream. */
 ads_status ads_factor(ads_sim* sim);
 
+/* Time-stepping coefficient set of the P-wave (before ads_factor; default
+ * ADS_SCHEME_NEWMARK).  ADS_SCHEME_NEWMARK is standard Newmark beta = 1/4,
+ * gamma = 1/2 with the direction-split left-hand side (Section 2, eq. scheme
+ * and eq. pwave2 read with the u''_n terms the printed equations drop).
+ * ADS_SCHEME_LITERAL applies the coefficient set exactly as printed, a
+ * diagnostic of that erratum: G a' = F - K(u + tau u'), u' += tau/2 a',
+ * u += tau u' (old u'); it propagates waves at 1/sqrt(2) of the speed.
+ * ADS_EINVAL for unknown schemes or elasticity; ADS_ESTATE after ads_factor. */
+typedef enum { ADS_SCHEME_NEWMARK = 0, ADS_SCHEME_LITERAL = 1 } ads_scheme;
+ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
+
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 

@@ -96,6 +96,7 @@ def load_library():
         "ads_set_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_set_point_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_factor": [c_void_p],
+        "ads_set_scheme": [c_void_p, c_int32],
         "ads_step": [c_void_p, c_int32],
         "ads_get_state": [c_void_p, c_void_p, c_void_p, c_void_p],
         "ads_set_state": [c_void_p, c_void_p, c_void_p, c_void_p, c_int64],
@@ -220,6 +221,13 @@ class Sim:
         xs = np.ascontiguousarray(xs, dtype=np.float64)
         amps = np.ascontiguousarray(amps, dtype=np.float64)
         _check(load_library().ads_set_point_load(self._h, xs.ctypes.data, amps.ctypes.data, int(amps.size)))
+
+    SCHEMES = {"newmark": 0, "literal": 1}
+
+    def set_scheme(self, scheme):
+        """'newmark' (default) or 'literal' (the printed coefficient set; a
+        P-wave diagnostic).  Before factor()."""
+        _check(load_library().ads_set_scheme(self._h, int(self.SCHEMES.get(scheme, scheme))))
 
     def factor(self):
         _check(load_library().ads_factor(self._h))

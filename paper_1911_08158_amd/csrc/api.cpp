@@ -137,6 +137,7 @@ struct ads_sim {
   int ncu = 0;          // compute units of the device (tiling of the right-hand side)
   int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
   bool mixed = false;   // FP32 contractions in the right-hand side
+  bool literal = false; // P-wave: the printed coefficient set (diagnostic)
   // kernel timing (measurement support)
   bool prof = false;
   std::vector<hipEvent_t> ev;     // (launches + 1) events per recorded step
@@ -591,13 +592,14 @@ ads_status build_launches(ads_sim* s) {
   const double tau = s->prm.tau, eta = 0.25 * tau * tau;
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
-    RhsJob rj = rhs_pwave_job(s, 1.0, tau, eta, 1, s->mixed ? 1 : 0, s->rhs_var);
+    // (the printed coefficient set drops the u'' term of the predictor)
+    RhsJob rj = rhs_pwave_job(s, 1.0, tau, s->literal ? 0.0 : eta, 1, s->mixed ? 1 : 0, s->rhs_var);
     const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
     if (!d) return fail(ADS_ENOMEM, err);
     s->step_l.push_back(
         Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(rj)});
     SweepJob z{};
-    z.epi = EPI_NEWMARK;
+    z.epi = s->literal ? EPI_NEWMARK_LITERAL : EPI_NEWMARK;
     z.c0 = tau;
     z.c1 = eta;
     z.e0 = s->u;
@@ -819,6 +821,15 @@ ads_status ads_set_point_load(ads_sim* s, const double xs[3], const double* amp,
   if ((st = build_launches(s)) != ADS_OK) return st;
   HIPCHECK(hipStreamSynchronize(s->stream));
   return ADS_OK;
+}
+
+ads_status ads_set_scheme(ads_sim* s, int32_t scheme) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (scheme != ADS_SCHEME_NEWMARK && scheme != ADS_SCHEME_LITERAL) return fail(ADS_EINVAL, "unknown scheme");
+  if (s->elastic && scheme != ADS_SCHEME_NEWMARK) return fail(ADS_EINVAL, "the printed scheme is a P-wave diagnostic");
+  if (s->factored) return fail(ADS_ESTATE, "ads_set_scheme after ads_factor");
+  s->literal = scheme == ADS_SCHEME_LITERAL;
+  return build_launches(s);
 }
 
 ads_status ads_factor(ads_sim* s) {

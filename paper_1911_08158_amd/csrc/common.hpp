@@ -39,7 +39,8 @@ struct Factor1D {
 enum SweepEpi : int {
   EPI_STORE = 0,     // out[g] = x
   EPI_NEWMARK = 1,   // a' = x; v += tau/2 (a + a'); u += tau v + eta (a + a'); a = a'
-  EPI_THREELEVEL = 2 // out[g] = x; U^{n-1} <- U^n; U^n <- 2 U^n - U^{n-1} + x
+  EPI_THREELEVEL = 2, // out[g] = x; U^{n-1} <- U^n; U^n <- 2 U^n - U^{n-1} + x
+  EPI_NEWMARK_LITERAL = 3  // printed coefficient set: a' = x; u += tau v; v += tau/2 a'
 };
 
 // One set of line solves of a field along one direction.

@@ -89,6 +89,20 @@ __device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long lon
         J.e0[g[k]] = u[k] + J.c0 * v[k] + J.c1 * s;
         J.e2[g[k]] = x[k];
       }
+  } else if (J.epi == EPI_NEWMARK_LITERAL) {
+    double u[kEpi], v[kEpi];
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k) {
+      u[k] = ok[k] ? J.e0[g[k]] : 0.0;
+      v[k] = ok[k] ? J.e1[g[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kEpi; ++k)
+      if (ok[k]) {
+        J.e0[g[k]] = u[k] + J.c0 * v[k];
+        J.e1[g[k]] = v[k] + 0.5 * J.c0 * x[k];
+        J.e2[g[k]] = x[k];
+      }
   } else {  // EPI_THREELEVEL
     double un[kEpi], um[kEpi];
 #pragma unroll

@@ -204,3 +204,41 @@ def test_energy_conserved_on_gpu():
     E = np.array(E)
     assert np.all(np.abs(E / E[0] - 1) < 1e-11)
     sim.close()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_literal_scheme_matches_oracle(p):
+    """The printed coefficient set (a diagnostic of the dropped u''_n terms)
+    through ads_set_scheme: parity with the oracle's literal step."""
+    _cuda()
+    from oracle import pwave
+    cfg = W.C1.with_(nelem=(7, 9, 6), p=p, q=p + 1, tau=0.01, steps=6)
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau)
+    xs = [pw.quad_points(d) for d in range(3)]
+    u0 = pw.project(W.initial_values(cfg, *xs))
+    _, hist = pw.run(u0, None, cfg.steps, literal=True, history=True)
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+    sim.set_scheme("literal")
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, a = sim.get_state()
+        errs = [rel_l2(x.cpu().numpy(), pw.to_full(r)) for x, r in zip((u, v, a), hist[k])]
+        assert max(errs) <= TOL, (k, errs)
+    sim.close()
+
+
+def test_scheme_rejected_after_factor_and_for_elasticity():
+    _cuda()
+    from paper_1911_08158_amd import binding
+    sim, _ = gpu_sim(W.C1.with_(nelem=(4, 4, 4)))
+    sim.factor()
+    with pytest.raises(binding.AdsError) as e:
+        sim.set_scheme("literal")
+    assert e.value.status == -4
+    sim.close()
+    sim, _ = gpu_sim(W.C4.with_(nelem=(3, 3, 3)))
+    with pytest.raises(binding.AdsError) as e:
+        sim.set_scheme("literal")
+    assert e.value.status == -1
+    sim.close()
