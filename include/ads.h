@@ -145,6 +145,15 @@ ads_status ads_factor(ads_sim* sim);
 typedef enum { ADS_SCHEME_NEWMARK = 0, ADS_SCHEME_LITERAL = 1 } ads_scheme;
 ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
 
+/* Discrete energy of the current P-wave state (synchronous):
+ *   E = 1/2 u'.(G - tau^2/4 K) u' + 1/2 u.K u,
+ * G the direction-split operator of eq. pwave2, K the stiffness (quadrature,
+ * as in the step).  Without load it is constant from the first step on: the
+ * energy counterpart of the stability discussion of Sections 3 and 6 (the
+ * paper's energy plots).  Writes one double to host memory; uses R as
+ * scratch.  ADS_EINVAL for elasticity, ADS_ESTATE before ads_factor. */
+ads_status ads_energy(ads_sim* sim, double* host_energy);
+
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 

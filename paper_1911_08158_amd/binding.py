@@ -97,6 +97,7 @@ def load_library():
         "ads_set_point_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_factor": [c_void_p],
         "ads_set_scheme": [c_void_p, c_int32],
+        "ads_energy": [c_void_p, c_void_p],
         "ads_step": [c_void_p, c_int32],
         "ads_get_state": [c_void_p, c_void_p, c_void_p, c_void_p],
         "ads_set_state": [c_void_p, c_void_p, c_void_p, c_void_p, c_int64],
@@ -231,6 +232,12 @@ class Sim:
 
     def factor(self):
         _check(load_library().ads_factor(self._h))
+
+    def energy(self):
+        """Discrete P-wave energy of the current state (host float)."""
+        e = c_double()
+        _check(load_library().ads_energy(self._h, byref(e)))
+        return e.value
 
     def step(self, n=1):
         _check(load_library().ads_step(self._h, int(n)))

@@ -125,12 +125,14 @@ struct ads_sim {
   double* d_bandM[3];
   double* d_bandG[3];
   double* d_bandGT[3];
+  double* d_bandA[3];   // P-wave: split band M_d + tau^2/4 K_d (energy diagnostic)
+  double* red;          // dot-product partial sums + 3 results
   DevFactor fS[3], fS2[3], fM[3];  // P-wave: fS = M + eta K; elastic: fS = mu, fS2 = 2mu+lam
   double *u, *v, *a, *R, *X, *T, *Y, *Z, *load, *amp;
   unsigned long long* counter;
   unsigned long long* flag;
   JobArena arena;
-  std::vector<Launch> step_l, start_l, projM_l;
+  std::vector<Launch> step_l, start_l, projM_l, energy_l;
   bool factored = false, need_start = true, have_load = false;
   int namp = 0;
   int tz = 0;
@@ -261,7 +263,9 @@ void carve(ads_sim* s, Carver& c) {
   } else {
     s->a = c.dbl(nfr);
     s->T = s->Y = s->Z = nullptr;
+    for (int d = 0; d < 3; ++d) s->d_bandA[d] = c.dbl((size_t)s->nf[d] * (2 * p + 1));
   }
+  s->red = c.dbl(dot_scratch_doubles() + 4);
   s->counter = (unsigned long long*)c.take(64);
   s->flag = (unsigned long long*)c.take(64);
   s->arena.d_base = (char*)c.take(kJobArena);
@@ -589,6 +593,7 @@ ads_status build_launches(ads_sim* s) {
   s->step_l.clear();
   s->start_l.clear();
   s->projM_l.clear();
+  s->energy_l.clear();
   const double tau = s->prm.tau, eta = 0.25 * tau * tau;
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
@@ -613,6 +618,26 @@ ads_status build_launches(ads_sim* s) {
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
     s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, 0, 0, as_bytes(r0)});
+    // energy diagnostic: R = K u, R = K v (FP64 quadrature), R = G v (split operator)
+    for (double* src : {s->u, s->v}) {
+      RhsJob ke = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, 0);
+      ke.u = src;
+      ke.load = nullptr;
+      ke.amp = nullptr;
+      ke.rscale = -1.0;
+      d = s->arena.add(std::vector<RhsJob>{ke}, err);
+      if (!d) return fail(ADS_ENOMEM, err);
+      s->energy_l.push_back(Launch{Launch::RHS_P, d, 1, ke.ntiles, 0, s->p, -1, 0, 0, as_bytes(ke)});
+    }
+    {
+      KronJob G = kron_base(s, s->R, nullptr, 0.0);
+      KronTerm t{};
+      t.src = s->v;
+      for (int dd = 0; dd < 3; ++dd) t.T[dd] = s->d_bandA[dd];
+      t.coef = 1.0;
+      G.term[G.nterm++] = t;
+      if (!push_kron(s, s->energy_l, G, err)) return fail(ADS_ENOMEM, err);
+    }
     if (!add_ads_solve(s, s->start_l, s->fS, s->R, s->R, s->a, 1.0, plain_epi(), err))
       return fail(ADS_ENOMEM, err);
   } else {
@@ -823,6 +848,28 @@ ads_status ads_set_point_load(ads_sim* s, const double xs[3], const double* amp,
   return ADS_OK;
 }
 
+ads_status ads_energy(ads_sim* s, double* host_energy) {
+  if (!s || !host_energy) return fail(ADS_EINVAL, "NULL argument");
+  if (s->elastic) return fail(ADS_EINVAL, "the energy diagnostic is implemented for the P-wave");
+  if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_energy before ads_factor");
+  const int nd = dot_scratch_doubles();
+  double* out = s->red + nd;
+  ads_status st;
+  // u.Ku, v.Kv, v.Gv
+  const double* dots[3][2] = {{s->u, s->R}, {s->v, s->R}, {s->v, s->R}};
+  for (int k = 0; k < 3; ++k) {
+    std::vector<Launch> one(1, s->energy_l[k]);
+    if ((st = enqueue(s, one)) != ADS_OK) return st;
+    HIPCHECK(launch_dot(dots[k][0], dots[k][1], s->nfree, s->red, out + k, s->stream));
+  }
+  double h[3];
+  HIPCHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  const double eta = 0.25 * s->prm.tau * s->prm.tau;
+  *host_energy = 0.5 * (h[2] - eta * h[1]) + 0.5 * h[0];
+  return ADS_OK;
+}
+
 ads_status ads_set_scheme(ads_sim* s, int32_t scheme) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   if (scheme != ADS_SCHEME_NEWMARK && scheme != ADS_SCHEME_LITERAL) return fail(ADS_EINVAL, "unknown scheme");
@@ -840,6 +887,7 @@ ads_status ads_factor(ads_sim* s) {
     if (!s->elastic) {
       Band A = axpby(1.0, s->Mf[d], 0.25 * tau * tau, s->Kf[d]);
       if ((st = upload_factor(s, s->fS[d], A)) != ADS_OK) return st;
+      if ((st = upload(s, s->d_bandA[d], A.a.data(), A.a.size() * 8)) != ADS_OK) return st;
     } else {
       const double rho = s->prm.rho, mu = s->prm.mu, lam = s->prm.lambda;
       Band A1 = axpby(1.0, s->Mf[d], tau * tau * mu / (4.0 * rho), s->Kf[d]);

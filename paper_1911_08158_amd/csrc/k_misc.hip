@@ -88,6 +88,39 @@ __global__ void nonfinite_kernel(const double* x, long long n, unsigned long lon
   if (local) atomicAdd(cnt, local);
 }
 
+// Dot product in a fixed order (deterministic): every block sums a
+// grid-stride slice and reduces it by a fixed tree; one block then reduces
+// the kDotBlocks partial sums the same way.
+constexpr int kDotBlocks = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double* x, const double* y, long long n,
+                                                          double* partial) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    acc = fma(x[i], y[i], acc);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void dot_final_kernel(const double* partial, int nb, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
 static inline int grid_for(long long n) {
   long long g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -132,6 +165,14 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
 hipError_t launch_axpby(double* out, const double* x, const double* y, double a, double b, long long n,
                         hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, x, y, a, b, n);
+  return hipGetLastError();
+}
+
+int dot_scratch_doubles() { return kDotBlocks; }
+
+hipError_t launch_dot(const double* x, const double* y, long long n, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, partial, kDotBlocks, out);
   return hipGetLastError();
 }
 

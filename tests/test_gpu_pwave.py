@@ -242,3 +242,43 @@ def test_scheme_rejected_after_factor_and_for_elasticity():
         sim.set_scheme("literal")
     assert e.value.status == -1
     sim.close()
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C1.with_(nelem=(9, 7, 8), tau=0.05, steps=4),
+    W.C1.with_(nelem=(6, 5, 7), p=3, q=4, tau=0.5, steps=3, bc="natural"),
+], ids=lambda c: f"{c.nelem}-p{c.p}-{c.bc}")
+def test_device_energy_matches_oracle(cfg):
+    """ads_energy (on-device products and reductions) equals the oracle's
+    energy of the same state."""
+    _cuda()
+    from runners import oracle_bc
+    from oracle import pwave
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
+    sim, _ = gpu_sim(cfg)
+    sim.factor()
+    for k in range(cfg.steps):
+        sim.step(1)
+        u, v, _ = sim.get_state()
+        ref = pw.energy(pw.to_free(u.cpu().numpy()), pw.to_free(v.cpu().numpy()))
+        e = sim.energy()
+        assert abs(e - ref) <= 1e-12 * abs(ref), (k, e, ref)
+    sim.close()
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "natural"])
+def test_device_energy_curve_paper_run(bc):
+    """The paper's P-wave runs (32^3 elements, tau = 1e-2) with the energy
+    computed on the device after every step: constant from step 1 on."""
+    _cuda()
+    cfg = W.C1.with_(nelem=(32, 32, 32), tau=1e-2, steps=60, bc=bc)
+    sim, _ = gpu_sim(cfg)
+    sim.factor()
+    E = []
+    for k in range(cfg.steps):
+        sim.step(1)
+        E.append(sim.energy())
+    E = np.array(E)
+    print(f"32^3 {bc}: E = {E[0]:.12e}, max |E/E1 - 1| = {np.abs(E / E[0] - 1).max():.2e}", flush=True)
+    assert E[0] > 0 and np.all(np.abs(E / E[0] - 1) < 1e-12)
+    sim.close()
