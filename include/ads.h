@@ -145,13 +145,19 @@ ads_status ads_factor(ads_sim* sim);
 typedef enum { ADS_SCHEME_NEWMARK = 0, ADS_SCHEME_LITERAL = 1 } ads_scheme;
 ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
 
-/* Discrete energy of the current P-wave state (synchronous):
+/* Discrete energy of the current state (synchronous; one double written to
+ * host memory).  P-wave:
  *   E = 1/2 u'.(G - tau^2/4 K) u' + 1/2 u.K u,
  * G the direction-split operator of eq. pwave2, K the stiffness (quadrature,
- * as in the step).  Without load it is constant from the first step on: the
- * energy counterpart of the stability discussion of Sections 3 and 6 (the
- * paper's energy plots).  Writes one double to host memory; uses R as
- * scratch.  ADS_EINVAL for elasticity, ADS_ESTATE before ads_factor. */
+ * as in the step).  Elasticity, with V = (U^n - U^{n-1})/tau and
+ * W = (U^n + U^{n-1})/2:
+ *   E = 1/2 V.(D - tau^2/4 Upsilon) V + 1/2 W.Upsilon W,
+ * D = L (rho M)^{-1} L^T the alternating-triangular operator of eq. pre /
+ * eq. corr with the split diagonal blocks of eq. spill.  Without load both
+ * are constant from the first step on: the energy counterpart of the
+ * stability discussion of Sections 3 and 6 (the paper's energy plots).
+ * Uses the simulation's scratch fields (between steps only).  ADS_ESTATE
+ * before ads_factor. */
 ads_status ads_energy(ads_sim* sim, double* host_energy);
 
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */

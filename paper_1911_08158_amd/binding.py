@@ -234,7 +234,8 @@ class Sim:
         _check(load_library().ads_factor(self._h))
 
     def energy(self):
-        """Discrete P-wave energy of the current state (host float)."""
+        """Discrete energy of the current state (host float; P-wave or
+        elasticity, see ads_energy)."""
         e = c_double()
         _check(load_library().ads_energy(self._h, byref(e)))
         return e.value

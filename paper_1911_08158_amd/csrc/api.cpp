@@ -125,7 +125,8 @@ struct ads_sim {
   double* d_bandM[3];
   double* d_bandG[3];
   double* d_bandGT[3];
-  double* d_bandA[3];   // P-wave: split band M_d + tau^2/4 K_d (energy diagnostic)
+  double* d_bandA[3];   // split bands (energy diagnostic): P-wave M_d + tau^2/4 K_d,
+  double* d_bandA2[3];  // elasticity M_d + tau^2 c K_d/(4 rho), c = mu (A) and 2 mu + lambda (A2)
   double* red;          // dot-product partial sums + 3 results
   DevFactor fS[3], fS2[3], fM[3];  // P-wave: fS = M + eta K; elastic: fS = mu, fS2 = 2mu+lam
   double *u, *v, *a, *R, *X, *T, *Y, *Z, *load, *amp;
@@ -259,6 +260,8 @@ void carve(ads_sim* s, Carver& c) {
       s->d_bandM[d] = c.dbl(bw);
       s->d_bandG[d] = c.dbl(bw);
       s->d_bandGT[d] = c.dbl(bw);
+      s->d_bandA[d] = c.dbl(bw);
+      s->d_bandA2[d] = c.dbl(bw);
     }
   } else {
     s->a = c.dbl(nfr);
@@ -648,6 +651,34 @@ ads_status build_launches(ads_sim* s) {
     if (!add_at_solve(s, s->step_l, true, true, err)) return fail(ADS_ENOMEM, err);
     s->start_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, 0, 0, as_bytes(rj)});
     if (!add_at_solve(s, s->start_l, false, false, err)) return fail(ADS_ENOMEM, err);
+    // energy diagnostic (V = (U^{n+1} - U^n)/tau in Y, W = (U^{n+1} + U^n)/2 in Z):
+    // R = Upsilon W, R = Upsilon V (quadrature), R = L^T V (split diagonal and
+    // upper couplings), Z = (rho M)^{-1} R per component
+    const long long nf = s->nfree;
+    const double tau = s->prm.tau, rho = s->prm.rho, h = 0.5 * tau * tau;
+    for (double* src : {s->Z, s->Y}) {
+      RhsJob ke = rhs_elastic_job(s);
+      ke.u = src;
+      ke.load = nullptr;
+      ke.amp = nullptr;
+      ke.rscale = -1.0;
+      d = s->arena.add(std::vector<RhsJob>{ke}, err);
+      if (!d) return fail(ADS_ENOMEM, err);
+      s->energy_l.push_back(Launch{Launch::RHS_E, d, 1, ke.ntiles, 0, s->p, -1, 0, 0, as_bytes(ke)});
+    }
+    for (int i = 0; i < 3; ++i) {
+      KronJob K = kron_base(s, s->R + i * nf, nullptr, 0.0);
+      KronTerm t{};
+      t.src = s->Y + i * nf;
+      for (int dd = 0; dd < 3; ++dd) t.T[dd] = dd == i ? s->d_bandA2[dd] : s->d_bandA[dd];
+      t.coef = rho;
+      K.term[K.nterm++] = t;
+      for (int jj = i + 1; jj < 3; ++jj) kron_add_upsilon(s, K, i, jj, s->Y + jj * nf, h);
+      if (!push_kron(s, s->energy_l, K, err)) return fail(ADS_ENOMEM, err);
+    }
+    for (int i = 0; i < 3; ++i)
+      if (!add_ads_solve(s, s->energy_l, s->fM, s->R + i * nf, s->T, s->Z + i * nf, 1.0 / rho, plain_epi(), err))
+        return fail(ADS_ENOMEM, err);
   }
   // mass solve used by the projection: R -> R (per component, offset applied at launch)
   if (!add_ads_solve(s, s->projM_l, s->fM, s->R, s->R, s->R, 1.0, plain_epi(), err))
@@ -850,11 +881,31 @@ ads_status ads_set_point_load(ads_sim* s, const double xs[3], const double* amp,
 
 ads_status ads_energy(ads_sim* s, double* host_energy) {
   if (!s || !host_energy) return fail(ADS_EINVAL, "NULL argument");
-  if (s->elastic) return fail(ADS_EINVAL, "the energy diagnostic is implemented for the P-wave");
   if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_energy before ads_factor");
   const int nd = dot_scratch_doubles();
   double* out = s->red + nd;
   ads_status st;
+  if (s->elastic) {
+    // u = U^{n+1}, v = U^n
+    const long long n3 = 3 * s->nfree;
+    const double tau = s->prm.tau;
+    HIPCHECK(launch_axpby(s->Y, s->u, s->v, 1.0 / tau, -1.0 / tau, n3, s->stream));
+    HIPCHECK(launch_axpby(s->Z, s->u, s->v, 0.5, 0.5, n3, s->stream));
+    std::vector<Launch> L(s->energy_l.begin(), s->energy_l.begin() + 1);
+    if ((st = enqueue(s, L)) != ADS_OK) return st;
+    HIPCHECK(launch_dot(s->Z, s->R, n3, s->red, out + 0, s->stream));   // W.Upsilon W
+    L.assign(s->energy_l.begin() + 1, s->energy_l.begin() + 2);
+    if ((st = enqueue(s, L)) != ADS_OK) return st;
+    HIPCHECK(launch_dot(s->Y, s->R, n3, s->red, out + 1, s->stream));   // V.Upsilon V
+    L.assign(s->energy_l.begin() + 2, s->energy_l.end());
+    if ((st = enqueue(s, L)) != ADS_OK) return st;
+    HIPCHECK(launch_dot(s->R, s->Z, n3, s->red, out + 2, s->stream));   // V.D V
+    double h[3];
+    HIPCHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+    *host_energy = 0.5 * (h[2] - 0.25 * tau * tau * h[1]) + 0.5 * h[0];
+    return ADS_OK;
+  }
   // u.Ku, v.Kv, v.Gv
   const double* dots[3][2] = {{s->u, s->R}, {s->v, s->R}, {s->v, s->R}};
   for (int k = 0; k < 3; ++k) {
@@ -894,6 +945,8 @@ ads_status ads_factor(ads_sim* s) {
       Band A2 = axpby(1.0, s->Mf[d], tau * tau * (2.0 * mu + lam) / (4.0 * rho), s->Kf[d]);
       if ((st = upload_factor(s, s->fS[d], A1)) != ADS_OK) return st;
       if ((st = upload_factor(s, s->fS2[d], A2)) != ADS_OK) return st;
+      if ((st = upload(s, s->d_bandA[d], A1.a.data(), A1.a.size() * 8)) != ADS_OK) return st;
+      if ((st = upload(s, s->d_bandA2[d], A2.a.data(), A2.a.size() * 8)) != ADS_OK) return st;
     }
   }
   if (s->need_start) {

@@ -78,3 +78,40 @@ def test_elastic_energy_on_gpu():
     E = np.array(E)
     assert np.all(np.abs(E / E[0] - 1) < 1e-10)
     sim.close()
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C4.with_(nelem=(6, 7, 5), steps=3, tau=0.02, lam=0.8, mu=0.6, rho=1.3),
+    W.C4.with_(nelem=(5, 4, 6), p=3, q=4, steps=3, tau=0.05, lam=2.0, mu=0.5, bc="natural"),
+], ids=lambda c: f"{c.nelem}-p{c.p}-{c.bc}")
+def test_device_energy_matches_oracle(cfg):
+    """ads_energy (three-level energy with the alternating-triangular
+    operator, on the device) equals the oracle's energy of the same states."""
+    _cuda()
+    el, U0_ref, _ = oracle_elastic(cfg, 0)
+    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref))
+    sim.factor()
+    for k in range(cfg.steps):
+        sim.step(1)
+        u, v, _ = sim.get_state()
+        ref = el.energy(el.to_free(u.cpu().numpy()), el.to_free(v.cpu().numpy()))
+        e = sim.energy()
+        assert abs(e - ref) <= 1e-12 * abs(ref), (k, e, ref)
+    sim.close()
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "natural"])
+def test_device_energy_conserved(bc):
+    """Elasticity on 16^3 elements: the device energy is constant over 40 steps."""
+    _cuda()
+    cfg = W.C4.with_(nelem=(16, 16, 16), tau=1e-2, steps=40, bc=bc)
+    sim, _ = gpu_sim(cfg)
+    sim.factor()
+    E = []
+    for k in range(cfg.steps):
+        sim.step(1)
+        E.append(sim.energy())
+    E = np.array(E)
+    print(f"elasticity 16^3 {bc}: E = {E[0]:.12e}, max |E/E1 - 1| = {np.abs(E / E[0] - 1).max():.2e}", flush=True)
+    assert E[0] > 0 and np.all(np.abs(E / E[0] - 1) < 1e-11)
+    sim.close()
