@@ -36,7 +36,12 @@ from .kron import AXIS, ads_solve, apply_dir, kron3
 
 class PWave:
     def __init__(self, nelem, p: int, q: int | None = None, tau: float = 1e-2,
-                 bc: str = "dirichlet"):
+                 bc: str = "dirichlet", coef: np.ndarray | None = None, c2ref: float = 1.0):
+        """coef: squared wave speed c^2 at every Gauss point [(Ez q), (Ey q),
+        (Ex q)] (None: c^2 = 1).  With it the stiffness is the element-loop
+        quadrature of (c^2 grad B_i, grad w) and the direction-split
+        left-hand side uses the constant c2ref (the ADS step then solves with
+        an approximation of M + eta K, a preconditioned step)."""
         if np.isscalar(nelem):
             nelem = (nelem,) * 3
         self.nelem = tuple(int(e) for e in nelem)
@@ -49,7 +54,9 @@ class PWave:
         self.idx = [mx.free_index(b.n, bc) for b in self.b1]
         self.M = [mx.restrict(mx.mass(b), i) for b, i in zip(self.b1, self.idx)]
         self.K = [mx.restrict(mx.stiffness(b), i) for b, i in zip(self.b1, self.idx)]
-        self.A = [M + self.eta * K for M, K in zip(self.M, self.K)]
+        self.coef = None if coef is None else np.asarray(coef, dtype=np.float64)
+        self.c2ref = float(c2ref)
+        self.A = [M + self.eta * self.c2ref * K for M, K in zip(self.M, self.K)]
         self.fA = [band_lu(A, p) for A in self.A]
         self.fM = [band_lu(M, p) for M in self.M]
 
@@ -79,7 +86,11 @@ class PWave:
 
     # -- operators (Section 2, the 1D matrices in Kronecker form) ----------
     def stiffness(self, w: np.ndarray) -> np.ndarray:
-        """K w with K = K_x(x)M_y(x)M_z + M_x(x)K_y(x)M_z + M_x(x)M_y(x)K_z."""
+        """K w with K = K_x(x)M_y(x)M_z + M_x(x)K_y(x)M_z + M_x(x)M_y(x)K_z
+        (constant coefficient), else the element-loop quadrature with c^2."""
+        if self.coef is not None:
+            from .quadref import stiffness_action
+            return self.to_free(stiffness_action(self.b1, self.to_full(w), self.coef))
         Mx, My, Mz = self.M
         Kx, Ky, Kz = self.K
         return kron3(Kx, My, Mz, w) + kron3(Mx, Ky, Mz, w) + kron3(Mx, My, Kz, w)
@@ -167,7 +178,8 @@ class PWave:
     def energy(self, u, v) -> float:
         """E = 1/2 v^T (G - eta K) v + 1/2 u^T K u: conserved exactly (F = 0)
         by the scheme from step 1 on, because the split step is Newmark with
-        the modified mass G - eta K >= M."""
+        the modified mass G - eta K >= M (with a coefficient field: when
+        c2ref >= max c^2)."""
         mt = self.G(v) - self.eta * self.stiffness(v)
         return 0.5 * float(np.sum(v * mt)) + 0.5 * float(np.sum(u * self.stiffness(u)))
 

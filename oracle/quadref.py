@@ -25,10 +25,12 @@ def _element_tables(b: mx.Basis1D, e: int):
     return b.N[rows, cols], b.D[rows, cols], b.w[rows]
 
 
-def stiffness_action(b1, u: np.ndarray) -> np.ndarray:
-    """out_i = int grad B_i . grad u_h over the cube, u: full [z, y, x]."""
+def stiffness_action(b1, u: np.ndarray, coef: np.ndarray | None = None) -> np.ndarray:
+    """out_i = int c(x) grad B_i . grad u_h over the cube, u: full [z, y, x];
+    coef: c at every Gauss point, [(Ez q), (Ey q), (Ex q)] (None: c = 1)."""
     bx, by, bz = b1
     p = bx.p
+    q = bx.q
     out = np.zeros_like(u)
     for ez, ey, ex in itertools.product(range(bz.E), range(by.E), range(bx.E)):
         Nx, Dx, wx = _element_tables(bx, ex)
@@ -40,6 +42,8 @@ def stiffness_action(b1, u: np.ndarray) -> np.ndarray:
         uy = np.einsum("ka,jb,ic,abc->kji", Nz, Dy, Nx, c)
         uz = np.einsum("ka,jb,ic,abc->kji", Dz, Ny, Nx, c)
         W = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+        if coef is not None:
+            W = W * coef[ez * q:(ez + 1) * q, ey * q:(ey + 1) * q, ex * q:(ex + 1) * q]
         out[ez:ez + p + 1, ey:ey + p + 1, ex:ex + p + 1] += (
             np.einsum("ka,jb,ic,kji->abc", Nz, Ny, Dx, W * ux)
             + np.einsum("ka,jb,ic,kji->abc", Nz, Dy, Nx, W * uy)
