@@ -134,6 +134,18 @@ ads_status ads_set_point_load(ads_sim* sim, const double xs[3], const double* ho
  * with Z^0 = D^{-1} tau^2 (f^0 - Upsilon U^0).  Synchronizes the stream. */
 ads_status ads_factor(ads_sim* sim);
 
+/* Variable wave speed of the P-wave (before ads_factor): the stiffness of
+ * the right-hand side becomes the Gauss quadrature of (c^2 grad B_i, grad w)
+ * with dev_c2 = c^2 at every Gauss point, a device FP64 array laid out like
+ * the data of ads_project ([z][y][x] over (E_z q) x (E_y q) x (E_x q)
+ * points; NULL = c^2 = 1).  The direction-split left-hand side keeps the
+ * constant c2ref (G = (x)_d (M_d + tau^2/4 c2ref K_d)), so the ADS step is a
+ * preconditioned Newmark step; with c2ref >= max c^2 the discrete energy of
+ * ads_energy stays conserved.  The library keeps the pointer: the caller
+ * keeps the array alive and unchanged until ads_destroy.  ADS_EINVAL for
+ * elasticity or c2ref <= 0, ADS_ESTATE after ads_factor. */
+ads_status ads_set_coefficient(ads_sim* sim, const double* dev_c2, double c2ref);
+
 /* Time-stepping coefficient set of the P-wave (before ads_factor; default
  * ADS_SCHEME_NEWMARK).  ADS_SCHEME_NEWMARK is standard Newmark beta = 1/4,
  * gamma = 1/2 with the direction-split left-hand side (Section 2, eq. scheme

@@ -97,6 +97,7 @@ def load_library():
         "ads_set_point_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_factor": [c_void_p],
         "ads_set_scheme": [c_void_p, c_int32],
+        "ads_set_coefficient": [c_void_p, c_void_p, c_double],
         "ads_energy": [c_void_p, c_void_p],
         "ads_step": [c_void_p, c_int32],
         "ads_get_state": [c_void_p, c_void_p, c_void_p, c_void_p],
@@ -222,6 +223,18 @@ class Sim:
         xs = np.ascontiguousarray(xs, dtype=np.float64)
         amps = np.ascontiguousarray(amps, dtype=np.float64)
         _check(load_library().ads_set_point_load(self._h, xs.ctypes.data, amps.ctypes.data, int(amps.size)))
+
+    def set_coefficient(self, c2, c2ref):
+        """Wave-speed field c^2 at the Gauss points (device tensor laid out like
+        project()'s input, or None) and the c^2 of the split left-hand side.
+        The tensor is kept referenced for the simulation's lifetime.  Before
+        factor()."""
+        import torch
+        if c2 is not None:
+            c2 = c2.to(self.device, torch.float64).contiguous()
+        self._coef = c2
+        self._pre()
+        _check(load_library().ads_set_coefficient(self._h, _ptr(c2), float(c2ref)))
 
     SCHEMES = {"newmark": 0, "literal": 1}
 

@@ -64,6 +64,7 @@ struct Launch {
   int mixed = 0;  // right-hand side: FP32 contractions
   std::vector<char> host_jobs;
   int w = 4;      // sweeps: lines per wave tile
+  int coef = 0;   // P-wave right-hand side: jobs carry a wave-speed field
 };
 
 struct DevFactor {
@@ -141,6 +142,8 @@ struct ads_sim {
   int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
   bool mixed = false;   // FP32 contractions in the right-hand side
   bool literal = false; // P-wave: the printed coefficient set (diagnostic)
+  const double* coef = nullptr;   // P-wave: caller's c^2 at the Gauss points, or null
+  double c2ref = 1.0;             // P-wave: c^2 of the split left-hand side
   // kernel timing (measurement support)
   bool prof = false;
   std::vector<hipEvent_t> ev;     // (launches + 1) events per recorded step
@@ -419,9 +422,10 @@ RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_
   J.amp_shift = amp_shift;
   J.counter = s->counter;
   J.rscale = 1.0;
+  J.coef = s->coef;
   fill_tables(s, J);
   rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p, mixed, var),
-            (long long)rhs_blocks_per_cu(s->p, mixed, var) * s->ncu);
+            (long long)rhs_blocks_per_cu(s->p, mixed, var, s->coef != nullptr) * s->ncu);
   return J;
 }
 
@@ -550,7 +554,7 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
     hipError_t e = hipSuccess;
     switch (l.kind) {
       case Launch::RHS_P:
-        e = launch_rhs_pwave(l.p, l.mixed, l.var, l.d_hdr, grid_of(l, grid_cap), s->stream);
+        e = launch_rhs_pwave(l.p, l.mixed, l.var, l.coef, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::RHS_E:
         e = launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
@@ -606,6 +610,7 @@ ads_status build_launches(ads_sim* s) {
     if (!d) return fail(ADS_ENOMEM, err);
     s->step_l.push_back(
         Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(rj)});
+    s->step_l.back().coef = s->coef != nullptr;
     SweepJob z{};
     z.epi = s->literal ? EPI_NEWMARK_LITERAL : EPI_NEWMARK;
     z.c0 = tau;
@@ -621,6 +626,7 @@ ads_status build_launches(ads_sim* s) {
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
     s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, 0, 0, as_bytes(r0)});
+    s->start_l.back().coef = s->coef != nullptr;
     // energy diagnostic: R = K u, R = K v (FP64 quadrature), R = G v (split operator)
     for (double* src : {s->u, s->v}) {
       RhsJob ke = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, 0);
@@ -631,6 +637,7 @@ ads_status build_launches(ads_sim* s) {
       d = s->arena.add(std::vector<RhsJob>{ke}, err);
       if (!d) return fail(ADS_ENOMEM, err);
       s->energy_l.push_back(Launch{Launch::RHS_P, d, 1, ke.ntiles, 0, s->p, -1, 0, 0, as_bytes(ke)});
+      s->energy_l.back().coef = s->coef != nullptr;
     }
     {
       KronJob G = kron_base(s, s->R, nullptr, 0.0);
@@ -921,6 +928,16 @@ ads_status ads_energy(ads_sim* s, double* host_energy) {
   return ADS_OK;
 }
 
+ads_status ads_set_coefficient(ads_sim* s, const double* dev_c2, double c2ref) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (s->elastic) return fail(ADS_EINVAL, "the wave-speed field is a P-wave parameter");
+  if (!(c2ref > 0.0) || !std::isfinite(c2ref)) return fail(ADS_EINVAL, "c2ref must be positive and finite");
+  if (s->factored) return fail(ADS_ESTATE, "ads_set_coefficient after ads_factor");
+  s->coef = dev_c2;
+  s->c2ref = c2ref;
+  return build_launches(s);
+}
+
 ads_status ads_set_scheme(ads_sim* s, int32_t scheme) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   if (scheme != ADS_SCHEME_NEWMARK && scheme != ADS_SCHEME_LITERAL) return fail(ADS_EINVAL, "unknown scheme");
@@ -936,7 +953,7 @@ ads_status ads_factor(ads_sim* s) {
   ads_status st;
   for (int d = 0; d < 3; ++d) {
     if (!s->elastic) {
-      Band A = axpby(1.0, s->Mf[d], 0.25 * tau * tau, s->Kf[d]);
+      Band A = axpby(1.0, s->Mf[d], 0.25 * tau * tau * s->c2ref, s->Kf[d]);
       if ((st = upload_factor(s, s->fS[d], A)) != ADS_OK) return st;
       if ((st = upload(s, s->d_bandA[d], A.a.data(), A.a.size() * 8)) != ADS_OK) return st;
     } else {
@@ -1145,7 +1162,7 @@ bool is_kron_stage(int k) { return k % 4 == 0; }   // stages 4, 8, 12, 16, 20
 
 struct PoolLaunch {
   Launch::Kind kind;
-  int p, mixed, var;
+  int p, mixed, var, coef;
   int stage;        // 0: right-hand side class, k >= 1: k-th launch after it
   int grid;
   int w;            // sweeps: lines per wave tile (chosen per batch)
@@ -1203,20 +1220,21 @@ namespace {
 void pool_build_seq(ads_pool* P, int ncu) {
   P->seq.clear();
   size_t off = 0;
-  auto add = [&](Launch::Kind k, int p, int mixed, int var, int stage, int grid, size_t js) {
-    PoolLaunch L{k, p, mixed, var, stage, grid, 4, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
+  auto add = [&](Launch::Kind k, int p, int mixed, int var, int coef, int stage, int grid, size_t js) {
+    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
     off += (L.cap + kAlign - 1) / kAlign * kAlign;
     P->seq.push_back(L);
   };
   for (int p = 2; p <= 3; ++p)
-    for (int mixed = 0; mixed <= 1; ++mixed) {
-      int var = P->var[p - 2][mixed];
-      add(Launch::RHS_P, p, mixed, var, 0, rhs_blocks_per_cu(p, mixed, var) * ncu, sizeof(RhsJob));
-    }
-  for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
+    for (int mixed = 0; mixed <= 1; ++mixed)
+      for (int coef = 0; coef <= 1; ++coef) {
+        int var = P->var[p - 2][mixed];
+        add(Launch::RHS_P, p, mixed, var, coef, 0, rhs_blocks_per_cu(p, mixed, var, coef) * ncu, sizeof(RhsJob));
+      }
+  for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
-    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
-    else add(Launch::SWEEP, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
+    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
+    else add(Launch::SWEEP, 0, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
 }
@@ -1235,7 +1253,8 @@ ads_status pool_rebuild(ads_pool* P) {
       if ((int)st.size() <= L.stage) continue;
       const Launch& l = st[L.stage];
       if (l.kind != L.kind) continue;
-      if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && l.var != L.var)))
+      if (L.stage == 0 &&
+          (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && (l.var != L.var || l.coef != L.coef))))
         continue;
       sel.push_back(l.host_jobs);
       fixed_tz = fixed_tz || sl.sim->tz > 0;
@@ -1321,7 +1340,7 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
     const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
     hipError_t e = hipSuccess;
     switch (L.kind) {
-      case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, h, L.grid, P->stream); break;
+      case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); break;
       case Launch::RHS_E: e = launch_rhs_elastic(L.p, h, L.grid, P->stream); break;
       case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, P->stream); break;
       case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;

@@ -79,6 +79,7 @@ struct RhsJob {
   int amp_shift;          // amplitude index = *counter + amp_shift
   const unsigned long long* counter;
   double rscale;          // R = rscale * (amp * load - A(w))
+  const double* coef;     // P-wave: c^2 at every Gauss point [Ez q][Ey q][Ex q], or null (c^2 = 1)
   double lam, mu;         // elasticity Lame constants
   const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P]
   int E[3], nf[3], off[3];

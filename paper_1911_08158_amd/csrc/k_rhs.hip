@@ -25,6 +25,8 @@
 //   * the Gauss-row buffer is double-buffered: two barriers per z Gauss point
 //     and one per element layer;
 //   * a z-layer is written once its last contributing element is done.
+// With a wave-speed field (c^2 at the Gauss points) the three point
+// gradients are scaled by it between the x-forward and x-backward stages.
 // Derivative tables satisfy sum_a D_a = 0 on every element (partition of
 // unity), so the forward derivative contractions use differences against
 // the first coefficient and the backward x-derivative slot 0 is minus the
@@ -110,9 +112,11 @@ struct RhsGeom {
   static_assert(lds_bytes <= 160 * 1024, "LDS budget of one workgroup");
 };
 
-// FP32: at least four waves per SIMD (at most 128 VGPRs)
-template <typename T, int P, int Q, int TY_, int NT_>
-__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_pwave_kernel(
+// FP32 p = 2: at least four waves per SIMD (three with a field).  CF: the jobs
+// carry a wave-speed field (a separate instantiation, so that the constant
+// coefficient kernels keep their registers).
+template <typename T, int P, int Q, int TY_, int NT_, bool CF>
+__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1) void rhs_pwave_kernel(
     const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
@@ -180,6 +184,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_p
     const double* __restrict__ V = J.v;
     const double* __restrict__ A = J.a;
     const double cu = J.cu, cv = J.cv, ca = J.ca;
+    const double* __restrict__ C = J.coef;
 
     // forward y tables of the tile's y-elements (zero outside the mesh)
     const double* tyg = J.tab[1];
@@ -404,6 +409,17 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_p
 #pragma unroll
         for (int i = 0; i < NRW; ++i) {
           T* row = sbb + xrow0 + 2 * i * TXH;
+          // wave-speed field: the lane's q points of this Gauss row (0 outside the mesh)
+          T cq[Q];
+          if constexpr (CF) {
+            const int r = wv * WE * Q + 4 * i + grp;
+            const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
+            const bool ok = exv && ey >= 0 && ey < Ey;
+            const double* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
+                                       ((long long)Ex * Q) + (long long)ex * Q;
+#pragma unroll
+            for (int gx = 0; gx < Q; ++gx) cq[gx] = ok ? (T)cp[gx] : T(0);
+          }
           T c0[P], c1[P], c2[P];
 #pragma unroll
           for (int a = 0; a < P; ++a) {
@@ -429,6 +445,11 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? 4 : 1) void rhs_p
               gX *= xW[gx];
               gY *= xW[gx];
               gZ *= xW[gx];
+            }
+            if constexpr (CF) {
+              gX *= cq[gx];
+              gY *= cq[gx];
+              gZ *= cq[gx];
             }
             if (gx == 0) {
 #pragma unroll
@@ -526,64 +547,71 @@ int rhs_tile_y(int p, int mixed, int var) {
 }
 
 // op 0: launch; op 1: *out = resident workgroups per CU (persistent grids)
-template <typename T, int P, int TY, int NT>
+template <typename T, int P, int TY, int NT, bool CF>
 static hipError_t launch_one(const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
   using Gm = RhsGeom<T, P, P, TY, NT>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)rhs_pwave_kernel<T, P, P, TY, NT>,
+    hipError_t e = hipFuncSetAttribute((const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::lds_bytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (op == 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)rhs_pwave_kernel<T, P, P, TY, NT>, NT,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF>, NT,
                                                         Gm::lds_bytes);
-  hipLaunchKernelGGL((rhs_pwave_kernel<T, P, P, TY, NT>), dim3(grid), dim3(NT), Gm::lds_bytes, s, d_hdr);
+  hipLaunchKernelGGL((rhs_pwave_kernel<T, P, P, TY, NT, CF>), dim3(grid), dim3(NT), Gm::lds_bytes, s, d_hdr);
   return hipGetLastError();
 }
 
+template <bool CF>
 static hipError_t launch_f(int p, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
   if (p == 2) {
     switch (var) {
-      case 0: return launch_one<float, 3, 14, 256>(d_hdr, grid, s, op, out);
-      case 1: return launch_one<float, 3, 26, 448>(d_hdr, grid, s, op, out);
-      default: return launch_one<float, 3, 46, 768>(d_hdr, grid, s, op, out);
+      case 0: return launch_one<float, 3, 14, 256, CF>(d_hdr, grid, s, op, out);
+      case 1: return launch_one<float, 3, 26, 448, CF>(d_hdr, grid, s, op, out);
+      default: return launch_one<float, 3, 46, 768, CF>(d_hdr, grid, s, op, out);
     }
   }
   switch (var) {
-    case 0: return launch_one<float, 4, 13, 256>(d_hdr, grid, s, op, out);
-    case 1: return launch_one<float, 4, 29, 512>(d_hdr, grid, s, op, out);
-    default: return launch_one<float, 4, 21, 384>(d_hdr, grid, s, op, out);
+    case 0: return launch_one<float, 4, 13, 256, CF>(d_hdr, grid, s, op, out);
+    case 1: return launch_one<float, 4, 29, 512, CF>(d_hdr, grid, s, op, out);
+    default: return launch_one<float, 4, 21, 384, CF>(d_hdr, grid, s, op, out);
   }
 }
 
+template <bool CF>
 static hipError_t launch_d(int p, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
   if (p == 2) {
     switch (var) {
-      case 0: return launch_one<double, 3, 14, 256>(d_hdr, grid, s, op, out);
-      case 1: return launch_one<double, 3, 30, 512>(d_hdr, grid, s, op, out);
-      default: return launch_one<double, 3, 22, 384>(d_hdr, grid, s, op, out);
+      case 0: return launch_one<double, 3, 14, 256, CF>(d_hdr, grid, s, op, out);
+      case 1: return launch_one<double, 3, 30, 512, CF>(d_hdr, grid, s, op, out);
+      default: return launch_one<double, 3, 22, 384, CF>(d_hdr, grid, s, op, out);
     }
   }
   switch (var) {
-    case 0: return launch_one<double, 4, 13, 256>(d_hdr, grid, s, op, out);
-    case 1: return launch_one<double, 4, 21, 384>(d_hdr, grid, s, op, out);
-    default: return launch_one<double, 4, 9, 192>(d_hdr, grid, s, op, out);
+    case 0: return launch_one<double, 4, 13, 256, CF>(d_hdr, grid, s, op, out);
+    case 1: return launch_one<double, 4, 21, 384, CF>(d_hdr, grid, s, op, out);
+    default: return launch_one<double, 4, 9, 192, CF>(d_hdr, grid, s, op, out);
   }
 }
 
-hipError_t launch_rhs_pwave(int p, int mixed, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s) {
+static hipError_t dispatch(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s,
+                           int op, int* out) {
+  if (mixed) return coef ? launch_f<true>(p, var, d_hdr, grid, s, op, out) : launch_f<false>(p, var, d_hdr, grid, s, op, out);
+  return coef ? launch_d<true>(p, var, d_hdr, grid, s, op, out) : launch_d<false>(p, var, d_hdr, grid, s, op, out);
+}
+
+hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (p != 2 && p != 3) return hipErrorInvalidValue;
   if (var < 0 || var > 2) var = 0;
-  return mixed ? launch_f(p, var, d_hdr, grid, s, 0, nullptr) : launch_d(p, var, d_hdr, grid, s, 0, nullptr);
+  return dispatch(p, mixed, var, coef, d_hdr, grid, s, 0, nullptr);
 }
 
-int rhs_blocks_per_cu(int p, int mixed, int var) {
+int rhs_blocks_per_cu(int p, int mixed, int var, int coef) {
   int n = 1;
-  if (mixed) launch_f(p, var, nullptr, 0, nullptr, 1, &n);
-  else launch_d(p, var, nullptr, 0, nullptr, 1, &n);
+  dispatch(p, mixed, var, coef, nullptr, 0, nullptr, 1, &n);
   return n < 1 ? 1 : n;
 }
 

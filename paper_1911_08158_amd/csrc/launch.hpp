@@ -18,8 +18,9 @@ hipError_t sweep_set_attributes();
 int rhs_num_variants(int p);
 int rhs_tile_x(int p);
 int rhs_tile_y(int p, int mixed, int var);
-int rhs_blocks_per_cu(int p, int mixed, int var);
-hipError_t launch_rhs_pwave(int p, int mixed, int var, const LaunchHdr* d_hdr, int grid, hipStream_t s);
+int rhs_blocks_per_cu(int p, int mixed, int var, int coef);
+// coef: the jobs carry a wave-speed field (RhsJob::coef)
+hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int rhs_el_tile_x(int p);
 int rhs_el_tile_y(int p);
 hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s);

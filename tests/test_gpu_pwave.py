@@ -282,3 +282,94 @@ def test_device_energy_curve_paper_run(bc):
     print(f"32^3 {bc}: E = {E[0]:.12e}, max |E/E1 - 1| = {np.abs(E / E[0] - 1).max():.2e}", flush=True)
     assert E[0] > 0 and np.all(np.abs(E / E[0] - 1) < 1e-12)
     sim.close()
+
+
+def _field_case(cfg, steps, precision="fp64"):
+    """Oracle and GPU runs with the smooth wave-speed field (c^2 in [0.5, 1.5],
+    split left-hand side at c2ref = 1.5) from identical coefficients."""
+    import torch
+    from runners import oracle_bc
+    from oracle import pwave
+    base = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
+    xs = [base.quad_points(d) for d in range(3)]
+    c2 = W.wave_speed_field(*xs)
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg), coef=c2, c2ref=1.5)
+    u0 = pw.project(W.initial_values(cfg, *xs))
+    _, hist = pw.run(u0, None, steps, history=True)
+    sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0))
+    sim.set_coefficient(torch.from_numpy(c2).cuda(), 1.5)
+    sim.factor()
+    return pw, hist, sim
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C1.with_(nelem=(9, 7, 8), tau=0.02, steps=5),
+    W.C1.with_(nelem=(6, 5, 7), p=3, q=4, tau=0.02, steps=4, bc="natural"),
+], ids=lambda c: f"{c.nelem}-p{c.p}-{c.bc}")
+def test_wave_speed_field_matches_oracle(cfg):
+    """Variable wave speed: the quadrature RHS with c^2 at the Gauss points
+    and the split left-hand side at c2ref, against the oracle's element-loop
+    quadrature; the device energy stays conserved."""
+    _cuda()
+    pw, hist, sim = _field_case(cfg, cfg.steps)
+    u, v, a = sim.get_state()
+    assert rel_l2(a.cpu().numpy(), pw.to_full(hist[0][2])) <= TOL
+    E = []
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, a = sim.get_state()
+        errs = [rel_l2(x.cpu().numpy(), pw.to_full(r)) for x, r in zip((u, v, a), hist[k])]
+        assert max(errs) <= TOL, (k, errs)
+        E.append(sim.energy())
+    assert np.all(np.abs(np.array(E) / E[0] - 1) < 1e-12)
+    sim.close()
+
+
+def test_wave_speed_field_mixed_precision():
+    """FP32 contractions with the field: within 1e-6 of the FP64 oracle."""
+    _cuda()
+    cfg = W.C1.with_(nelem=(12, 10, 9), tau=0.01, steps=10)
+    pw, hist, sim = _field_case(cfg, cfg.steps, precision="mixed_fp32")
+    sim.step(cfg.steps)
+    u, _, _ = sim.get_state()
+    e = rel_l2(u.cpu().numpy(), pw.to_full(hist[-1][0]))
+    assert e <= 1e-6, e
+    sim.close()
+
+
+def test_wave_speed_field_in_pool_bitwise():
+    """A simulation with a field and one without share a pool (separate
+    right-hand-side launch classes); each equals its run alone bitwise."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool
+    cfgs = [W.C1.with_(nelem=(10, 9, 8), tau=0.02), W.C1.with_(nelem=(8, 11, 9), tau=0.02)]
+
+    def setup(sim, cfg, with_field):
+        xs = [sim.quad_points(d) for d in range(3)]
+        u0 = sim.project(torch.from_numpy(np.ascontiguousarray(W.initial_values(cfg, *xs))).cuda())
+        sim.set_state(u0, None, None, 0)
+        if with_field:
+            sim.set_coefficient(torch.from_numpy(W.wave_speed_field(*xs)).cuda(), 1.5)
+        sim.factor()
+
+    from paper_1911_08158_amd import Sim
+    ref = []
+    for i, c in enumerate(cfgs):
+        s = Sim(c, device="cuda")
+        setup(s, c, i == 0)
+        s.step(5)
+        ref.append([t.cpu().numpy() for t in s.get_state()])
+        s.close()
+    pool = Pool(256 << 20, max_slots=4)
+    sims = []
+    for i, c in enumerate(cfgs):
+        s = pool.admit(c)
+        setup(s, c, i == 0)
+        pool.activate(s)
+        sims.append(s)
+    pool.step(5)
+    for s, r in zip(sims, ref):
+        for x, y in zip(s.get_state(), r):
+            assert np.array_equal(x.cpu().numpy(), y)
+    pool.close()

@@ -204,6 +204,14 @@ def initial_coefficients(cfg: SimConfig) -> np.ndarray:
     return np.ascontiguousarray(c)
 
 
+def wave_speed_field(xs, ys, zs, amp: float = 0.5) -> np.ndarray:
+    """Smooth squared wave speed c^2 = 1 + amp sin(2 pi x) cos(2 pi y) sin(2 pi z + 0.3)
+    on the tensor grid of the given points, [z, y, x] (values in [1 - amp, 1 + amp])."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    return 1.0 + amp * (np.sin(2 * np.pi * zs + 0.3)[:, None, None] * np.cos(2 * np.pi * ys)[None, :, None]
+                        * np.sin(2 * np.pi * xs)[None, None, :])
+
+
 # ---------------------------------------------------------------------------
 # loads
 # ---------------------------------------------------------------------------
