@@ -76,10 +76,15 @@ typedef enum { ADS_BC_DIRICHLET0 = 0, ADS_BC_NATURAL = 1 } ads_bc;
  * degree p with open uniform knots and maximal continuity C^{p-1}, nquad
  * Gauss points per element and direction (0 means p+1; only p+1 is
  * supported), time step tau, density rho and Lame constants lambda, mu
- * (elasticity only; the P-wave has unit wave speed). */
+ * (elasticity only; the P-wave has unit wave speed).  nelem[2] = 0 selects
+ * the two-dimensional P-wave on the unit square, the setting of the paper's
+ * exposition (Section 2: K = K_x (x) M_y + M_x (x) K_y, split left-hand side
+ * (M_x + eta K_x) (x) (M_y + eta K_y)); its arrays have one z-layer
+ * (n_z = 1) and the z-index of Gauss-point data runs over q points whose
+ * weights sum to 1. */
 typedef struct {
   int32_t problem;     /* ads_problem   */
-  int32_t nelem[3];    /* >= 1 each     */
+  int32_t nelem[3];    /* >= 1 each; nelem[2] = 0: two-dimensional P-wave */
   int32_t p;           /* 2 or 3        */
   int32_t nquad;       /* 0 or p+1      */
   int32_t bc;          /* ads_bc        */

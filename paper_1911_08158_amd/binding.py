@@ -61,7 +61,9 @@ class Params(ctypes.Structure):
 
     @property
     def n(self):
-        return tuple(int(self.nelem[d]) + int(self.p) for d in range(3))
+        """Basis functions per direction (nelem[2] = 0: two-dimensional, n_z = 1)."""
+        return tuple((1 if (d == 2 and int(self.nelem[2]) == 0) else int(self.nelem[d]) + int(self.p))
+                     for d in range(3))
 
     @property
     def comps(self):
@@ -143,7 +145,10 @@ def workspace_bytes(prm: Params) -> int:
 
 
 def quad_points(prm: Params, d: int) -> np.ndarray:
-    out = np.zeros(int(prm.nelem[d]) * (prm.p + 1))
+    ne = int(prm.nelem[d])
+    if d == 2 and ne == 0:   # two-dimensional: the flat direction has one element
+        ne = 1
+    out = np.zeros(ne * (prm.p + 1))
     _check(load_library().ads_quad_points(byref(prm), d, out.ctypes.data))
     return out
 

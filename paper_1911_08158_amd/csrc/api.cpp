@@ -157,7 +157,16 @@ namespace {
 
 // Free coefficients of direction d: all n = nelem + p of them with natural
 // conditions, the n - 2 interior ones with zero Dirichlet conditions.
-int free_count(const ads_params& P, int d) { return P.nelem[d] + P.p - (P.bc == ADS_BC_NATURAL ? 0 : 2); }
+// nelem[2] = 0: a two-dimensional P-wave problem (x, y); the z-direction is
+// one constant function (one free coefficient).
+bool flat_z(const ads_params& P) { return P.nelem[2] == 0; }
+int free_count(const ads_params& P, int d) {
+  if (d == 2 && flat_z(P)) return 1;
+  return P.nelem[d] + P.p - (P.bc == ADS_BC_NATURAL ? 0 : 2);
+}
+Tables1D tables_of(const ads_params& P, int d) {
+  return (d == 2 && flat_z(P)) ? make_tables_flat(P.p, P.p + 1) : make_tables(P.nelem[d], P.p, P.p + 1);
+}
 
 bool valid_params(const ads_params* prm, std::string& why) {
   if (!prm) {
@@ -168,11 +177,13 @@ bool valid_params(const ads_params* prm, std::string& why) {
     why = "problem must be ADS_PWAVE or ADS_ELASTIC";
     return false;
   }
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
+    if (d == 2 && prm->nelem[2] == 0 && prm->problem == ADS_PWAVE) continue;   // two-dimensional
     if (prm->nelem[d] < 1 || prm->nelem[d] > 4096) {
-      why = "nelem must be in [1, 4096]";
+      why = "nelem must be in [1, 4096] (nelem[2] = 0: two-dimensional P-wave)";
       return false;
     }
+  }
   if (prm->p != 2 && prm->p != 3) {
     why = "spline degree p must be 2 or 3";
     return false;
@@ -219,10 +230,11 @@ void geometry(ads_sim* s) {
   s->elastic = P.problem == ADS_ELASTIC;
   s->ncomp = s->elastic ? 3 : 1;
   for (int d = 0; d < 3; ++d) {
-    s->E[d] = P.nelem[d];
-    s->n[d] = P.nelem[d] + P.p;
+    const bool flat = d == 2 && flat_z(P);
+    s->E[d] = flat ? 1 : P.nelem[d];
+    s->n[d] = flat ? 1 : P.nelem[d] + P.p;
     s->nf[d] = free_count(P, d);
-    s->off[d] = P.bc == ADS_BC_NATURAL ? 0 : 1;
+    s->off[d] = (flat || P.bc == ADS_BC_NATURAL) ? 0 : 1;
   }
   s->nfree = (long long)s->nf[0] * s->nf[1] * s->nf[2];
   s->mixed = P.precision == ADS_MIXED_FP32;
@@ -717,7 +729,7 @@ ads_status ads_quad_points(const ads_params* prm, int32_t d, double* host_out) {
   std::string why;
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
   if (d < 0 || d > 2 || !host_out) return fail(ADS_EINVAL, "bad direction or NULL output");
-  Tables1D t = make_tables(prm->nelem[d], prm->p, prm->p + 1);
+  Tables1D t = tables_of(*prm, d);
   std::memcpy(host_out, t.X.data(), t.X.size() * sizeof(double));
   return ADS_OK;
 }
@@ -727,8 +739,8 @@ ads_status ads_project_scratch_bytes(const ads_params* prm, size_t* bytes) {
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
   if (!bytes) return fail(ADS_EINVAL, "bytes is NULL");
   const long long q = prm->p + 1;
-  const long long gz = prm->nelem[2] * q, gy = prm->nelem[1] * q;
-  const long long fx = prm->nelem[0] + prm->p - 2, fy = prm->nelem[1] + prm->p - 2;
+  const long long gz = (flat_z(*prm) ? 1 : prm->nelem[2]) * q, gy = prm->nelem[1] * q;
+  const long long fx = free_count(*prm, 0), fy = free_count(*prm, 1);
   *bytes = (size_t)(gz * gy * fx + gz * fy * fx) * sizeof(double) + 2 * kAlign;
   return ADS_OK;
 }
@@ -763,7 +775,7 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   carve(s, c);
   // host tables and matrices
   for (int d = 0; d < 3; ++d) {
-    s->tab[d] = make_tables(s->E[d], s->p, s->q);
+    s->tab[d] = tables_of(s->prm, d);
     Band M = assemble(s->tab[d], MAT_MASS), K = assemble(s->tab[d], MAT_STIFF), G = assemble(s->tab[d], MAT_MIXED);
     s->Mf[d] = restrict_band(M, s->off[d], s->nf[d]);
     s->Kf[d] = restrict_band(K, s->off[d], s->nf[d]);
@@ -859,6 +871,10 @@ ads_status ads_set_point_load(ads_sim* s, const double xs[3], const double* amp,
   if (namp < 0 || namp > kAmpCap) return fail(ADS_ENOMEM, "at most 4096 load amplitudes");
   std::vector<double> v[3];
   for (int d = 0; d < 3; ++d) {
+    if (d == 2 && flat_z(s->prm)) {   // two-dimensional: the constant function
+      v[2].assign(1, 1.0);
+      continue;
+    }
     double x = std::min(1.0, std::max(0.0, xs[d]));
     std::vector<double> t = open_knots(s->E[d], s->p);
     int e = std::min(s->E[d] - 1, (int)std::floor(x * s->E[d]));

@@ -120,6 +120,27 @@ Tables1D make_tables(int E, int p, int q) {
   return T;
 }
 
+Tables1D make_tables_flat(int p, int q) {
+  Tables1D T;
+  T.E = 1;
+  T.p = p;
+  T.q = q;
+  T.n = 1 + p;
+  std::vector<double> gx, gw;
+  gauss_legendre(q, gx, gw);
+  const int P = p + 1;
+  T.N.assign((size_t)q * P, 0.0);
+  T.D.assign((size_t)q * P, 0.0);
+  T.W.assign(q, 0.0);
+  T.X.assign(q, 0.0);
+  for (int g = 0; g < q; ++g) {
+    T.X[g] = 0.5 + 0.5 * gx[g];
+    T.W[g] = 0.5 * gw[g];
+    T.N[(size_t)g * P] = 1.0;
+  }
+  return T;
+}
+
 Band assemble(const Tables1D& t, MatKind kind) {
   Band A;
   A.n = t.n;

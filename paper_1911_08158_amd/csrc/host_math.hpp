@@ -27,6 +27,10 @@ struct Tables1D {
   std::vector<double> N, D, W, X;
 };
 Tables1D make_tables(int E, int p, int q);
+// The missing direction of a two-dimensional problem: one element [0, 1]
+// carrying one constant function (N = 1 in slot 0, D = 0), so that its 1D
+// mass matrix is [1] and its stiffness [0].
+Tables1D make_tables_flat(int p, int q);
 
 // Banded n x n matrix, band[i*(2p+1) + (j-i+p)] for |i-j| <= p.
 struct Band {

@@ -51,8 +51,9 @@ class SimConfig:
 
     @property
     def n(self):
-        """Basis functions per direction (open knots, maximal continuity)."""
-        return tuple(e + self.p for e in self.nelem)
+        """Basis functions per direction (open knots, maximal continuity);
+        nelem[2] = 0 is the two-dimensional P-wave (one z-layer)."""
+        return tuple(1 if (d == 2 and e == 0) else e + self.p for d, e in enumerate(self.nelem))
 
     @property
     def comps(self):
