@@ -25,6 +25,33 @@ __host__ __device__ inline const Job* hdr_jobs(const LaunchHdr* h) {
   return reinterpret_cast<const Job*>(h + 1);
 }
 
+// Global-memory views of the device pointers held in job tables.  Through a
+// plain pointer read from memory the compiler cannot tell global memory from
+// LDS and emits flat loads and stores, which count on the same wait counter
+// as LDS and scalar loads: every LDS wait would then also wait for all
+// global loads in flight (no prefetch survives it).  Accesses through these
+// views are global loads and stores, waited for on their own counter.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ const gmem<T>* gview(const T* p) {
+  return (const gmem<T>*)p;
+}
+template <class T>
+__device__ __forceinline__ gmem<T>* gview(T* p) {
+  return (gmem<T>*)p;
+}
+
+// Read-only view (constant address space) of tables that no kernel writes
+// while it runs: loads at wave-uniform addresses become scalar loads, which
+// neither occupy vector registers nor wait behind vector loads in flight.
+template <class T>
+using cmem = __attribute__((address_space(4))) T;
+template <class T>
+__device__ __forceinline__ const cmem<T>* cview(const T* p) {
+  return (const cmem<T>*)p;
+}
+
 // One 1D banded factor (banded LU without pivoting of a free-row block):
 // L[i*p + k-1] = l_{i,i-k}, U[i*p + k-1] = u_{i,i+k} (zero where the index
 // leaves the matrix), rd[i] = 1 / u_{ii}.

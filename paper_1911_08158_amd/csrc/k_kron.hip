@@ -61,10 +61,10 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
     double v = 0.0;
     if (row < KTX) {
       const int x = X0 + row;
-      if (x < nx) v = J.term[term].T[0][(long long)x * B + c];
+      if (x < nx) v = gview(J.term[term].T[0])[(long long)x * B + c];
     } else {
       const int y = Y0 + row - KTX;
-      if (y < ny) v = J.term[term].T[1][(long long)y * B + c];
+      if (y < ny) v = gview(J.term[term].T[1])[(long long)y * B + c];
     }
     Tb[k] = v;
   }
@@ -81,17 +81,24 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
   }
   const long long sxy = (long long)nx * ny;
   double pf[NS];
+  // (positions outside the field load offset 0 of the layer and are
+  // zeroed: no branch around the loads)
   auto prefetch = [&](int zs, int term) {
-    const double* src = J.term[term].src + (long long)zs * sxy;
+    const gmem<double>* src = gview(J.term[term].src) + (long long)zs * sxy;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) pf[i] = sval[i] ? src[soff[i]] : 0.0;
+    for (int i = 0; i < NS; ++i) pf[i] = src[sval[i] ? soff[i] : 0];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pf[i] = sval[i] ? pf[i] : 0.0;
   };
   const bool ocol = X0 + lx < nx && Y0 + ly < ny;
   const long long obase = (long long)(Y0 + ly) * nx + X0 + lx;
+  gmem<double>* __restrict__ out = gview(J.out);
+  const gmem<double>* __restrict__ bse = gview(J.base);
+  const double alpha = J.alpha;
   auto store = [&](int z, double v) {
     if (ocol && z >= Z0 && z < Z1) {
       const long long g = (long long)z * sxy + obase;
-      J.out[g] = (J.base != nullptr) ? fma(J.alpha, J.base[g], v) : v;
+      out[g] = (bse != nullptr) ? fma(alpha, bse[g], v) : v;
     }
   };
   double acc[B];
@@ -130,7 +137,8 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
 #pragma unroll
       for (int b = 1; b < B; ++b) sy = fma(tby[b], X[(ly + b) * KTX + lx], sy);
       sy *= J.term[term].coef;
-      const double* Tz = J.term[term].T[2];
+      // z band at wave-uniform rows: scalar loads
+      const cmem<double>* Tz = cview(J.term[term].T[2]);
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int z = zs - p + k;

@@ -180,14 +180,17 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     const int X0 = ox + tx * TX, Y0 = oy + ty * TY, Z0 = oz + tz * J.TZ;
     const int Zend = min(Z0 + J.TZ, oz + nfz);
     const long long sxy = (long long)nfx * nfy;
-    const double* __restrict__ U = J.u;
-    const double* __restrict__ V = J.v;
-    const double* __restrict__ A = J.a;
+    const gmem<double>* __restrict__ U = gview(J.u);
+    const gmem<double>* __restrict__ V = gview(J.v);
+    const gmem<double>* __restrict__ A = gview(J.a);
     const double cu = J.cu, cv = J.cv, ca = J.ca;
-    const double* __restrict__ C = J.coef;
+    const gmem<double>* __restrict__ C = gview(J.coef);
+    const gmem<double>* __restrict__ LD = gview(J.load);
+    gmem<double>* __restrict__ R = gview(J.R);
+    const double rscale = J.rscale;
 
     // forward y tables of the tile's y-elements (zero outside the mesh)
-    const double* tyg = J.tab[1];
+    const gmem<double>* tyg = gview(J.tab[1]);
     for (int k = tid; k < EY * Q * P; k += NT) {
       const int eyl = k / (Q * P), rest = k - eyl * (Q * P);
       const int ey = Y0 - p + eyl;
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     const bool exv = ex >= 0 && ex < Ex;
     T xN[Q][P], xD[Q][P], xNw[QW][P], xDw[QW][P], xW[QX];
     {
-      const double* txg = J.tab[0];
+      const gmem<double>* txg = gview(J.tab[0]);
 #pragma unroll
       for (int g = 0; g < Q; ++g) {
         const double w = exv ? txg[2ll * Ex * Q * P + (long long)ex * Q + g] : 0.0;
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     auto bxD = [&](int gx, int a) -> T { if constexpr (kFoldX) return xDw[gx][a]; else return xD[gx][a]; };
     double ampv = 0.0;
     if (J.load != nullptr && J.amp != nullptr) {
-      long long ai = (long long)(*J.counter) + J.amp_shift;
-      ampv = (ai >= 0 && ai < J.namp) ? J.amp[ai] : 0.0;
+      long long ai = (long long)(*gview(J.counter)) + J.amp_shift;
+      ampv = (ai >= 0 && ai < J.namp) ? gview(J.amp)[ai] : 0.0;
     }
 
     // predictor loads: ring position k = tid + i*NT, global row offset per tile
@@ -256,21 +259,27 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
       pval[i] = k < NC && cy >= oy && cy < oy + nfy && cx >= ox && cx < ox + nfx;
       prow[i] = (long long)(cy - oy) * nfx + (cx - ox);
     }
+    // (positions outside the mesh load offset 0 and are zeroed: no branch
+    // around the loads)
     double pf[NF];
     auto prefetch_layer = [&](int cz) {
       const bool zv = cz >= oz && cz < oz + nfz;
       const long long zo = (long long)(cz - oz) * sxy;
+      long long gi[NF];
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        double w = 0.0;
-        if (zv && pval[i]) {
-          const long long gi = zo + prow[i];
-          w = cu * U[gi];
-          if (V != nullptr) w = fma(cv, V[gi], w);
-          if (A != nullptr) w = fma(ca, A[gi], w);
-        }
-        pf[i] = w;
+      for (int i = 0; i < NF; ++i) gi[i] = (zv && pval[i]) ? zo + prow[i] : 0;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) pf[i] = cu * U[gi[i]];
+      if (V != nullptr) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) pf[i] = fma(cv, V[gi[i]], pf[i]);
       }
+      if (A != nullptr) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) pf[i] = fma(ca, A[gi[i]], pf[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) pf[i] = (zv && pval[i]) ? pf[i] : 0.0;
     };
     auto commit_layer = [&](int cz) {
       T* dst = ring + (cz % P) * NC;
@@ -285,8 +294,8 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     auto store_out = [&](int cz, double accv) {
       if (ocol && cz >= Z0 && cz < Zend) {
         const long long gi = (long long)(cz - oz) * sxy + obase;
-        const double f = (J.load != nullptr) ? ampv * J.load[gi] : 0.0;
-        J.R[gi] = J.rscale * (f - accv);
+        const double f = (LD != nullptr) ? ampv * LD[gi] : 0.0;
+        R[gi] = rscale * (f - accv);
       }
     };
 
@@ -302,7 +311,9 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     }
     __syncthreads();
 
-    const double* tzg = J.tab[2];
+    // z tables at wave-uniform addresses: scalar loads, which do not wait
+    // behind the predictor prefetch in flight
+    const cmem<double>* tzg = cview(J.tab[2]);
     int buf = 0;
     for (int ez = ez0; ez <= ez1; ++ez) {
       if (ez < ez1) prefetch_layer(ez + P);
@@ -415,7 +426,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             const int r = wv * WE * Q + 4 * i + grp;
             const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
             const bool ok = exv && ey >= 0 && ey < Ey;
-            const double* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
+            const gmem<double>* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
                                        ((long long)Ex * Q) + (long long)ex * Q;
 #pragma unroll
             for (int gx = 0; gx < Q; ++gx) cq[gx] = ok ? (T)cp[gx] : T(0);
@@ -492,7 +503,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
         // (B) y-backward and z-backward into the owned column's accumulators
         if (own) {
           // backward z tables at this Gauss point (weighted tables W*N, W*D)
-          const double* tw = tzg + (2ll * Ez * Q * P + (long long)Ez * Q) + ((long long)ez * Q + gz) * P;
+          const cmem<double>* tw = tzg + (2ll * Ez * Q * P + (long long)Ez * Q) + ((long long)ez * Q + gz) * P;
           double nzw[P], dzw[P];
 #pragma unroll
           for (int a = 0; a < P; ++a) {

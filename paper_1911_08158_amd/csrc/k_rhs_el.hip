@@ -74,8 +74,12 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
     const long long sxy = (long long)nfx * nfy;
     const long long nfree = sxy * nfz;
     const double mu = J.mu, lam = J.lam;
+    const gmem<double>* __restrict__ Ug = gview(J.u);
+    const gmem<double>* __restrict__ LD = gview(J.load);
+    gmem<double>* __restrict__ Rg = gview(J.R);
+    const double rscale = J.rscale;
 
-    const double* tyg = J.tab[1];
+    const gmem<double>* tyg = gview(J.tab[1]);
     for (int k = tid; k < EY * Q * P; k += NT) {
       int eyl = k / (Q * P), rest = k - eyl * (Q * P);
       int ey = Y0 - p + eyl;
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
     const bool exv = ex >= 0 && ex < Ex;
     double xN[Q][P], xD[Q][P], xW[Q];
     {
-      const double* txg = J.tab[0];
+      const gmem<double>* txg = gview(J.tab[0]);
 #pragma unroll
       for (int g = 0; g < Q; ++g) {
 #pragma unroll
@@ -105,8 +109,8 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
     }
     double ampv = 0.0;
     if (J.load != nullptr && J.amp != nullptr) {
-      long long ai = (long long)(*J.counter) + J.amp_shift;
-      ampv = (ai >= 0 && ai < J.namp) ? J.amp[ai] : 0.0;
+      long long ai = (long long)(*gview(J.counter)) + J.amp_shift;
+      ampv = (ai >= 0 && ai < J.namp) ? gview(J.amp)[ai] : 0.0;
     }
 
     auto load_layer = [&](int cz) {
@@ -118,9 +122,9 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
         double w0 = 0.0, w1 = 0.0, w2 = 0.0;
         if (zv && cy >= oy && cy < oy + nfy && cx >= ox && cx < ox + nfx) {
           long long gi = (long long)(cz - oz) * sxy + (long long)(cy - oy) * nfx + (cx - ox);
-          w0 = J.u[gi];
-          w1 = J.u[nfree + gi];
-          w2 = J.u[2 * nfree + gi];
+          w0 = Ug[gi];
+          w1 = Ug[nfree + gi];
+          w2 = Ug[2 * nfree + gi];
         }
         ring[0][slot][cyl][cxl] = w0;
         ring[1][slot][cyl][cxl] = w1;
@@ -131,8 +135,8 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
       const int cy = Y0 + cyo, cx = X0 + cxo;
       if (cz >= Z0 && cz < Zend && cy < oy + nfy && cx < ox + nfx) {
         long long gi = (long long)(cz - oz) * sxy + (long long)(cy - oy) * nfx + (cx - ox) + c * nfree;
-        double f = (J.load != nullptr) ? ampv * J.load[gi] : 0.0;
-        J.R[gi] = J.rscale * (f - accv);
+        double f = (LD != nullptr) ? ampv * LD[gi] : 0.0;
+        Rg[gi] = rscale * (f - accv);
       }
     };
 
@@ -147,7 +151,8 @@ __global__ __launch_bounds__(256) void rhs_elastic_kernel(const LaunchHdr* __res
     for (int cz = ez0; cz <= ez0 + p; ++cz) load_layer(cz);
     __syncthreads();
 
-    const double* tzg = J.tab[2];
+    // z tables at wave-uniform addresses: scalar loads
+    const cmem<double>* tzg = cview(J.tab[2]);
     for (int ez = ez0; ez <= ez1; ++ez) {
       for (int gz = 0; gz < Q; ++gz) {
         double nz[P], dz[P];

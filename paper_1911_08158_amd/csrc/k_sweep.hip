@@ -64,58 +64,69 @@ __device__ __forceinline__ void line_geom(const SweepJob& J, int line, long long
   }
 }
 
-// Epilogue on K solved values at global offsets g[k] (ok[k] false = skip);
-// all old-state loads of the batch are issued before any is used.
+// A job's output side, read once per group: the pointers as global views.
+struct EpiView {
+  gmem<double>* out;
+  gmem<double>* e0;
+  gmem<double>* e1;
+  gmem<double>* e2;
+  double c0, c1;
+  int epi;
+};
+
+// Epilogue on K solved values at global offsets g[k] (ok[k] false = skip;
+// g[k] is then still a valid offset of the field, so the old-state loads
+// need no branch); all loads of the batch are issued before any is used.
 constexpr int kEpi = 4;
-__device__ __forceinline__ void epilogue_batch(const SweepJob& J, const long long* g, const double* x,
+__device__ __forceinline__ void epilogue_batch(const EpiView& E, const long long* g, const double* x,
                                                const bool* ok) {
-  if (J.epi == EPI_STORE) {
+  if (E.epi == EPI_STORE) {
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
-      if (ok[k]) J.out[g[k]] = x[k];
-  } else if (J.epi == EPI_NEWMARK) {
+      if (ok[k]) E.out[g[k]] = x[k];
+  } else if (E.epi == EPI_NEWMARK) {
     double u[kEpi], v[kEpi], a[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
-      u[k] = ok[k] ? J.e0[g[k]] : 0.0;
-      v[k] = ok[k] ? J.e1[g[k]] : 0.0;
-      a[k] = ok[k] ? J.e2[g[k]] : 0.0;
+      u[k] = E.e0[g[k]];
+      v[k] = E.e1[g[k]];
+      a[k] = E.e2[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
         double s = a[k] + x[k];
-        J.e1[g[k]] = v[k] + 0.5 * J.c0 * s;
-        J.e0[g[k]] = u[k] + J.c0 * v[k] + J.c1 * s;
-        J.e2[g[k]] = x[k];
+        E.e1[g[k]] = v[k] + 0.5 * E.c0 * s;
+        E.e0[g[k]] = u[k] + E.c0 * v[k] + E.c1 * s;
+        E.e2[g[k]] = x[k];
       }
-  } else if (J.epi == EPI_NEWMARK_LITERAL) {
+  } else if (E.epi == EPI_NEWMARK_LITERAL) {
     double u[kEpi], v[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
-      u[k] = ok[k] ? J.e0[g[k]] : 0.0;
-      v[k] = ok[k] ? J.e1[g[k]] : 0.0;
+      u[k] = E.e0[g[k]];
+      v[k] = E.e1[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
-        J.e0[g[k]] = u[k] + J.c0 * v[k];
-        J.e1[g[k]] = v[k] + 0.5 * J.c0 * x[k];
-        J.e2[g[k]] = x[k];
+        E.e0[g[k]] = u[k] + E.c0 * v[k];
+        E.e1[g[k]] = v[k] + 0.5 * E.c0 * x[k];
+        E.e2[g[k]] = x[k];
       }
   } else {  // EPI_THREELEVEL
     double un[kEpi], um[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
-      un[k] = ok[k] ? J.e0[g[k]] : 0.0;
-      um[k] = ok[k] ? J.e1[g[k]] : 0.0;
+      un[k] = E.e0[g[k]];
+      um[k] = E.e1[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
-        J.out[g[k]] = x[k];
-        J.e1[g[k]] = un[k];
-        J.e0[g[k]] = 2.0 * un[k] - um[k] + x[k];
+        E.out[g[k]] = x[k];
+        E.e1[g[k]] = un[k];
+        E.e0[g[k]] = 2.0 * un[k] - um[k] + x[k];
       }
   }
 }
@@ -230,11 +241,14 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
     if (jb != staged) {   // uniform over the workgroup
       __syncthreads();    // no wave still reads the previous factor
       const int mp = m * J.p;
+      const gmem<double>* fL = gview(J.f.L);
+      const gmem<double>* fU = gview(J.f.U);
+      const gmem<double>* frd = gview(J.f.rd);
       for (int k = tid; k < mp; k += kNT) {
-        fl[k] = J.f.L[k];
-        fl[mp + k] = J.f.U[k];
+        fl[k] = fL[k];
+        fl[mp + k] = fU[k];
       }
-      for (int k = tid; k < m; k += kNT) fl[2 * mp + k] = J.f.rd[k];
+      for (int k = tid; k < m; k += kNT) fl[2 * mp + k] = frd[k];
       __syncthreads();
       staged = jb;
     }
@@ -242,23 +256,27 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
     if (line0 >= J.nlines) continue;   // the job's last group may be partial
     const int nl = min(W, J.nlines - line0);
     const bool lact = ll < nl;
+    const int dir = J.dir;
+    const double scale = J.scale;
+    const gmem<double>* __restrict__ gin = gview(J.in);
+    const EpiView E{gview(J.out), gview(J.e0), gview(J.e1), gview(J.e2), J.c0, J.c1, J.epi};
+    // inactive lanes of a partial tile take line 0 of the tile: every
+    // address below stays inside the field (loads need no branch)
     long long base = 0, stride = 0;
-    if (J.dir != 0 && lact) line_geom(J, line0 + ll, base, stride);
-    if (J.dir == 0) {
+    if (dir != 0) line_geom(J, line0 + (lact ? ll : 0), base, stride);
+    if (dir == 0) {
       // x-lines: the nl lines of the tile are one contiguous block of nl*m
+      // (loads past its end re-read its last element)
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
       int l = lane / m, i = lane - l * m;   // (line, row) of flat index f0 + lane
       for (int f0 = 0; f0 < tot; f0 += kChunk * 64) {
         double c[kChunk];
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-          const int fidx = f0 + k * 64 + lane;
-          c[k] = fidx < tot ? J.in[gb + fidx] : 0.0;
-        }
+        for (int k = 0; k < kChunk; ++k) c[k] = gin[gb + min(f0 + k * 64 + lane, tot - 1)];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-          if (f0 + k * 64 + lane < tot) tl[sidx<W>(i, l)] = J.scale * c[k];
+          if (f0 + k * 64 + lane < tot) tl[sidx<W>(i, l)] = scale * c[k];
           i += 64;
           while (i >= m) {   // at most once for m >= 64
             i -= m;
@@ -270,14 +288,11 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
       for (int i0 = lq; i0 < m; i0 += kChunk * RL) {
         double c[kChunk];
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-          const int i = i0 + k * RL;
-          c[k] = i < m ? J.in[base + (long long)i * stride] : 0.0;
-        }
+        for (int k = 0; k < kChunk; ++k) c[k] = gin[base + (long long)min(i0 + k * RL, m - 1) * stride];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
           const int i = i0 + k * RL;
-          if (i < m) tl[sidx<W>(i, ll)] = J.scale * c[k];
+          if (i < m) tl[sidx<W>(i, ll)] = scale * c[k];
         }
       }
     }
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
       else substitute<W, 3>(tl, lane, m, fl);
     }
     wave_sync_sw();
-    if (J.dir == 0) {
+    if (dir == 0) {
       const long long gb = (long long)line0 * m;
       const int tot = nl * m;
       int l = lane / m, i = lane - l * m;   // (line, row) of flat index f0 + lane
@@ -299,7 +314,7 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
         for (int k = 0; k < kEpi; ++k) {
           const int fidx = f0 + k * 64 + lane;
           ok[k] = fidx < tot;
-          g[k] = gb + fidx;
+          g[k] = gb + (ok[k] ? fidx : 0);
           x[k] = ok[k] ? tl[sidx<W>(i, l)] : 0.0;
           i += 64;
           while (i >= m) {
@@ -307,7 +322,7 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
             ++l;
           }
         }
-        epilogue_batch(J, g, x, ok);
+        epilogue_batch(E, g, x, ok);
       }
     } else if (lact) {
       for (int i0 = lq; i0 < m; i0 += kEpi * RL) {
@@ -318,13 +333,13 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
         for (int k = 0; k < kEpi; ++k) {
           const int i = i0 + k * RL;
           ok[k] = i < m;
-          g[k] = base + (long long)i * stride;
+          g[k] = base + (long long)(ok[k] ? i : 0) * stride;
           x[k] = ok[k] ? tl[sidx<W>(i, ll)] : 0.0;
         }
-        epilogue_batch(J, g, x, ok);
+        epilogue_batch(E, g, x, ok);
       }
     }
-    if (line0 == 0 && lane == 0 && J.counter != nullptr) *J.counter += 1ull;
+    if (line0 == 0 && lane == 0 && J.counter != nullptr) *gview(J.counter) += 1ull;
     // the next tile of this wave overwrites the tile region: every lane's
     // epilogue reads of it come first
     wave_sync_sw();
