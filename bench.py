@@ -52,8 +52,8 @@ SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_z": 56}   # per free DOF (z 
 # once the right-hand-side sources hash differently.
 RHS_TRAFFIC = {
     "sources": ["paper_1911_08158_amd/csrc/k_rhs.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-    "sha256": "bfabc7cca70e0b78d2c3bbbefbd916e80ce1245e3fa4f4c5828997ff6981c6bc",
-    "fetch_kib": 312897.0, "fetch_scale": 2.0,
+    "sha256": "2e1809f4fe476700456448da7ec31c91a0985cef06459c954cae0a57a7ad2b50",
+    "fetch_kib": 278749.9, "fetch_scale": 2.0,
     "write_kib": 75776.0, "write_scale": 1.0,
     "batch": 4,
 }
@@ -71,6 +71,11 @@ def rhs_traffic(batch):
     if h.hexdigest() != t["sha256"]:
         return None
     return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
+
+
+def workspace_bytes_of(cfg):
+    from paper_1911_08158_amd.binding import Params, workspace_bytes
+    return workspace_bytes(Params.of(cfg))
 
 
 def gpu_info():
@@ -184,6 +189,35 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
     }
 
 
+def measure_small_latency(cfg, steps, warmup):
+    """The small configuration (launch/latency-bound): one FP64 simulation
+    in a pool, one graph replay per step; per-step time from HIP events."""
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.binding import Params, workspace_bytes
+    need = workspace_bytes(Params.of(cfg, precision="fp64"))
+    pool = Pool((8 << 20) + need + 4096, max_slots=1, device="cuda:0")
+    s = pool.admit(cfg, precision="fp64")
+    setup_sim(s, cfg)
+    pool.activate(s)
+    pool.step(warmup)
+    pool.step_times()
+    pool.stream.synchronize()
+    t0 = time.perf_counter()
+    pool.step(steps)
+    pool.stream.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = pool.step_times()
+    s.check_finite()
+    pool.close()
+    return {
+        "workload": f"P-wave {cfg.nelem[0]}^3 elements p={cfg.p} ({cfg.n[0]}^3 DOFs) tau={cfg.tau}, FP64, "
+                    "one simulation, graph replay",
+        "dof_steps_per_s": cfg.dofs() * steps / wall,
+        "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "step_ms_p99": float(np.percentile(step_ms, 99)),
+    }
+
+
 def measure_elastic(cfg, steps, warmup):
     """Elasticity (alternating-triangular step), one FP64 simulation."""
     import torch
@@ -252,32 +286,55 @@ def measure_serving(nreq, pool_gib, max_slots):
     }
 
 
-def cpu_baseline(cfg, seconds):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline(cfg, seconds, seconds_1thread):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     setup and the start are untimed; steps are timed until ``seconds``
-    elapse (at least 2)."""
+    elapse (at least 2), with the BLAS threads the process has, then again
+    with one thread."""
     import workloads as W
     from oracle import pwave
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau)
-    u = pw.project(W.initial_values(cfg, *[pw.quad_points(d) for d in range(3)]))
-    v = np.zeros_like(u)
-    a = pw.initial_accel(u)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        u, v, a = pw.step(u, v, a)
-        n += 1
-        dt = time.perf_counter() - t0
-        if n >= 2 and dt >= seconds:
-            break
-    return {"value": cfg.dofs() * n / dt, "unit": "DOF-steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} steps of one {cfg.nelem[0]}x{cfg.nelem[1]}x{cfg.nelem[2]} p={cfg.p} P-wave simulation "
-                      f"(NumPy FP64 oracle; setup, projection and start untimed)"}
+    u0 = pw.project(W.initial_values(cfg, *[pw.quad_points(d) for d in range(3)]))
+    a0 = pw.initial_accel(u0)
+
+    def run(limit):
+        u, v, a = u0, np.zeros_like(u0), a0
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            u, v, a = pw.step(u, v, a)
+            n += 1
+            dt = time.perf_counter() - t0
+            if n >= 2 and dt >= limit:
+                return n, dt
+
+    n, dt = run(seconds)
+    out = {"value": cfg.dofs() * n / dt, "unit": "DOF-steps/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} steps of one {cfg.nelem[0]}x{cfg.nelem[1]}x{cfg.nelem[2]} p={cfg.p} P-wave simulation "
+                     f"(NumPy FP64 oracle; setup, projection and start untimed)",
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    if threadpool_limits is not None and seconds_1thread > 0:
+        with threadpool_limits(limits=1):
+            n1, dt1 = run(seconds_1thread)
+        out["one_thread"] = {"value": cfg.dofs() * n1 / dt1, "steps": n1}
+    return out
 
 
 def calibration_copy():
@@ -300,6 +357,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-1thread", type=float, default=5.0)
+    ap.add_argument("--large-batch", type=int, default=16,
+                    help="second batch whose footprint exceeds the 256 MB Infinity Cache (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
@@ -366,10 +426,18 @@ def main():
         "gpu": gpu_info(),
     }
     out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup)
+    c2 = W.C2.with_(precision="fp64")
+    out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
+                                        "FP64, one simulation", **measure_plain(c2, args.steps, args.warmup)}
+    out["c1_latency"] = measure_small_latency(W.C1, 200, 20)
+    if args.large_batch > 0:
+        lb = measure_batched(cfg.with_(precision="mixed_fp32"), args.large_batch, 20, 3)
+        need = workspace_bytes_of(cfg.with_(precision="mixed_fp32"))
+        out["large_batch"] = {"batch": args.large_batch, "footprint_bytes": need * args.large_batch, **lb}
     if not args.no_serving:
         out["serving"] = measure_serving(args.requests, 16, 64)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, args.cpu_seconds_1thread)
     print(json.dumps(out), flush=True)
 
 
