@@ -43,7 +43,8 @@ def rhs_flops_per_element(p, q=None):
     return 2 * (2 * P * (2 * q + 3 * q * q + 3 * q ** 3) + 3 * q ** 3)
 
 
-SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_z": 56}   # per free DOF (z fused with Newmark update)
+SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_xy": 16,   # per free DOF; x and y in one in-plane launch: 16
+               "sweep_z": 56}                                 # z fused with the Newmark update
 
 # HBM traffic of one batched right-hand-side launch (4 simulations), from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same counters

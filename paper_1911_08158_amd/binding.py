@@ -292,7 +292,7 @@ class Sim:
     def profile(self, enable=True):
         _check(load_library().ads_profile(self._h, 1 if enable else 0))
 
-    KIND_NAMES = {0: "rhs", 1: "sweep_x", 2: "sweep_y", 3: "sweep_z", 4: "couple"}
+    KIND_NAMES = {0: "rhs", 1: "sweep_x", 2: "sweep_y", 3: "sweep_z", 4: "couple", 6: "sweep_xy"}
 
     def profile_read(self, max_steps=100000):
         """Mean kernel durations (ms) per launch position of one step, their
@@ -382,7 +382,7 @@ class Pool:
         _check(load_library().ads_pool_step_times(self._h, ms.ctypes.data, cap, byref(n)))
         return ms[:n.value].copy()
 
-    POOL_KINDS = {0: "rhs", 5: "rhs_elastic", 1: "sweep_x", 2: "sweep_y", 3: "sweep_z", 4: "couple"}
+    POOL_KINDS = {0: "rhs", 5: "rhs_elastic", 1: "sweep_x", 2: "sweep_y", 3: "sweep_z", 4: "couple", 6: "sweep_xy"}
 
     def profile(self, enable=True):
         _check(load_library().ads_pool_profile(self._h, 1 if enable else 0))

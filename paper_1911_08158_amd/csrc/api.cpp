@@ -56,7 +56,7 @@ struct Carver {
 // One kernel launch of a step (or of setup), with its device job table
 // (LaunchHdr + jobs) and a host copy of the jobs (for batching).
 struct Launch {
-  enum Kind { RHS_P, RHS_E, SWEEP, KRON } kind;
+  enum Kind { RHS_P, RHS_E, SWEEP, KRON, PLANE } kind;
   const LaunchHdr* d_hdr;
   int njobs, total_tiles, max_m, p;
   int dir = -1;   // sweeps: direction
@@ -65,6 +65,7 @@ struct Launch {
   std::vector<char> host_jobs;
   int w = 4;      // sweeps: lines per wave tile
   int coef = 0;   // P-wave right-hand side: jobs carry a wave-speed field
+  size_t lds = 0; // in-plane sweeps: dynamic LDS bytes
 };
 
 struct DevFactor {
@@ -313,9 +314,29 @@ SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* 
 }
 
 // Three sweeps x (in -> X), y (X -> tmp), z (tmp -> out/epilogue) with one
-// factor per direction.
+// factor per direction; when a z-plane fits in LDS the x- and y-sweeps are
+// one in-plane launch (in -> tmp).
 bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], const double* in, double* tmp,
                    double* out, double scale, SweepJob zlast, std::string& err) {
+  const bool fused = plane_fits(s->nf[0], s->nf[1], s->p);
+  if (fused) {
+    PlaneJob jp{};
+    jp.in = in;
+    jp.out = tmp;
+    jp.fx = Factor1D{f[0].L, f[0].U, f[0].rd, f[0].m};
+    jp.fy = Factor1D{f[1].L, f[1].U, f[1].rd, f[1].m};
+    jp.p = s->p;
+    jp.nx = s->nf[0];
+    jp.ny = s->nf[1];
+    jp.nz = s->nf[2];
+    jp.scale = scale;
+    jp.tile0 = 0;
+    jp.ntiles = s->nf[2];
+    const LaunchHdr* d = s->arena.add(std::vector<PlaneJob>{jp}, err);
+    if (!d) return false;
+    L.push_back(Launch{Launch::PLANE, d, 1, jp.ntiles, max_m(s), s->p, -1, 0, 0, as_bytes(jp)});
+    L.back().lds = plane_lds_bytes(jp.nx, jp.ny, jp.p);
+  }
   SweepJob jx = sweep_job(s, 0, f[0], in, s->X, scale);
   SweepJob jy = sweep_job(s, 1, f[1], s->X, tmp, 1.0);
   SweepJob jz = zlast;
@@ -332,7 +353,9 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
   jz.ntiles = base.ntiles;
   jz.tile0 = 0;
   jz.scale = 1.0;
-  for (SweepJob* j : {&jx, &jy, &jz}) {
+  std::vector<SweepJob*> js{&jx, &jy, &jz};
+  if (fused) js = {&jz};
+  for (SweepJob* j : js) {
     const LaunchHdr* d = s->arena.add(std::vector<SweepJob>{*j}, err);
     if (!d) return false;
     L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir, 0, 0, as_bytes(*j)});
@@ -577,6 +600,9 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
       case Launch::KRON:
         e = launch_kron(l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
+      case Launch::PLANE:
+        e = launch_planes(l.d_hdr, grid_of(l, grid_cap), l.lds, s->stream);
+        break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     if (evs) HIPCHECK(hipEventRecord(evs[li + 1], s->stream));
@@ -585,9 +611,11 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
 }
 
 // 0 = right-hand side, 1..3 = x/y/z sweep, 4 = coupling apply
+// 0 right-hand side, 1/2/3 x/y/z sweep, 4 coupling, 6 in-plane (x and y) sweeps
 int launch_kind_code(const Launch& l) {
   if (l.kind == Launch::RHS_P || l.kind == Launch::RHS_E) return 0;
   if (l.kind == Launch::KRON) return 4;
+  if (l.kind == Launch::PLANE) return 6;
   return 1 + l.dir;
 }
 
@@ -1171,10 +1199,15 @@ ads_status ads_destroy(ads_sim* s) {
 // ============================================================================
 namespace {
 
-constexpr int kPoolStages = 23;   // launches after the right-hand side (elasticity: 3 + 5 x 4)
+// Launches after the right-hand side: per direction-split solve an in-plane
+// (x, y) launch and a z-sweep, a coupling before every elasticity solve but
+// the first (elasticity: 6 x 2 + 5; the P-wave uses the first two).
+constexpr int kPoolStages = 17;
 constexpr int kPoolMaxM = 128;    // free coefficients per direction in pooled simulations
+static_assert(kPoolMaxM <= 128, "a pooled z-plane fits in LDS");
 
-bool is_kron_stage(int k) { return k % 4 == 0; }   // stages 4, 8, 12, 16, 20
+bool is_kron_stage(int k) { return k % 3 == 0; }    // stages 3, 6, 9, 12, 15
+bool is_plane_stage(int k) { return k % 3 == 1; }   // stages 1, 4, 7, 10, 13, 16
 
 struct PoolLaunch {
   Launch::Kind kind;
@@ -1182,6 +1215,7 @@ struct PoolLaunch {
   int stage;        // 0: right-hand side class, k >= 1: k-th launch after it
   int grid;
   int w;            // sweeps: lines per wave tile (chosen per batch)
+  size_t lds;       // in-plane sweeps: dynamic LDS bytes (largest plane of the batch)
   size_t off, cap;  // table offset/capacity (bytes) in the pool's table region
   size_t job_size;
 };
@@ -1237,7 +1271,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   P->seq.clear();
   size_t off = 0;
   auto add = [&](Launch::Kind k, int p, int mixed, int var, int coef, int stage, int grid, size_t js) {
-    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
+    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, 0, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
     off += (L.cap + kAlign - 1) / kAlign * kAlign;
     P->seq.push_back(L);
   };
@@ -1250,6 +1284,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
     if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
+    else if (is_plane_stage(k)) add(Launch::PLANE, 0, 0, 0, 0, k, ncu, sizeof(PlaneJob));
     else add(Launch::SWEEP, 0, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
@@ -1301,6 +1336,15 @@ ads_status pool_rebuild(ads_pool* P) {
       const int k = best_zchunks(xy_nfz, 2 * pmax, L.grid);
       for (auto& j : sel) set_kron_zchunks(*(KronJob*)j.data(), k);
     }
+    // in-plane sweeps: LDS of the largest plane, persistent grid for it
+    if (L.kind == Launch::PLANE && !sel.empty()) {
+      L.lds = 0;
+      for (const auto& j : sel) {
+        const PlaneJob* r = (const PlaneJob*)j.data();
+        L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p));
+      }
+      L.grid = plane_blocks_per_cu(L.lds) * P->ncu;
+    }
     // sweeps: tile width and persistent grid for the batch's line count
     if (L.kind == Launch::SWEEP && !sel.empty()) {
       long long lines = 0;
@@ -1324,6 +1368,10 @@ ads_status pool_rebuild(ads_pool* P) {
         KronJob* s = (KronJob*)j.data();
         s->tile0 = total;
         total += s->ntiles;
+      } else if (L.kind == Launch::PLANE) {
+        PlaneJob* s = (PlaneJob*)j.data();
+        s->tile0 = total;
+        total += s->ntiles;
       } else {
         RhsJob* s = (RhsJob*)j.data();
         s->tile0 = total;
@@ -1335,7 +1383,9 @@ ads_status pool_rebuild(ads_pool* P) {
     LaunchHdr h{};
     h.njobs = n;
     h.total_tiles = total;
-    P->nonempty[li] = n == 0 ? 0 : (L.kind == Launch::SWEEP ? L.w : 1);
+    // launch shape (a captured graph holds it): sweep tile width, or the
+    // in-plane LDS size
+    P->nonempty[li] = n == 0 ? 0 : (L.kind == Launch::SWEEP ? L.w : L.kind == Launch::PLANE ? (int)L.lds : 1);
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
@@ -1360,6 +1410,7 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
       case Launch::RHS_E: e = launch_rhs_elastic(L.p, h, L.grid, P->stream); break;
       case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, P->stream); break;
       case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;
+      case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, P->stream); break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
     if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
@@ -1548,9 +1599,9 @@ ads_status ads_pool_profile_read(ads_pool* P, double* ms, int32_t* kind, int32_t
     const PoolLaunch& l = P->seq[i];
     if (ms) ms[i] = (i < P->nonempty.size() && !P->nonempty[i]) ? -1.0 : (P->prof_steps ? sum / P->prof_steps : 0.0);
     if (kind) {
-      int kd = l.kind == Launch::RHS_P ? 0 : l.kind == Launch::RHS_E ? 5 : l.kind == Launch::KRON ? 4 : 1;
-      if (l.kind == Launch::SWEEP) kd = 1 + ((l.stage - 1) % 4) % 3;   // x, y, z of each solve
-      kind[i] = kd;
+      // 0 / 5 right-hand sides, 6 in-plane sweeps, 3 z-sweeps, 4 couplings
+      kind[i] = l.kind == Launch::RHS_P ? 0 : l.kind == Launch::RHS_E ? 5 : l.kind == Launch::KRON ? 4
+                : l.kind == Launch::PLANE ? 6 : 3;
     }
     if (pp) pp[i] = l.p;
     if (mixed) mixed[i] = l.mixed;

@@ -90,6 +90,19 @@ struct SweepJob {
   unsigned long long* counter;  // incremented once by the job (end of a step)
 };
 
+// The x- then the y-sweep of every z-plane of a field, the plane held in
+// LDS (the in-plane pair of a direction-split solve).
+struct PlaneJob {
+  const double* in;
+  double* out;
+  Factor1D fx, fy;
+  int p;
+  int nx, ny, nz;   // free sizes of the field
+  double scale;     // the input is multiplied by this before the solve
+  int tile0;        // first global tile (plane) index of this job
+  int ntiles;       // = nz
+};
+
 // Right-hand side by sum-factorized Gauss quadrature on one field
 // (P-wave) or three fields (elasticity).
 struct RhsJob {

@@ -346,6 +346,206 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// In-plane sweeps.  The 160 KiB LDS of a CU holds a whole z-plane of up to
+// 128 x 128 FP64 unknowns (padded rows of nx + 1) with the x- and y-factor
+// rows, so one workgroup solves the x-lines and then the y-lines of a plane
+// without writing the intermediate to memory: 16 B per unknown instead of
+// 32 for the two sweeps, and one lane per line with all lanes of the
+// workgroup busy (a thread per x-line, then a thread per y-line).  With the
+// odd row pitch the x-lines' accesses (lanes a row apart) and the y-lines'
+// (lanes adjacent) are free of bank conflicts.
+
+constexpr int kPT = 256;   // threads per plane workgroup
+constexpr int kPL = 64;    // plane values per thread loaded before any is stored to LDS
+
+__device__ __forceinline__ int find_job_plane(const PlaneJob* jobs, int njobs, int tile) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Substitution of one line in LDS with element i at col[i * st]; factor
+// rows fl = L[m*P], U[m*P], rd[m] in LDS (broadcast reads).  Same
+// arithmetic, in the same order, as `substitute`.
+template <int P>
+__device__ __forceinline__ void substitute_st(double* col, int st, int m, const double* fl) {
+  const double* Lf = fl;
+  const double* Uf = fl + m * P;
+  const double* rdf = fl + 2 * m * P;
+  const int nb = m / kSB;
+  double h[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    double* rb = col + b * kSB * st;
+    const double* Lb = Lf + b * kSB * P;
+    double v[kSB], f[kSB][P];
+#pragma unroll
+    for (int k = 0; k < kSB; ++k) {
+      v[k] = rb[k * st];
+#pragma unroll
+      for (int j = 0; j < P; ++j) f[k][j] = Lb[k * P + j];
+    }
+#pragma unroll
+    for (int k = 0; k < kSB; ++k) {
+      double s = v[k];
+#pragma unroll
+      for (int j = P - 1; j >= 0; --j) s = fma(-f[k][j], h[j], s);
+#pragma unroll
+      for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+      h[0] = s;
+      rb[k * st] = s;
+    }
+  }
+  for (int i = nb * kSB; i < m; ++i) {
+    double s = col[i * st];
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) s = fma(-Lf[i * P + j], h[j], s);
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+    h[0] = s;
+    col[i * st] = s;
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = 0.0;
+  for (int i = m - 1; i >= nb * kSB; --i) {
+    double s = col[i * st];
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) s = fma(-Uf[i * P + j], h[j], s);
+    s *= rdf[i];
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+    h[0] = s;
+    col[i * st] = s;
+  }
+  for (int b = nb - 1; b >= 0; --b) {
+    double* rb = col + b * kSB * st;
+    const double* Ub = Uf + b * kSB * P;
+    const double* rdb = rdf + b * kSB;
+    double v[kSB], f[kSB][P], r[kSB];
+#pragma unroll
+    for (int k = 0; k < kSB; ++k) {
+      v[k] = rb[k * st];
+      r[k] = rdb[k];
+#pragma unroll
+      for (int j = 0; j < P; ++j) f[k][j] = Ub[k * P + j];
+    }
+#pragma unroll
+    for (int k = kSB - 1; k >= 0; --k) {
+      double s = v[k];
+#pragma unroll
+      for (int j = P - 1; j >= 0; --j) s = fma(-f[k][j], h[j], s);
+      s *= r[k];
+#pragma unroll
+      for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+      h[0] = s;
+      rb[k * st] = s;
+    }
+  }
+}
+
+// LDS: plane [ny][nx + 1], then the x-factor rows (2p+1 per x) and the
+// y-factor rows (2p+1 per y).
+size_t plane_lds_bytes(int nx, int ny, int p) {
+  return ((size_t)ny * (nx + 1) + (size_t)(2 * p + 1) * (nx + ny)) * sizeof(double);
+}
+bool plane_fits(int nx, int ny, int p) { return plane_lds_bytes(nx, ny, p) <= (size_t)160 * 1024; }
+
+__global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __restrict__ hdr) {
+  extern __shared__ double lds[];
+  const int njobs = hdr->njobs, total = hdr->total_tiles;
+  const PlaneJob* __restrict__ jobs = hdr_jobs<PlaneJob>(hdr);
+  const int tid = threadIdx.x;
+  int staged = -1;   // job whose factor rows are in LDS
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int jb = find_job_plane(jobs, njobs, t);
+    const PlaneJob& J = jobs[jb];
+    const int nx = J.nx, ny = J.ny, p = J.p, PX = nx + 1, n = nx * ny;
+    double* pl = lds;
+    double* fxl = pl + (size_t)ny * PX;
+    double* fyl = fxl + (2 * p + 1) * nx;
+    __syncthreads();   // the previous plane's stores have read the LDS
+    if (jb != staged) {
+      const gmem<double>* lx = gview(J.fx.L);
+      const gmem<double>* ux = gview(J.fx.U);
+      const gmem<double>* rx = gview(J.fx.rd);
+      const gmem<double>* ly = gview(J.fy.L);
+      const gmem<double>* uy = gview(J.fy.U);
+      const gmem<double>* ry = gview(J.fy.rd);
+      for (int k = tid; k < nx * p; k += kPT) {
+        fxl[k] = lx[k];
+        fxl[nx * p + k] = ux[k];
+      }
+      for (int k = tid; k < nx; k += kPT) fxl[2 * nx * p + k] = rx[k];
+      for (int k = tid; k < ny * p; k += kPT) {
+        fyl[k] = ly[k];
+        fyl[ny * p + k] = uy[k];
+      }
+      for (int k = tid; k < ny; k += kPT) fyl[2 * ny * p + k] = ry[k];
+      staged = jb;
+    }
+    // load the plane (all of a thread's loads of a chunk before any store
+    // to LDS).  Row of flat index k from a float reciprocal: (k + 1/2)/nx
+    // lies at least 1/(2 nx) from an integer and is computed with a
+    // relative error below 2^-22, i.e. an absolute error below ny 2^-22,
+    // which is smaller whenever nx ny < 2^21 (a plane that fits in LDS
+    // holds at most 20480 unknowns)
+    const long long gb = (long long)(t - J.tile0) * n;
+    const gmem<double>* __restrict__ gin = gview(J.in) + gb;
+    const double scale = J.scale;
+    const float rnx = 1.0f / (float)nx;
+    for (int k0 = 0; k0 < n; k0 += kPT * kPL) {
+      double v[kPL];
+#pragma unroll
+      for (int i = 0; i < kPL; ++i) v[i] = gin[min(k0 + i * kPT + tid, n - 1)];
+#pragma unroll
+      for (int i = 0; i < kPL; ++i) {
+        const int k = k0 + i * kPT + tid;
+        if (k < n) {
+          const int y = (int)(((float)k + 0.5f) * rnx), x = k - y * nx;
+          pl[y * PX + x] = scale * v[i];
+        }
+      }
+    }
+    __syncthreads();
+    for (int y = tid; y < ny; y += kPT) {
+      if (p == 2) substitute_st<2>(pl + y * PX, 1, nx, fxl);
+      else substitute_st<3>(pl + y * PX, 1, nx, fxl);
+    }
+    __syncthreads();
+    for (int x = tid; x < nx; x += kPT) {
+      if (p == 2) substitute_st<2>(pl + x, PX, ny, fyl);
+      else substitute_st<3>(pl + x, PX, ny, fyl);
+    }
+    __syncthreads();
+    gmem<double>* __restrict__ gout = gview(J.out) + gb;
+    for (int k = tid; k < n; k += kPT) {
+      const int y = (int)(((float)k + 0.5f) * rnx), x = k - y * nx;
+      gout[k] = pl[y * PX + x];
+    }
+  }
+}
+
+int plane_blocks_per_cu(size_t lds_bytes) {
+  int n = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_plane_kernel, kPT, lds_bytes);
+  const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds_bytes, 1));
+  if (e != hipSuccess || n <= 0) n = by_lds;
+  return std::max(1, std::min(n, by_lds));
+}
+
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (lds_bytes > (size_t)160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sweep_plane_kernel, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  return hipGetLastError();
+}
+
 // Dynamic LDS of a workgroup: the factor rows (2p+1 <= 7 per line position)
 // and kWaves tiles of max_m rows of pitch W + 1.
 static size_t sweep_lds_bytes(int W, int max_m) {
@@ -408,6 +608,8 @@ hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hip
 
 hipError_t sweep_set_attributes() {
   hipError_t e;
+  e = hipFuncSetAttribute((const void*)sweep_plane_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)sweep_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)sweep_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

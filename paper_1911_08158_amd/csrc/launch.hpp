@@ -14,6 +14,12 @@ int sweep_groups(long long lines, int W);
 int sweep_blocks_per_cu(int W, int max_m);
 hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hipStream_t s);
 hipError_t sweep_set_attributes();
+// In-plane sweeps: one workgroup per z-plane (PlaneJob tiles are planes);
+// a plane of nx x ny unknowns fits when plane_lds_bytes <= 160 KiB.
+size_t plane_lds_bytes(int nx, int ny, int p);
+bool plane_fits(int nx, int ny, int p);
+int plane_blocks_per_cu(size_t lds_bytes);
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, hipStream_t s);
 
 int rhs_num_variants(int p);
 int rhs_tile_x(int p);
