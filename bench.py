@@ -53,8 +53,8 @@ SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_xy": 16,   # per free DOF; x
 # once the right-hand-side sources hash differently.
 RHS_TRAFFIC = {
     "sources": ["paper_1911_08158_amd/csrc/k_rhs.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-    "sha256": "2e1809f4fe476700456448da7ec31c91a0985cef06459c954cae0a57a7ad2b50",
-    "fetch_kib": 278749.9, "fetch_scale": 2.0,
+    "sha256": "5c41ef209c4ca2363f2007fd2ad0fd6fb85bfa8f9446dc4a60cee604b1c6334c",
+    "fetch_kib": 278795.7, "fetch_scale": 2.0,
     "write_kib": 75776.0, "write_scale": 1.0,
     "batch": 4,
 }
