@@ -215,7 +215,9 @@ ads_status ads_check_finite(ads_sim* sim);
  * of one time step (in launch order), its mean duration in ms over the
  * recorded steps (host_ms, up to cap entries) and its kind (host_kind:
  * 0 = right-hand side, 1 = x-sweep, 2 = y-sweep, 3 = z-sweep, 4 = coupling
- * apply), plus the per-step durations in ms (host_step_ms, up to step_cap
+ * apply, 6 = x- and y-sweeps of every z-plane in one launch, used when a
+ * plane fits in the 160 KiB LDS), plus the per-step durations in ms
+ * (host_step_ms, up to step_cap
  * entries; *nsteps receives the count).  Reading resets the record. */
 ads_status ads_profile(ads_sim* sim, int32_t enable);
 ads_status ads_profile_read(ads_sim* sim, double* host_ms, int32_t* host_kind, int32_t cap,
@@ -270,7 +272,8 @@ ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int
  * returns the mean ms per launch position of one pool step over the
  * recorded steps (-1 for a class with no simulation in the batch, which is
  * not launched), its kind (0 = P-wave right-hand side, 5 = elasticity
- * right-hand side, 1/2/3 = sweeps, 4 = coupling apply), degree and
+ * right-hand side, 6 = x- and y-sweeps of the z-planes, 3 = z-sweeps,
+ * 4 = coupling apply), degree and
  * mixed flag (host arrays of cap entries), and resets the record. */
 ads_status ads_pool_profile(ads_pool* pool, int32_t enable);
 ads_status ads_pool_profile_read(ads_pool* pool, double* host_ms, int32_t* host_kind, int32_t* host_p,

@@ -27,6 +27,8 @@ def _cuda():
     W.C1.with_(nelem=(3, 2, 260), steps=2, init="noise"),       # z-lines longer than 256 (16-lane tiles)
     W.C1.with_(nelem=(300, 128, 128), steps=2, init="noise"),   # many lines too long for 16-line LDS tiles
     W.C1.with_(nelem=(512, 4, 3), steps=2, init="noise"),       # the longest lines accepted
+    W.C1.with_(nelem=(3, 300, 2), steps=2, init="noise"),       # in-plane sweeps: more x-lines than threads
+    W.C1.with_(nelem=(200, 90, 2), steps=2, init="noise"),      # in-plane: a 145 KB plane, loaded in two chunks
     W.C1.with_(tau=50.0, steps=5),                               # stiff: tau^2 lambda >> 1
     W.C1.with_(nelem=(9, 7, 11), steps=5, bc="natural"),        # natural conditions: no elimination
     W.C1.with_(nelem=(6, 13, 5), p=3, q=4, steps=4, tau=0.02, bc="natural"),
