@@ -116,11 +116,12 @@ def kernel_table(entries, cfg, batch, mixed_peak=False):
     return out
 
 
-def measure_plain(cfg, steps, warmup):
-    """Plain per-simulation FP64 form: one simulation, per-kernel launches."""
+def measure_plain(cfg, steps, warmup, precision="fp64"):
+    """Plain per-simulation form (FP64 unless asked): one simulation,
+    per-kernel launches."""
     import torch
     from paper_1911_08158_amd import Sim
-    sim = Sim(cfg, device="cuda:0", precision="fp64")
+    sim = Sim(cfg, device="cuda:0", precision=precision)
     setup_sim(sim, cfg)
     tune = sim.tune()
     sim.step(warmup)
@@ -431,6 +432,11 @@ def main():
     out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
                                         "FP64, one simulation", **measure_plain(c2, args.steps, args.warmup)}
     out["c1_latency"] = measure_small_latency(W.C1, 200, 20)
+    out["bf16_inputs"] = {"workload": "P-wave 128^3 elements p=2, one simulation, right-hand side on the predictor "
+                                      "rounded to BF16 plus a correction pass on the FP64 remainder (FP32 "
+                                      "contractions; two right-hand-side launches per step)",
+                          **measure_plain(cfg.with_(precision="mixed_bf16"), args.steps, args.warmup,
+                                          precision="mixed_bf16")}
     if args.large_batch > 0:
         lb = measure_batched(cfg.with_(precision="mixed_fp32"), args.large_batch, 20, 3)
         need = workspace_bytes_of(cfg.with_(precision="mixed_fp32"))

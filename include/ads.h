@@ -57,11 +57,15 @@ typedef enum {
 typedef enum { ADS_PWAVE = 0, ADS_ELASTIC = 1 } ads_problem;
 
 /* Arithmetic of the right-hand-side quadrature.  Sweeps, factors and the
- * time update are FP64 in every mode. */
+ * time update are FP64 in every mode.  ADS_MIXED_BF16 contracts the
+ * predictor rounded to BF16 (the inputs a BF16 matrix unit would take; the
+ * basis tables stay FP32), then a second pass contracts the FP64 remainder
+ * and adds it (one correction step), FP32 arithmetic in both: two
+ * right-hand-side launches per step, P-wave only, not accepted by pools. */
 typedef enum {
   ADS_FP64 = 0,        /* FP64 sum-factorized quadrature                     */
   ADS_MIXED_FP32 = 1,  /* FP32 contractions, FP64 combination and assembly   */
-  ADS_MIXED_BF16 = 2   /* reserved                                           */
+  ADS_MIXED_BF16 = 2   /* BF16 inputs + FP64-remainder correction pass       */
 } ads_precision;
 
 /* Boundary conditions on all six faces.  ADS_BC_NATURAL is the homogeneous

@@ -142,6 +142,7 @@ struct ads_sim {
   int ncu = 0;          // compute units of the device (tiling of the right-hand side)
   int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
   bool mixed = false;   // FP32 contractions in the right-hand side
+  bool bf16 = false;    // ... on BF16 inputs, plus a correction pass on the remainder
   bool literal = false; // P-wave: the printed coefficient set (diagnostic)
   const double* coef = nullptr;   // P-wave: caller's c^2 at the Gauss points, or null
   double c2ref = 1.0;             // P-wave: c^2 of the split left-hand side
@@ -201,11 +202,11 @@ bool valid_params(const ads_params* prm, std::string& why) {
     why = "tau must be positive and finite";
     return false;
   }
-  if (prm->precision != ADS_FP64 && prm->precision != ADS_MIXED_FP32) {
-    why = "precision must be ADS_FP64 or ADS_MIXED_FP32";
+  if (prm->precision != ADS_FP64 && prm->precision != ADS_MIXED_FP32 && prm->precision != ADS_MIXED_BF16) {
+    why = "precision must be ADS_FP64, ADS_MIXED_FP32 or ADS_MIXED_BF16";
     return false;
   }
-  if (prm->precision == ADS_MIXED_FP32 && prm->problem != ADS_PWAVE) {
+  if (prm->precision != ADS_FP64 && prm->problem != ADS_PWAVE) {
     why = "mixed precision is implemented for the P-wave only";
     return false;
   }
@@ -238,7 +239,8 @@ void geometry(ads_sim* s) {
     s->off[d] = (flat || P.bc == ADS_BC_NATURAL) ? 0 : 1;
   }
   s->nfree = (long long)s->nf[0] * s->nf[1] * s->nf[2];
-  s->mixed = P.precision == ADS_MIXED_FP32;
+  s->mixed = P.precision == ADS_MIXED_FP32 || P.precision == ADS_MIXED_BF16;
+  s->bf16 = P.precision == ADS_MIXED_BF16;
 }
 
 // Walks every device allocation of a simulation (sizing and carving).
@@ -646,11 +648,25 @@ ads_status build_launches(ads_sim* s) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
     // (the printed coefficient set drops the u'' term of the predictor)
     RhsJob rj = rhs_pwave_job(s, 1.0, tau, s->literal ? 0.0 : eta, 1, s->mixed ? 1 : 0, s->rhs_var);
-    const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
-    if (!d) return fail(ADS_ENOMEM, err);
-    s->step_l.push_back(
-        Launch{Launch::RHS_P, d, 1, rj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(rj)});
-    s->step_l.back().coef = s->coef != nullptr;
+    // BF16 inputs: the predictor rounded to BF16, then a second pass on the
+    // remainder accumulated into R (the one-step correction)
+    std::vector<RhsJob> passes{rj};
+    if (s->bf16) {
+      passes[0].wsplit = 1;
+      RhsJob lo = rj;
+      lo.wsplit = 2;
+      lo.accumulate = 1;
+      lo.load = nullptr;
+      passes.push_back(lo);
+    }
+    const LaunchHdr* d = nullptr;
+    for (const RhsJob& pj : passes) {
+      d = s->arena.add(std::vector<RhsJob>{pj}, err);
+      if (!d) return fail(ADS_ENOMEM, err);
+      s->step_l.push_back(
+          Launch{Launch::RHS_P, d, 1, pj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(pj)});
+      s->step_l.back().coef = s->coef != nullptr;
+    }
     SweepJob z{};
     z.epi = s->literal ? EPI_NEWMARK_LITERAL : EPI_NEWMARK;
     z.c0 = tau;
@@ -1471,6 +1487,8 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
   for (int d = 0; d < 3; ++d)
     if (free_count(*prm, d) > kPoolMaxM) return fail(ADS_EINVAL, "pooled meshes: <= 128 free coefficients");
+  if (prm->precision == ADS_MIXED_BF16)
+    return fail(ADS_EINVAL, "ADS_MIXED_BF16 (two right-hand-side passes) is not pooled");
   int free_slot = -1;
   for (int i = 0; i < P->max_slots; ++i)
     if (!P->slots[i].sim) {

@@ -119,6 +119,8 @@ struct RhsJob {
   int amp_shift;          // amplitude index = *counter + amp_shift
   const unsigned long long* counter;
   double rscale;          // R = rscale * (amp * load - A(w))
+  int wsplit;             // P-wave: contract w (0), its BF16 rounding hi (1), or w - hi (2)
+  int accumulate;         // 1: R += rscale * (amp * load - A(w)) instead of R =
   const double* coef;     // P-wave: c^2 at every Gauss point [Ez q][Ey q][Ex q], or null (c^2 = 1)
   double lam, mu;         // elasticity Lame constants
   const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P]

@@ -59,6 +59,14 @@ __device__ __forceinline__ float row_shr1(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xF, 0xF, true));
 }
 
+// x rounded to the nearest BF16 value (ties to even), as an FP32 value;
+// finite inputs only (the predictor of a finite state)
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // sum_a o[a] of lane i-a, as a Horner chain of one-lane shifts
 template <int P, typename T>
 __device__ __forceinline__ T horner_shift(const T (&o)[P]) {
@@ -188,6 +196,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     const gmem<double>* __restrict__ LD = gview(J.load);
     gmem<double>* __restrict__ R = gview(J.R);
     const double rscale = J.rscale;
+    const bool accumulate = J.accumulate != 0;
 
     // forward y tables of the tile's y-elements (zero outside the mesh)
     const gmem<double>* tyg = gview(J.tab[1]);
@@ -281,12 +290,21 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
 #pragma unroll
       for (int i = 0; i < NF; ++i) pf[i] = (zv && pval[i]) ? pf[i] : 0.0;
     };
+    // BF16 input split (wsplit 1 / 2): hi = w rounded to BF16 (through
+    // FP32, to nearest even), lo = w - hi in FP64 (exact: hi is within a
+    // factor 2 of w); the two passes together contract w
+    const int wsplit = J.wsplit;
     auto commit_layer = [&](int cz) {
       T* dst = ring + (cz % P) * NC;
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
         const int k = tid + i * NT;
-        if (k < NC) dst[k] = (T)pf[i];
+        double w = pf[i];
+        if (wsplit != 0) {
+          const double hi = (double)bf16_round((float)w);
+          w = wsplit == 1 ? hi : w - hi;
+        }
+        if (k < NC) dst[k] = (T)w;
       }
     };
     const long long obase = (long long)(Y0 + cyo - oy) * nfx + (X0 + cxo - ox);
@@ -295,7 +313,8 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
       if (ocol && cz >= Z0 && cz < Zend) {
         const long long gi = (long long)(cz - oz) * sxy + obase;
         const double f = (LD != nullptr) ? ampv * LD[gi] : 0.0;
-        R[gi] = rscale * (f - accv);
+        const double r = rscale * (f - accv);
+        R[gi] = accumulate ? R[gi] + r : r;
       }
     };
 

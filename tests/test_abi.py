@@ -39,6 +39,7 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(p=1), dict(p=4), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
                                  dict(problem="elastic", mu=0.0), dict(problem="elastic", rho=-1.0),
                                  dict(problem="elastic", precision="mixed_fp32"),
+                                 dict(problem="elastic", precision="mixed_bf16"),
                                  dict(nelem=(600, 4, 4)), dict(bc=2), dict(bc=-1),
                                  dict(nelem=(511, 4, 4), bc="natural"),
                                  dict(problem="elastic", nelem=(4, 4, 0)), dict(nelem=(0, 4, 4))])
@@ -47,6 +48,12 @@ def test_invalid_params_rejected(lib, bad):
     with pytest.raises(binding.AdsError) as e:
         binding.workspace_bytes(_params(**bad))
     assert e.value.status == -1
+
+
+def test_precision_modes_accepted(lib):
+    from paper_1911_08158_amd import binding
+    sizes = {m: binding.workspace_bytes(_params(precision=m)) for m in ("fp64", "mixed_fp32", "mixed_bf16")}
+    assert len(set(sizes.values())) == 1, sizes   # same fields and tables in every mode
 
 
 def test_workspace_scales_linearly(lib):

@@ -1,7 +1,9 @@
 """Mixed-precision right-hand side (FP32 contractions, FP64 predictor,
 z-accumulation, assembly, factors, sweeps and update) against the FP64
 oracle: relative L2 error of u reported per step; target <= 1e-6 after 100
-steps on C3 (128^3 elements, p = 2)."""
+steps on C3 (128^3 elements, p = 2).  The BF16-input mode (predictor rounded
+to BF16, then a correction pass on the FP64 remainder) is held to the same
+bar."""
 import numpy as np
 import pytest
 
@@ -33,12 +35,40 @@ def test_mixed_small_meshes(cfg):
     sim.close()
 
 
-def test_mixed_c3_error_per_step():
+@pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
+                                 W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
+                         ids=["p2", "p3"])
+def test_bf16_inputs_small_meshes(cfg):
+    _cuda()
+    pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, precision="mixed_bf16", u0_full=pw.to_full(u0))
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, _, _ = sim.get_state()
+        e = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
+        assert e <= 1e-6, (k, e)
+    sim.close()
+
+
+def test_bf16_inputs_not_pooled():
+    _cuda()
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.binding import AdsError
+    pool = Pool(64 << 20, max_slots=2)
+    with pytest.raises(AdsError) as e:
+        pool.admit(W.C1, precision="mixed_bf16")
+    assert e.value.status == -1
+    pool.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_mixed_c3_error_per_step(precision):
     """C3, 100 steps: the error against the FP64 oracle at every 10th step."""
     _cuda()
     cfg = W.C3
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
-    sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0))
+    sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0))
     sim.factor()
     errs = []
     for k in range(1, cfg.steps + 1):
@@ -48,6 +78,6 @@ def test_mixed_c3_error_per_step():
             eu = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
             ev = rel_l2(v.cpu().numpy(), pw.to_full(hist[k][1]))
             errs.append((k, eu, ev))
-            print(f"C3 mixed step {k}: rel L2 u {eu:.3e} v {ev:.3e}", flush=True)
+            print(f"C3 {precision} step {k}: rel L2 u {eu:.3e} v {ev:.3e}", flush=True)
     sim.close()
     assert errs[-1][1] <= 1e-6, errs
