@@ -369,8 +369,8 @@ def main():
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the hot path is measured on one "
-              "MI355X; multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        print("bench.py: measures one GPU only (the hot path runs on one MI355X; sharding "
+              "across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import workloads as W
