@@ -357,7 +357,6 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
 // (lanes adjacent) are free of bank conflicts.
 
 constexpr int kPT = 256;   // threads per plane workgroup
-constexpr int kPL = 64;    // plane values per thread loaded before any is stored to LDS
 
 __device__ __forceinline__ int find_job_plane(const PlaneJob* jobs, int njobs, int tile) {
   int lo = 0, hi = njobs - 1;
@@ -368,14 +367,12 @@ __device__ __forceinline__ int find_job_plane(const PlaneJob* jobs, int njobs, i
   return lo;
 }
 
-// Substitution of one line in LDS with element i at col[i * st]; factor
-// rows fl = L[m*P], U[m*P], rd[m] in LDS (broadcast reads).  Same
-// arithmetic, in the same order, as `substitute`.
+// Substitution passes of one line with element i at col[i * st] in LDS;
+// factor rows fl = L[m*P], U[m*P], rd[m] in LDS (broadcast reads).  The
+// arithmetic and its order are those of `substitute`.  Forward pass:
 template <int P>
-__device__ __forceinline__ void substitute_st(double* col, int st, int m, const double* fl) {
+__device__ __forceinline__ void fwd_st(double* col, int st, int m, const double* fl) {
   const double* Lf = fl;
-  const double* Uf = fl + m * P;
-  const double* rdf = fl + 2 * m * P;
   const int nb = m / kSB;
   double h[P];
 #pragma unroll
@@ -410,6 +407,83 @@ __device__ __forceinline__ void substitute_st(double* col, int st, int m, const 
     h[0] = s;
     col[i * st] = s;
   }
+}
+
+// Forward pass fed from global memory: element i is scale * src[i]; the
+// results go to col[i] in LDS.  The line is read in chunks of 2 kSB values,
+// the next chunk's loads in flight while the current one is substituted,
+// so that the plane's loads overlap the forward recurrences.
+template <int P>
+__device__ __forceinline__ void fwd_from_global(const gmem<double>* __restrict__ src, double scale, double* col,
+                                                int m, const double* fl) {
+  constexpr int C = 2 * kSB;
+  const double* Lf = fl;
+  const int nc = m / C;
+  double h[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = 0.0;
+  double va[C], vb[C];
+  auto load = [&](double (&v)[C], int c) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) v[k] = src[c * C + k];
+  };
+  auto run = [&](const double (&v)[C], int c) {
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      const int r0 = c * C + hb * kSB;
+      const double* Lb = Lf + r0 * P;
+      double f[kSB][P];
+#pragma unroll
+      for (int k = 0; k < kSB; ++k)
+#pragma unroll
+        for (int j = 0; j < P; ++j) f[k][j] = Lb[k * P + j];
+#pragma unroll
+      for (int k = 0; k < kSB; ++k) {
+        double s = scale * v[hb * kSB + k];
+#pragma unroll
+        for (int j = P - 1; j >= 0; --j) s = fma(-f[k][j], h[j], s);
+#pragma unroll
+        for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+        h[0] = s;
+        col[r0 + k] = s;
+      }
+    }
+  };
+  // chunks in pairs, each chunk's loads issued before the other chunk is
+  // substituted (every use unconditional, so that no load is moved next to
+  // its use; past the end the va reload re-reads the last chunk); the
+  // scheduling barriers keep the loads ahead of the substitution
+  if (nc > 0) load(va, 0);
+  int c = 0;
+  for (; c + 1 < nc; c += 2) {
+    load(vb, c + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    run(va, c);
+    load(va, min(c + 2, nc - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    run(vb, c + 1);
+  }
+  if (c < nc) run(va, c);
+  for (int i = nc * C; i < m; ++i) {
+    double s = scale * src[i];
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) s = fma(-Lf[i * P + j], h[j], s);
+#pragma unroll
+    for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
+    h[0] = s;
+    col[i] = s;
+  }
+}
+
+// Backward pass on the LDS line; each result is stored to dst[i * ds] in
+// global memory (ToGlobal) or back to col[i * st].
+template <int P, bool ToGlobal>
+__device__ __forceinline__ void bwd_st(double* col, int st, gmem<double>* __restrict__ dst, long long ds, int m,
+                                       const double* fl) {
+  const double* Uf = fl + m * P;
+  const double* rdf = fl + 2 * m * P;
+  const int nb = m / kSB;
+  double h[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) h[k] = 0.0;
   for (int i = m - 1; i >= nb * kSB; --i) {
@@ -420,7 +494,8 @@ __device__ __forceinline__ void substitute_st(double* col, int st, int m, const 
 #pragma unroll
     for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
     h[0] = s;
-    col[i * st] = s;
+    if constexpr (ToGlobal) dst[i * ds] = s;
+    else col[i * st] = s;
   }
   for (int b = nb - 1; b >= 0; --b) {
     double* rb = col + b * kSB * st;
@@ -443,7 +518,8 @@ __device__ __forceinline__ void substitute_st(double* col, int st, int m, const 
 #pragma unroll
       for (int j = P - 1; j > 0; --j) h[j] = h[j - 1];
       h[0] = s;
-      rb[k * st] = s;
+      if constexpr (ToGlobal) dst[(b * kSB + k) * ds] = s;
+      else rb[k * st] = s;
     }
   }
 }
@@ -468,7 +544,7 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
     double* pl = lds;
     double* fxl = pl + (size_t)ny * PX;
     double* fyl = fxl + (2 * p + 1) * nx;
-    __syncthreads();   // the previous plane's stores have read the LDS
+    __syncthreads();   // the previous plane's last reads of the LDS are done
     if (jb != staged) {
       const gmem<double>* lx = gview(J.fx.L);
       const gmem<double>* ux = gview(J.fx.U);
@@ -487,45 +563,36 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
       }
       for (int k = tid; k < ny; k += kPT) fyl[2 * ny * p + k] = ry[k];
       staged = jb;
+      __syncthreads();
     }
-    // load the plane (all of a thread's loads of a chunk before any store
-    // to LDS).  Row of flat index k from a float reciprocal: (k + 1/2)/nx
-    // lies at least 1/(2 nx) from an integer and is computed with a
-    // relative error below 2^-22, i.e. an absolute error below ny 2^-22,
-    // which is smaller whenever nx ny < 2^21 (a plane that fits in LDS
-    // holds at most 20480 unknowns)
     const long long gb = (long long)(t - J.tile0) * n;
     const gmem<double>* __restrict__ gin = gview(J.in) + gb;
+    gmem<double>* __restrict__ gout = gview(J.out) + gb;
     const double scale = J.scale;
-    const float rnx = 1.0f / (float)nx;
-    for (int k0 = 0; k0 < n; k0 += kPT * kPL) {
-      double v[kPL];
-#pragma unroll
-      for (int i = 0; i < kPL; ++i) v[i] = gin[min(k0 + i * kPT + tid, n - 1)];
-#pragma unroll
-      for (int i = 0; i < kPL; ++i) {
-        const int k = k0 + i * kPT + tid;
-        if (k < n) {
-          const int y = (int)(((float)k + 0.5f) * rnx), x = k - y * nx;
-          pl[y * PX + x] = scale * v[i];
-        }
+    // x-lines: the forward pass reads the line from global memory (the
+    // plane's loads overlap the recurrences), the backward pass works in
+    // LDS; a thread per line, lanes a padded row apart
+    for (int y = tid; y < ny; y += kPT) {
+      double* col = pl + y * PX;
+      if (p == 2) {
+        fwd_from_global<2>(gin + (long long)y * nx, scale, col, nx, fxl);
+        bwd_st<2, false>(col, 1, nullptr, 0, nx, fxl);
+      } else {
+        fwd_from_global<3>(gin + (long long)y * nx, scale, col, nx, fxl);
+        bwd_st<3, false>(col, 1, nullptr, 0, nx, fxl);
       }
     }
     __syncthreads();
-    for (int y = tid; y < ny; y += kPT) {
-      if (p == 2) substitute_st<2>(pl + y * PX, 1, nx, fxl);
-      else substitute_st<3>(pl + y * PX, 1, nx, fxl);
-    }
-    __syncthreads();
+    // y-lines: forward pass in LDS, the backward pass stores each final
+    // value (a row of adjacent lanes: coalesced) instead of writing it back
     for (int x = tid; x < nx; x += kPT) {
-      if (p == 2) substitute_st<2>(pl + x, PX, ny, fyl);
-      else substitute_st<3>(pl + x, PX, ny, fyl);
-    }
-    __syncthreads();
-    gmem<double>* __restrict__ gout = gview(J.out) + gb;
-    for (int k = tid; k < n; k += kPT) {
-      const int y = (int)(((float)k + 0.5f) * rnx), x = k - y * nx;
-      gout[k] = pl[y * PX + x];
+      if (p == 2) {
+        fwd_st<2>(pl + x, PX, ny, fyl);
+        bwd_st<2, true>(pl + x, PX, gout + x, nx, ny, fyl);
+      } else {
+        fwd_st<3>(pl + x, PX, ny, fyl);
+        bwd_st<3, true>(pl + x, PX, gout + x, nx, ny, fyl);
+      }
     }
   }
 }
