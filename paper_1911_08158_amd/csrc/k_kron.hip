@@ -7,13 +7,14 @@
 //
 // Sum factorization on gfx950: a workgroup owns a KTX x KTY column tile and
 // a z-range of outputs and walks the source layers that reach the range.
-// Per source layer and term it stages the layer (with a p-halo in x and y)
-// in LDS, applies the x-band (LDS -> LDS), then the y-band (one thread per
-// owned column) and scatters the result through the z-band into 2p+1
-// register accumulators (outputs zs-p .. zs+p); the oldest accumulator is
-// complete after each layer and is written out.  The next layer's global
-// loads are in flight while the current one is contracted.  The band rows
-// of every term for the tile's columns are staged once per tile.
+// Per source layer it stages the layer of every term (with a p-halo in x
+// and y) in LDS, applies the x-bands (LDS -> LDS), then per term the y-band
+// (one thread per owned column) and scatters the result through the z-band
+// into 2p+1 register accumulators (outputs zs-p .. zs+p); the oldest
+// accumulator is complete after each layer and is written out.  The next
+// layer's global loads, all terms at once, are in flight while the current
+// one is contracted (one load latency and two barriers per layer).  The
+// band rows of every term for the tile's columns are staged once per tile.
 #include <algorithm>
 
 #include "common.hpp"
@@ -37,18 +38,20 @@ struct KronGeom {
   static constexpr int B = 2 * p + 1;
   static constexpr int SX = KTX + 2 * p, SY = KTY + 2 * p;
   static constexpr int NS = (SY * SX + KNT - 1) / KNT;   // layer loads per thread
-  static constexpr int NX = (SY * KTX + KNT - 1) / KNT;  // x-band items per thread
-  // LDS: S [SY][SX], X [SY][KTX], band rows [terms][KTX + KTY][B]
-  static constexpr size_t lds_elems = (size_t)SY * SX + SY * KTX + (size_t)kKronMaxTerms * (KTX + KTY) * B;
+  static constexpr int NX = (SY * KTX + KNT - 1) / KNT;  // x-band items per thread and term
+  // LDS: S [terms][SY][SX], X [terms][SY][KTX], band rows [terms][KTX + KTY][B]
+  static constexpr size_t lds_elems =
+      (size_t)kKronMaxTerms * (SY * SX + SY * KTX) + (size_t)kKronMaxTerms * (KTX + KTY) * B;
 };
 
 template <int p>
 __device__ void kron_tile(const KronJob& J, int t, double* lds) {
   using Gm = KronGeom<p>;
   constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NX = Gm::NX;
-  double* S = lds;
-  double* X = S + SY * SX;
-  double* Tb = X + SY * KTX;
+  constexpr int MT = kKronMaxTerms;
+  double* S = lds;                      // [MT][SY][SX]
+  double* X = S + MT * SY * SX;         // [MT][SY][KTX]
+  double* Tb = X + MT * SY * KTX;
   const int tid = threadIdx.x, lx = tid % KTX, ly = tid / KTX;
   const int tx = t % J.tiles[0], t2 = t / J.tiles[0];
   const int ty = t2 % J.tiles[1], tz = t2 / J.tiles[1];
@@ -80,15 +83,22 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
     soff[i] = (long long)y * nx + x;
   }
   const long long sxy = (long long)nx * ny;
-  double pf[NS];
-  // (positions outside the field load offset 0 of the layer and are
-  // zeroed: no branch around the loads)
-  auto prefetch = [&](int zs, int term) {
-    const gmem<double>* src = gview(J.term[term].src) + (long long)zs * sxy;
+  double pf[MT][NS];
+  // layer zs of every term (positions outside the field load offset 0 of
+  // the layer and are zeroed: no branch around the loads)
+  auto prefetch = [&](int zs) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) pf[i] = src[sval[i] ? soff[i] : 0];
+    for (int term = 0; term < MT; ++term) {
+      if (term < nt) {
+        const gmem<double>* src = gview(J.term[term].src) + (long long)zs * sxy;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) pf[i] = sval[i] ? pf[i] : 0.0;
+        for (int i = 0; i < NS; ++i) pf[term][i] = src[sval[i] ? soff[i] : 0];
+      }
+    }
+#pragma unroll
+    for (int term = 0; term < MT; ++term)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) pf[term][i] = sval[i] ? pf[term][i] : 0.0;
   };
   const bool ocol = X0 + lx < nx && Y0 + ly < ny;
   const long long obase = (long long)(Y0 + ly) * nx + X0 + lx;
@@ -106,36 +116,45 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
   for (int k = 0; k < B; ++k) acc[k] = 0.0;
   // window: acc[k] is output z = zs - p + k
   const int zs0 = max(0, Z0 - p), zs1 = min(nz - 1, Z1 - 1 + p);
-  prefetch(zs0, 0);
+  prefetch(zs0);
   for (int zs = zs0; zs <= zs1; ++zs) {
-    for (int term = 0; term < nt; ++term) {
 #pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        const int k = tid + i * KNT;
-        if (k < SY * SX) S[k] = pf[i];
+    for (int term = 0; term < MT; ++term) {
+      if (term < nt) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const int k = tid + i * KNT;
+          if (k < SY * SX) S[term * (SY * SX) + k] = pf[term][i];
+        }
       }
-      __syncthreads();
-      // next (layer, term) in flight during the contractions
-      if (term + 1 < nt) prefetch(zs, term + 1);
-      else if (zs < zs1) prefetch(zs + 1, 0);
+    }
+    __syncthreads();
+    // the next layer in flight during the contractions
+    if (zs < zs1) prefetch(zs + 1);
+    for (int term = 0; term < nt; ++term) {
       const double* tbx = Tb + term * ((KTX + KTY) * B);
+      const double* St = S + term * (SY * SX);
+      double* Xt = X + term * (SY * KTX);
 #pragma unroll
       for (int i = 0; i < NX; ++i) {
         const int k = tid + i * KNT;
         if (k < SY * KTX) {
           const int yy = k / KTX, xo = k - yy * KTX;
-          const double* srow = S + yy * SX + xo;
+          const double* srow = St + yy * SX + xo;
           double s = tbx[xo * B] * srow[0];
 #pragma unroll
           for (int a = 1; a < B; ++a) s = fma(tbx[xo * B + a], srow[a], s);
-          X[k] = s;
+          Xt[k] = s;
         }
       }
-      __syncthreads();
-      const double* tby = tbx + KTX * B + ly * B;
-      double sy = tby[0] * X[ly * KTX + lx];
+    }
+    __syncthreads();
+    for (int term = 0; term < nt; ++term) {
+      const double* tby = Tb + term * ((KTX + KTY) * B) + KTX * B + ly * B;
+      const double* Xt = X + term * (SY * KTX);
+      double sy = tby[0] * Xt[ly * KTX + lx];
 #pragma unroll
-      for (int b = 1; b < B; ++b) sy = fma(tby[b], X[(ly + b) * KTX + lx], sy);
+      for (int b = 1; b < B; ++b) sy = fma(tby[b], Xt[(ly + b) * KTX + lx], sy);
       sy *= J.term[term].coef;
       // z band at wave-uniform rows: scalar loads
       const cmem<double>* Tz = cview(J.term[term].T[2]);
