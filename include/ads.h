@@ -268,7 +268,8 @@ ads_status ads_pool_step(ads_pool* pool, int32_t nsteps);
 /* Leave the batch and release the slot's memory (read the state first with
  * ads_get_state on ads_pool_sim's handle; the release is stream-ordered). */
 ads_status ads_pool_retire(ads_pool* pool, int32_t slot);
-/* Durations (ms) of the pool steps since the last call (synchronizes). */
+/* Durations (ms) of the pool steps since the last call (synchronizes); at
+ * most 65536 steps are timed between two calls, later ones are not. */
 ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int32_t* n);
 /* Kernel timing of pool steps (measurement support): with enable = 1 the
  * following ads_pool_step calls enqueue the launches directly (no graph)

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,13 @@ ads_status fail(ads_status s, const std::string& msg) {
     if (e_ != hipSuccess)                                                                   \
       return fail(ADS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
   } while (0)
+
+// Kernel attributes (dynamic LDS above the default) are set once per
+// process; the static's initialization is thread-safe.
+hipError_t set_attributes_once() {
+  static const hipError_t e = sweep_set_attributes();
+  return e;
+}
 
 constexpr int kAmpCap = 4096;
 constexpr size_t kAlign = 256;
@@ -799,15 +807,12 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   size_t need = 0;
   ads_workspace_bytes(prm, &need);
   if (bytes < need) return fail(ADS_ENOMEM, "workspace smaller than ads_workspace_bytes");
-  static bool attrs = false;
-  if (!attrs) {
-    HIPCHECK(sweep_set_attributes());
-    attrs = true;
-  }
+  HIPCHECK(set_attributes_once());
   int dev = 0, ncu = 0;
   HIPCHECK(hipGetDevice(&dev));
   HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   ads_sim* s = new ads_sim();
+  std::unique_ptr<ads_sim> owner(s);   // frees the handle on every error return
   s->prm = *prm;
   s->stream = (hipStream_t)stream;
   geometry(s);
@@ -825,10 +830,6 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
     s->Kf[d] = restrict_band(K, s->off[d], s->nf[d]);
     s->Gf[d] = restrict_band(G, s->off[d], s->nf[d]);
   }
-  auto cleanup = [&](ads_status st) {
-    delete s;
-    return st;
-  };
   ads_status st;
   for (int d = 0; d < 3; ++d) {
     const Tables1D& t = s->tab[d];
@@ -838,15 +839,15 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
     buf.insert(buf.end(), t.W.begin(), t.W.end());
     for (const std::vector<double>* v : {&t.N, &t.D})
       for (size_t k = 0; k < v->size(); ++k) buf.push_back(t.W[k / s->P] * (*v)[k]);
-    if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return cleanup(st);
-    if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return cleanup(st);
+    if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return st;
+    if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return st;
     if (s->elastic) {
       Band GT = s->Gf[d];
       for (int i = 0; i < GT.n; ++i)
         for (int j = std::max(0, i - GT.p); j <= std::min(GT.n - 1, i + GT.p); ++j) GT.at(i, j) = s->Gf[d].at(j, i);
-      if ((st = upload(s, s->d_bandM[d], s->Mf[d].a.data(), s->Mf[d].a.size() * 8)) != ADS_OK) return cleanup(st);
-      if ((st = upload(s, s->d_bandG[d], s->Gf[d].a.data(), s->Gf[d].a.size() * 8)) != ADS_OK) return cleanup(st);
-      if ((st = upload(s, s->d_bandGT[d], GT.a.data(), GT.a.size() * 8)) != ADS_OK) return cleanup(st);
+      if ((st = upload(s, s->d_bandM[d], s->Mf[d].a.data(), s->Mf[d].a.size() * 8)) != ADS_OK) return st;
+      if ((st = upload(s, s->d_bandG[d], s->Gf[d].a.data(), s->Gf[d].a.size() * 8)) != ADS_OK) return st;
+      if ((st = upload(s, s->d_bandGT[d], GT.a.data(), GT.a.size() * 8)) != ADS_OK) return st;
     }
   }
   const int nc = s->ncomp;
@@ -854,15 +855,15 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   // state: u (U^n), v (u' for the P-wave; V^0 then U^{n-1} for elasticity), a
   if (launch_full_to_free(u0, s->u, s->n, s->nf, s->off, nc, s->stream) != hipSuccess ||
       launch_full_to_free(v0, s->v, s->n, s->nf, s->off, nc, s->stream) != hipSuccess)
-    return cleanup(fail(ADS_EDEVICE, "layout copy failed"));
+    return fail(ADS_EDEVICE, "layout copy failed");
   if (s->a) HIPCHECK(launch_fill(s->a, nfr, 0.0, s->stream));
   HIPCHECK(launch_fill(s->load, nfr * nc, 0.0, s->stream));
   HIPCHECK(launch_fill(s->amp, kAmpCap, 0.0, s->stream));
   HIPCHECK(launch_set_u64(s->counter, 0ull, s->stream));
-  if ((st = build_launches(s)) != ADS_OK) return cleanup(st);
+  if ((st = build_launches(s)) != ADS_OK) return st;
   HIPCHECK(hipStreamSynchronize(s->stream));
   s->need_start = true;
-  *out = s;
+  *out = owner.release();
   return ADS_OK;
 }
 
@@ -1220,6 +1221,7 @@ namespace {
 // the first (elasticity: 6 x 2 + 5; the P-wave uses the first two).
 constexpr int kPoolStages = 17;
 constexpr int kPoolMaxM = 128;    // free coefficients per direction in pooled simulations
+constexpr int kStepEventCap = 1 << 16;   // pool steps timed between two ads_pool_step_times calls
 static_assert(kPoolMaxM <= 128, "a pooled z-plane fits in LDS");
 
 bool is_kron_stage(int k) { return k % 3 == 0; }    // stages 3, 6, 9, 12, 15
@@ -1444,11 +1446,7 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
   if (((uintptr_t)ws) % kAlign) return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
   if (max_slots < 1 || max_slots > 256) return fail(ADS_EINVAL, "max_slots must be in [1, 256]");
   if (use_graph && !stream) return fail(ADS_EINVAL, "graph replay needs a non-default stream");
-  static bool attrs = false;
-  if (!attrs) {
-    HIPCHECK(sweep_set_attributes());
-    attrs = true;
-  }
+  HIPCHECK(set_attributes_once());
   int dev = 0, ncu = 0;
   HIPCHECK(hipGetDevice(&dev));
   HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1584,6 +1582,8 @@ ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
     } else if ((st = pool_enqueue(P)) != ADS_OK) {
       return st;
     }
+    // step times are kept for at most kStepEventCap steps between reads
+    if (P->nev > kStepEventCap) continue;
     if ((int)P->ev.size() <= P->nev) {
       hipEvent_t e;
       HIPCHECK(hipEventCreate(&e));
