@@ -28,7 +28,7 @@ def _cuda():
     W.C1.with_(nelem=(300, 128, 128), steps=2, init="noise"),   # many lines too long for 16-line LDS tiles
     W.C1.with_(nelem=(512, 4, 3), steps=2, init="noise"),       # the longest lines accepted
     W.C1.with_(nelem=(3, 300, 2), steps=2, init="noise"),       # in-plane sweeps: more x-lines than threads
-    W.C1.with_(nelem=(200, 90, 2), steps=2, init="noise"),      # in-plane: a 145 KB plane, loaded in two chunks
+    W.C1.with_(nelem=(200, 90, 2), steps=2, init="noise"),      # in-plane: a 145 KB plane, x-lines of 200 (12 chunks + a tail)
     W.C1.with_(nelem=(40, 70, 3), steps=3, init="noise"),       # in-plane: 40 x 70 planes, lines of unequal lengths
     W.C1.with_(nelem=(50, 33, 2), p=3, q=4, steps=3, init="noise"),   # in-plane, p=3: 51 x 34 planes
     W.C1.with_(nelem=(45, 30, 2), steps=3, init="noise", bc="natural"),  # in-plane without elimination: 47 x 32 planes
