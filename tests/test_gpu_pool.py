@@ -126,3 +126,45 @@ def test_admission_by_memory():
     again = pool.admit(cfg)
     assert again is not None and again.slot == got[1].slot
     pool.close()
+
+
+def test_benchmark_batch_full_size():
+    """The configuration the benchmark times: four 128^3 p=2 simulations with
+    the mixed-precision right-hand side in one pool, one graph replay per
+    step.  They start from different seeded fields; each equals its run
+    alone bitwise, and the first stays within 1e-6 of the FP64 oracle
+    (started from the oracle's projection)."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.binding import Params, workspace_bytes
+    nsteps = 10
+    cfgs = [W.C3.with_(steps=nsteps)] + [W.C3.with_(steps=nsteps, init=f"gauss1:{k}") for k in (11, 12, 13)]
+    pw, u0, (ur, _, _) = oracle_pwave(cfgs[0], nsteps)
+    starts = [pw.to_full(u0), None, None, None]
+    need = workspace_bytes(Params.of(cfgs[0], precision="mixed_fp32"))
+    pool = Pool((8 << 20) + 4 * (need + 4096), max_slots=4, use_graph=True)
+    sims = []
+    for c, u in zip(cfgs, starts):
+        s = pool.admit(c, precision="mixed_fp32")
+        if u is None:
+            _setup(s, c)
+        else:
+            s.set_state(torch.from_numpy(u).cuda(), None, None, 0)
+            s.factor()
+        pool.activate(s)
+        sims.append(s)
+    pool.step(nsteps)
+    outs = [[t.cpu().numpy() for t in s.get_state() if t is not None] for s in sims]
+    pool.close()
+    e = rel_l2(outs[0][0], pw.to_full(ur))
+    print(f"batched 4 x 128^3 mixed, {nsteps} steps: rel L2 u {e:.3e}", flush=True)
+    assert e <= 1e-6, e
+    for c, u, out in zip(cfgs, starts, outs):
+        sim, _ = gpu_sim(c, precision="mixed_fp32", u0_full=u)
+        sim.factor()
+        sim.step(nsteps)
+        ref = [t.cpu().numpy() for t in sim.get_state() if t is not None]
+        sim.close()
+        for x, y in zip(out, ref):
+            assert np.array_equal(x, y), c.init
