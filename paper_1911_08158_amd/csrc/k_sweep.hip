@@ -351,10 +351,12 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
 // 128 x 128 FP64 unknowns (padded rows of nx + 1) with the x- and y-factor
 // rows, so one workgroup solves the x-lines and then the y-lines of a plane
 // without writing the intermediate to memory: 16 B per unknown instead of
-// 32 for the two sweeps, and one lane per line with all lanes of the
-// workgroup busy (a thread per x-line, then a thread per y-line).  With the
-// odd row pitch the x-lines' accesses (lanes a row apart) and the y-lines'
-// (lanes adjacent) are free of bank conflicts.
+// 32 for the two sweeps, a thread per x-line, then a thread per y-line.
+// The memory traffic rides on the recurrences: the x-forward pass reads its
+// line from global memory with the next chunk in flight, and the y-backward
+// pass stores each final value as it is produced.  With the odd row pitch
+// the x-lines' LDS accesses (lanes a row apart) and the y-lines' (lanes
+// adjacent) are free of bank conflicts.
 
 constexpr int kPT = 256;   // threads per plane workgroup
 
