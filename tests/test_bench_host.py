@@ -1,0 +1,44 @@
+"""Host logic of bench.py (no GPU): the algorithmic counts its roofline
+uses and its refusal of more than one GPU."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _count_sumfact_fmas(P, q):
+    """FMAs per element of the tile-shared sum factorization, counted stage
+    by stage: forward z (value and derivative of a shared column at q
+    points), forward y (value, y- and z-derivative rows), forward x (three
+    gradient components at q^3 points), the pointwise weights, and the
+    transposed backward stages."""
+    fwd_z = 2 * q * P            # per coefficient column (one per element in a tile's interior)
+    fwd_y = 3 * q * P * q        # per x-column and z Gauss point: 3 outputs at q y-points
+    fwd_x = 3 * q * P * q * q    # per Gauss row (q^2 of them): 3 components at q x-points
+    point = 3 * q ** 3
+    return 2 * (fwd_z + fwd_y + fwd_x) + point
+
+
+def test_rhs_flop_count():
+    # 765 / 2,176 FMAs per element for p = 2 / 3 (q = p + 1)
+    assert _count_sumfact_fmas(3, 3) == 765 and _count_sumfact_fmas(4, 4) == 2176
+    for p in (2, 3):
+        assert bench.rhs_flops_per_element(p) == 2 * _count_sumfact_fmas(p + 1, p + 1)
+
+
+def test_sweep_bytes_per_dof():
+    # in-plane x+y: read R, write the y-solved field; z with the Newmark
+    # update: read X and u, u', u'', write u, u', u''
+    assert bench.SWEEP_BYTES["sweep_xy"] == 8 + 8
+    assert bench.SWEEP_BYTES["sweep_z"] == 8 + 3 * 8 + 3 * 8
+
+
+def test_more_than_one_gpu_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
