@@ -220,6 +220,30 @@ def measure_small_latency(cfg, steps, warmup):
     }
 
 
+def measure_accuracy(cfg, steps):
+    """Error of the reduced-precision forms: relative L2 of u after `steps`
+    steps of the mixed FP32 and the BF16-input forms against the FP64 form,
+    all three started from the same projected initial state (the FP64 form
+    itself matches the FP64 oracle to <= 1e-12 in the parity tests)."""
+    import torch
+    from paper_1911_08158_amd import Sim
+    ref, out = None, {}
+    for prec in ("fp64", "mixed_fp32", "mixed_bf16"):
+        sim = Sim(cfg, device="cuda:0", precision=prec)
+        setup_sim(sim, cfg)
+        sim.step(steps)
+        u = sim.get_state()[0].to(torch.float64)
+        sim.close()
+        if ref is None:
+            ref = u
+        else:
+            out[prec] = float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
+    return {"workload": f"P-wave 128^3 elements p=2, one simulation per form, {steps} steps",
+            "rel_l2_u_vs_fp64": out,
+            "reference": "the FP64 form from the same initial coefficients (within 1e-12 of the FP64 oracle "
+                         "in the parity tests)"}
+
+
 def measure_elastic(cfg, steps, warmup):
     """Elasticity (alternating-triangular step), one FP64 simulation."""
     import torch
@@ -365,7 +389,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic"], default=None,
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy"], default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -390,6 +414,9 @@ def main():
         return
     if args.only == "elastic":
         print(json.dumps({"form": "elastic", **measure_elastic(W.C4, args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "accuracy":
+        print(json.dumps({"form": "accuracy", **measure_accuracy(cfg, args.steps)}), flush=True)
         return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
@@ -427,6 +454,7 @@ def main():
                                     "unit": "TFLOP/s", "frac": round(rhs64["tflops"] / FP64_PEAK_TFLOPS, 4)},
         "gpu": gpu_info(),
     }
+    out["accuracy"] = measure_accuracy(cfg, 100)
     out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup)
     c2 = W.C2.with_(precision="fp64")
     out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
