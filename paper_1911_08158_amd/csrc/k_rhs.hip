@@ -248,6 +248,41 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
         }
       }
     }
+    // Without a wave-speed field nothing pointwise sits between the x-forward
+    // and the x-backward contraction of a channel, so the pair is one 3x3
+    // (PxP) element matrix: the x-stiffness Kx = sum_g w_g D_g D_g^T for the
+    // x-derivative channel (rows and columns 1.. only: its rows and columns
+    // sum to zero, as the derivative tables do) and the x-mass
+    // Mx = sum_g w_g N_g N_g^T for the other two; formed in FP64 per lane.
+    T Kx[P - 1][P - 1], Mx[P][P];
+    if constexpr (!CF) {
+      const gmem<double>* txg = gview(J.tab[0]);
+      double k[P - 1][P - 1] = {}, mm[P][P] = {};
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        const double w = exv ? txg[2ll * Ex * Q * P + (long long)ex * Q + g] : 0.0;
+        double n[P], d[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          n[a] = exv ? txg[((long long)ex * Q + g) * P + a] : 0.0;
+          d[a] = exv ? txg[((long long)(Ex + ex) * Q + g) * P + a] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int b = 0; b < P; ++b) {
+            mm[a][b] = fma(w * n[a], n[b], mm[a][b]);
+            if (a > 0 && b > 0) k[a - 1][b - 1] = fma(w * d[a], d[b], k[a - 1][b - 1]);
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          Mx[a][b] = (T)mm[a][b];
+          if (a > 0 && b > 0) Kx[a - 1][b - 1] = (T)k[a - 1][b - 1];
+        }
+    }
     // backward x table entries at Gauss point gx
     auto bxN = [&](int gx, int a) -> T { if constexpr (kFoldX) return xNw[gx][a]; else return xN[gx][a]; };
     auto bxD = [&](int gx, int a) -> T { if constexpr (kFoldX) return xDw[gx][a]; else return xD[gx][a]; };
@@ -461,6 +496,27 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
 #pragma unroll
           for (int a = 1; a < P; ++a) d0[a] = c0[a] - c0[0];
           T o0[P], o1[P], o2[P];
+          if constexpr (!CF) {
+            // element matrices (see Kx, Mx): o0 = Kx d0, o1 = Mx c1, o2 = Mx c2
+#pragma unroll
+            for (int a = 1; a < P; ++a) {
+              T s = Kx[a - 1][0] * d0[1];
+#pragma unroll
+              for (int b = 2; b < P; ++b) s = fma(Kx[a - 1][b - 1], d0[b], s);
+              o0[a] = s;
+            }
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+              T s1 = Mx[a][0] * c1[0], s2 = Mx[a][0] * c2[0];
+#pragma unroll
+              for (int b = 1; b < P; ++b) {
+                s1 = fma(Mx[a][b], c1[b], s1);
+                s2 = fma(Mx[a][b], c2[b], s2);
+              }
+              o1[a] = s1;
+              o2[a] = s2;
+            }
+          } else {
 #pragma unroll
           for (int gx = 0; gx < Q; ++gx) {
             T gX = xD[gx][1] * d0[1], gY = xN[gx][0] * c1[0], gZ = xN[gx][0] * c2[0];
@@ -497,6 +553,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
                 o2[a] = fma(bxN(gx, a), gZ, o2[a]);
               }
             }
+          }
           }
           // backward derivative tables sum to zero: slot 0 from the others
           {
