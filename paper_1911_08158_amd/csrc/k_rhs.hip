@@ -161,13 +161,14 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
   const int yr0 = (wv * WE + yel) * Q;
   const int ysb = rowpos(yr0) + j, ypar = yr0 & 1, yty = (wv * WE + yel) * TS, yzc = yel * TXH + j;
   const bool xok = lane < NYX;
-  int xsb, xty, xzc;
+  int xsb, xty, xzc, xa;
   {
     const int gy = lane % Q, rest = lane / Q;
     const int el = rest / p, cx = 16 + rest % p;
     xsb = rowpos((wv * WE + el) * Q + gy) + cx;
     xty = (wv * WE + el) * TS + gy * P;
     xzc = el * TXH + cx;
+    xa = gy;   // without a field: the row's local y-slot
   }
   // x-stage rows of this row group: wave rows 4i + grp (same parity as
   // grp, so row i sits 2i rows of TXH further on)
@@ -198,18 +199,46 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     const double rscale = J.rscale;
     const bool accumulate = J.accumulate != 0;
 
-    // forward y tables of the tile's y-elements (zero outside the mesh)
     const gmem<double>* tyg = gview(J.tab[1]);
-    for (int k = tid; k < EY * Q * P; k += NT) {
-      const int eyl = k / (Q * P), rest = k - eyl * (Q * P);
-      const int ey = Y0 - p + eyl;
-      const bool v = ey >= 0 && ey < Ey;
-      tyl[eyl * TS + rest] = v ? (T)tyg[(long long)ey * Q * P + rest] : T(0);
-      tyl[eyl * TS + Q * P + rest] = v ? (T)tyg[(long long)(Ey + ey) * Q * P + rest] : T(0);
+    if constexpr (CF) {
+      // forward y tables of the tile's y-elements (zero outside the mesh)
+      for (int k = tid; k < EY * Q * P; k += NT) {
+        const int eyl = k / (Q * P), rest = k - eyl * (Q * P);
+        const int ey = Y0 - p + eyl;
+        const bool v = ey >= 0 && ey < Ey;
+        tyl[eyl * TS + rest] = v ? (T)tyg[(long long)ey * Q * P + rest] : T(0);
+        tyl[eyl * TS + Q * P + rest] = v ? (T)tyg[(long long)(Ey + ey) * Q * P + rest] : T(0);
+      }
+    } else {
+      // Without a field the y-forward and y-backward contractions of a
+      // channel collapse as in x: per y-element the mass matrix
+      // My = sum_g w_g N_g N_g^T, then the stiffness Ky = sum_g w_g D_g D_g^T
+      // (rows and columns 1..), formed in FP64 (zero outside the mesh).  Rows
+      // of the Gauss-row buffer then hold the local y-slots of an element.
+      constexpr int NM = P * P + (P - 1) * (P - 1);
+      static_assert(NM <= 2 * Q * P, "element matrices fit the table stride");
+      for (int k = tid; k < EY * NM; k += NT) {
+        const int eyl = k / NM, r = k - eyl * NM;
+        const int ey = Y0 - p + eyl;
+        const bool mass = r < P * P;
+        const int rr = mass ? r : r - P * P;
+        const int a = mass ? rr / P : rr / (P - 1) + 1, b = mass ? rr % P : rr % (P - 1) + 1;
+        const long long tb = mass ? 0 : (long long)Ey * Q * P;
+        double sm = 0.0;
+        if (ey >= 0 && ey < Ey) {
+          for (int g = 0; g < Q; ++g) {
+            const double w = tyg[2ll * Ey * Q * P + (long long)ey * Q + g];
+            const long long o = tb + ((long long)ey * Q + g) * P;
+            sm = fma(w * tyg[o + a], tyg[o + b], sm);
+          }
+        }
+        tyl[eyl * TS + r] = (T)sm;
+      }
     }
     // backward y tables of the owned column, y-weights folded in:
     // slot b of y-element cyo + p - b at Gauss point gy
     T bN[P][Q], bD[P][Q];
+    if constexpr (CF)
 #pragma unroll
     for (int b = 0; b < P; ++b) {
       const int ey = Y0 + cyo - b;
@@ -426,6 +455,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           T da[P];
 #pragma unroll
           for (int b = 1; b < P; ++b) da[b] = av[b] - av[0];
+          if constexpr (CF) {
           const T* tN = tyl + yty;
           const T* tD = tN + Q * P;
 #pragma unroll
@@ -443,6 +473,35 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             o[SBC] = dyv;
             o[2 * SBC] = dzv;
           }
+          } else {
+            // element matrices: row a (local y-slot) holds My av, Ky da
+            // (slot 0 minus the others), My bv
+            const T* tM = tyl + yty;
+            const T* tK = tM + P * P;
+            T ky[P];
+            ky[0] = T(0);
+#pragma unroll
+            for (int a = 1; a < P; ++a) {
+              T t = tK[(a - 1) * (P - 1)] * da[1];
+#pragma unroll
+              for (int b = 2; b < P; ++b) t = fma(tK[(a - 1) * (P - 1) + b - 1], da[b], t);
+              ky[a] = t;
+              ky[0] -= t;
+            }
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+              T c = tM[a * P] * av[0], dzv = tM[a * P] * bv[0];
+#pragma unroll
+              for (int b = 1; b < P; ++b) {
+                c = fma(tM[a * P + b], av[b], c);
+                dzv = fma(tM[a * P + b], bv[b], dzv);
+              }
+              T* o = sbb + rowstep(ysb, ypar, a);
+              o[0] = c;
+              o[SBC] = ky[a];
+              o[2 * SBC] = dzv;
+            }
+          }
         }
         if (xok) {
           const T* z0 = zc + (2 * gz) * NZW + xzc;
@@ -453,16 +512,45 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             av[b] = z0[b * TXH];
             bv[b] = z1[b * TXH];
           }
-          const T* tN = tyl + xty;
-          const T* tD = tN + Q * P;
-          T c = tN[0] * av[0], dzv = tN[0] * bv[0], dyv = tD[1] * (av[1] - av[0]);
+          T c, dzv, dyv;
+          if constexpr (CF) {
+            const T* tN = tyl + xty;
+            const T* tD = tN + Q * P;
+            c = tN[0] * av[0];
+            dzv = tN[0] * bv[0];
+            dyv = tD[1] * (av[1] - av[0]);
 #pragma unroll
-          for (int b = 1; b < P; ++b) {
-            c = fma(tN[b], av[b], c);
-            dzv = fma(tN[b], bv[b], dzv);
+            for (int b = 1; b < P; ++b) {
+              c = fma(tN[b], av[b], c);
+              dzv = fma(tN[b], bv[b], dzv);
+            }
+#pragma unroll
+            for (int b = 2; b < P; ++b) dyv = fma(tD[b], av[b] - av[0], dyv);
+          } else {
+            // local y-slot xa of the element (as in the full pass)
+            const T* tM = tyl + (xty - xa * P);
+            const T* tK = tM + P * P;
+            T da[P];
+#pragma unroll
+            for (int b = 1; b < P; ++b) da[b] = av[b] - av[0];
+            T kall = T(0), ka = T(0);
+#pragma unroll
+            for (int a = 1; a < P; ++a) {
+              T t = tK[(a - 1) * (P - 1)] * da[1];
+#pragma unroll
+              for (int b = 2; b < P; ++b) t = fma(tK[(a - 1) * (P - 1) + b - 1], da[b], t);
+              kall -= t;
+              if (a == xa) ka = t;
+            }
+            dyv = xa == 0 ? kall : ka;
+            c = tM[xa * P] * av[0];
+            dzv = tM[xa * P] * bv[0];
+#pragma unroll
+            for (int b = 1; b < P; ++b) {
+              c = fma(tM[xa * P + b], av[b], c);
+              dzv = fma(tM[xa * P + b], bv[b], dzv);
+            }
           }
-#pragma unroll
-          for (int b = 2; b < P; ++b) dyv = fma(tD[b], av[b] - av[0], dyv);
           T* o = sbb + xsb;
           o[0] = c;
           o[SBC] = dyv;
@@ -587,6 +675,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             dzw[a] = tw[(long long)Ez * Q * P + a];
           }
           T Ap = T(0), Bp = T(0);
+          if constexpr (CF) {
 #pragma unroll
           for (int b = 0; b < P; ++b) {
 #pragma unroll
@@ -595,6 +684,15 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               Ap = fma(bN[b][gy], e[0], Ap);
               Ap = fma(bD[b][gy], e[SBC], Ap);
               Bp = fma(bN[b][gy], e[2 * SBC], Bp);
+            }
+          }
+          } else {
+            // the column collects local slot b of y-element cyo + p - b
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+              const T* e = sbb + rowstep(brow0, bpar, (p - b) * Q + b);
+              Ap += e[0] + e[SBC];
+              Bp += e[2 * SBC];
             }
           }
 #pragma unroll
