@@ -651,13 +651,27 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             o0[0] = -s;
           }
           // coefficient c = ex collects slot a of element ex - a (lane j - a)
-          const T r0v = horner_shift<P, T>(o0);
-          const T r1v = horner_shift<P, T>(o1);
-          const T r2v = horner_shift<P, T>(o2);
-          if (j >= p) {
-            row[j - p] = r0v;
-            row[SBC + j - p] = r1v;
-            row[2 * SBC + j - p] = r2v;
+          if constexpr (CF) {
+            const T r0v = horner_shift<P, T>(o0);
+            const T r1v = horner_shift<P, T>(o1);
+            const T r2v = horner_shift<P, T>(o2);
+            if (j >= p) {
+              row[j - p] = r0v;
+              row[SBC + j - p] = r1v;
+              row[2 * SBC + j - p] = r2v;
+            }
+          } else {
+            // the x- and y-derivative channels share their z treatment and
+            // are summed by the backward stage: one sum, assembled once
+            T o01[P];
+#pragma unroll
+            for (int a = 0; a < P; ++a) o01[a] = o0[a] + o1[a];
+            const T r01 = horner_shift<P, T>(o01);
+            const T r2v = horner_shift<P, T>(o2);
+            if (j >= p) {
+              row[j - p] = r01;
+              row[2 * SBC + j - p] = r2v;
+            }
           }
         }
         // refill the ring slot of layer ez (its z stage is done in every
@@ -688,10 +702,11 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           }
           } else {
             // the column collects local slot b of y-element cyo + p - b
+            // (the x- and y-derivative channels already summed)
 #pragma unroll
             for (int b = 0; b < P; ++b) {
               const T* e = sbb + rowstep(brow0, bpar, (p - b) * Q + b);
-              Ap += e[0] + e[SBC];
+              Ap += e[0];
               Bp += e[2 * SBC];
             }
           }
