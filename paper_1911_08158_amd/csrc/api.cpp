@@ -255,8 +255,10 @@ void geometry(ads_sim* s) {
 void carve(ads_sim* s, Carver& c) {
   const long long nfr = s->nfree;
   const int P = s->P, q = s->q, p = s->p;
-  // per direction: N, D [E][q][P], W [E][q], then W*N, W*D [E][q][P]
-  for (int d = 0; d < 3; ++d) s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q);
+  // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P], then the
+  // element mass and stiffness matrices sum_g W N N^T, sum_g W D D^T [E][P][P]
+  for (int d = 0; d < 3; ++d)
+    s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q + (size_t)2 * s->E[d] * P * P);
   auto fac = [&](DevFactor& f, int d) {
     f.m = s->nf[d];
     f.L = c.dbl((size_t)f.m * p);
@@ -839,6 +841,17 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
     buf.insert(buf.end(), t.W.begin(), t.W.end());
     for (const std::vector<double>* v : {&t.N, &t.D})
       for (size_t k = 0; k < v->size(); ++k) buf.push_back(t.W[k / s->P] * (*v)[k]);
+    for (const std::vector<double>* v : {&t.N, &t.D})
+      for (int e = 0; e < s->E[d]; ++e)
+        for (int a = 0; a < s->P; ++a)
+          for (int b = 0; b < s->P; ++b) {
+            double m = 0.0;
+            for (int g = 0; g < s->q; ++g) {
+              const size_t r = ((size_t)e * s->q + g) * s->P;
+              m += t.W[(size_t)e * s->q + g] * (*v)[r + a] * (*v)[r + b];
+            }
+            buf.push_back(m);
+          }
     if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return st;
     if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return st;
     if (s->elastic) {

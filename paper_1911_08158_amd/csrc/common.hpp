@@ -123,7 +123,7 @@ struct RhsJob {
   int accumulate;         // 1: R += rscale * (amp * load - A(w)) instead of R =
   const double* coef;     // P-wave: c^2 at every Gauss point [Ez q][Ey q][Ex q], or null (c^2 = 1)
   double lam, mu;         // elasticity Lame constants
-  const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P]
+  const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P], M_e, K_e [E][P][P]
   int E[3], nf[3], off[3];
   int tiles[3];           // tiles along x, y, and z-chunks
   int TZ;                 // owned z-coefficients per chunk

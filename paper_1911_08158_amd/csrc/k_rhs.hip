@@ -404,6 +404,12 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
       // point (value, z-derivative)
       {
         T nz[Q][P], dz[Q][P];
+        // without a field: the layer's element matrices (after the tables:
+        // M_e, then K_e, [E][P][P]); the z-forward and z-backward
+        // contractions collapse to them, and the loop over z Gauss points
+        // below runs over the element's local z-slots instead
+        T mz[P][P], kz[P - 1][P - 1];
+        if constexpr (CF) {
 #pragma unroll
         for (int g = 0; g < Q; ++g)
 #pragma unroll
@@ -411,6 +417,17 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             nz[g][a] = (T)tzg[((long long)ez * Q + g) * P + a];
             dz[g][a] = (T)tzg[((long long)(Ez + ez) * Q + g) * P + a];
           }
+        } else {
+          const cmem<double>* tme = tzg + (4ll * Ez * Q * P + (long long)Ez * Q) + (long long)ez * P * P;
+          const cmem<double>* tke = tme + (long long)Ez * P * P;
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+              mz[a][b] = (T)tme[a * P + b];
+              if (a > 0 && b > 0) kz[a - 1][b - 1] = (T)tke[a * P + b];
+            }
+        }
         const T* rs[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) rs[a] = ring + ((ez + a) % P) * NC + wv * WE * TXH;
@@ -424,6 +441,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             T dr[P];
 #pragma unroll
             for (int a = 1; a < P; ++a) dr[a] = r[a] - r[0];
+            if constexpr (CF) {
 #pragma unroll
             for (int g = 0; g < Q; ++g) {
               T v = nz[g][0] * r[0], d = dz[g][1] * dr[1];
@@ -433,6 +451,28 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               for (int a = 2; a < P; ++a) d = fma(dz[g][a], dr[a], d);
               zc[(2 * g) * NZW + k] = v;
               zc[(2 * g + 1) * NZW + k] = d;
+            }
+            } else {
+              // element matrices of the layer: slot s holds Mz r and Kz r
+              // (Kz from the differences; slot 0 minus the others)
+              T kd[P];
+              kd[0] = T(0);
+#pragma unroll
+              for (int s2 = 1; s2 < P; ++s2) {
+                T d = kz[s2 - 1][0] * dr[1];
+#pragma unroll
+                for (int a = 2; a < P; ++a) d = fma(kz[s2 - 1][a - 1], dr[a], d);
+                kd[s2] = d;
+                kd[0] -= d;
+              }
+#pragma unroll
+              for (int s2 = 0; s2 < P; ++s2) {
+                T v = mz[s2][0] * r[0];
+#pragma unroll
+                for (int a = 1; a < P; ++a) v = fma(mz[s2][a], r[a], v);
+                zc[(2 * s2) * NZW + k] = v;
+                zc[(2 * s2 + 1) * NZW + k] = kd[s2];
+              }
             }
           }
         }
@@ -710,8 +750,15 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               Bp += e[2 * SBC];
             }
           }
+          if constexpr (CF) {
 #pragma unroll
-          for (int a = 0; a < P; ++a) acc[a] = fma(nzw[a], (double)Ap, fma(dzw[a], (double)Bp, acc[a]));
+            for (int a = 0; a < P; ++a) acc[a] = fma(nzw[a], (double)Ap, fma(dzw[a], (double)Bp, acc[a]));
+          } else {
+            // local z-slot gz of the layer's element: coefficient ez + gz
+            const double v = (double)Ap + (double)Bp;
+#pragma unroll
+            for (int a = 0; a < P; ++a) acc[a] += a == gz ? v : 0.0;
+          }
         }
         buf ^= 1;
       }
