@@ -528,6 +528,9 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               ky[a] = t;
               ky[0] -= t;
             }
+            // with z collapsed too, every channel ends in the same sum: the
+            // y- and z-derivative channels (both taken by the x-mass matrix)
+            // are added here, and the row holds two channels
 #pragma unroll
             for (int a = 0; a < P; ++a) {
               T c = tM[a * P] * av[0], dzv = tM[a * P] * bv[0];
@@ -538,8 +541,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               }
               T* o = sbb + rowstep(ysb, ypar, a);
               o[0] = c;
-              o[SBC] = ky[a];
-              o[2 * SBC] = dzv;
+              o[SBC] = ky[a] + dzv;
             }
           }
         }
@@ -593,8 +595,12 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           }
           T* o = sbb + xsb;
           o[0] = c;
-          o[SBC] = dyv;
-          o[2 * SBC] = dzv;
+          if constexpr (CF) {
+            o[SBC] = dyv;
+            o[2 * SBC] = dzv;
+          } else {
+            o[SBC] = dyv + dzv;
+          }
         }
         wave_sync();
         // (X) x-forward, x-weights, x-backward on this wave's rows; lanes
@@ -618,14 +624,15 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           for (int a = 0; a < P; ++a) {
             c0[a] = row[j + a];
             c1[a] = row[SBC + j + a];
-            c2[a] = row[2 * SBC + j + a];
+            if constexpr (CF) c2[a] = row[2 * SBC + j + a];
           }
           T d0[P];
 #pragma unroll
           for (int a = 1; a < P; ++a) d0[a] = c0[a] - c0[0];
           T o0[P], o1[P], o2[P];
           if constexpr (!CF) {
-            // element matrices (see Kx, Mx): o0 = Kx d0, o1 = Mx c1, o2 = Mx c2
+            // element matrices (see Kx, Mx): o0 = Kx d0, o1 = Mx c1 (c1: the
+            // y- and z-derivative channels summed by the y-stage)
 #pragma unroll
             for (int a = 1; a < P; ++a) {
               T s = Kx[a - 1][0] * d0[1];
@@ -635,14 +642,10 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             }
 #pragma unroll
             for (int a = 0; a < P; ++a) {
-              T s1 = Mx[a][0] * c1[0], s2 = Mx[a][0] * c2[0];
+              T s1 = Mx[a][0] * c1[0];
 #pragma unroll
-              for (int b = 1; b < P; ++b) {
-                s1 = fma(Mx[a][b], c1[b], s1);
-                s2 = fma(Mx[a][b], c2[b], s2);
-              }
+              for (int b = 1; b < P; ++b) s1 = fma(Mx[a][b], c1[b], s1);
               o1[a] = s1;
-              o2[a] = s2;
             }
           } else {
 #pragma unroll
@@ -701,17 +704,12 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               row[2 * SBC + j - p] = r2v;
             }
           } else {
-            // the x- and y-derivative channels share their z treatment and
-            // are summed by the backward stage: one sum, assembled once
+            // all channels end in one sum: assembled once, one value per row
             T o01[P];
 #pragma unroll
             for (int a = 0; a < P; ++a) o01[a] = o0[a] + o1[a];
             const T r01 = horner_shift<P, T>(o01);
-            const T r2v = horner_shift<P, T>(o2);
-            if (j >= p) {
-              row[j - p] = r01;
-              row[2 * SBC + j - p] = r2v;
-            }
+            if (j >= p) row[j - p] = r01;
           }
         }
         // refill the ring slot of layer ez (its z stage is done in every
@@ -742,13 +740,9 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           }
           } else {
             // the column collects local slot b of y-element cyo + p - b
-            // (the x- and y-derivative channels already summed)
+            // (all channels already summed)
 #pragma unroll
-            for (int b = 0; b < P; ++b) {
-              const T* e = sbb + rowstep(brow0, bpar, (p - b) * Q + b);
-              Ap += e[0];
-              Bp += e[2 * SBC];
-            }
+            for (int b = 0; b < P; ++b) Ap += sbb[rowstep(brow0, bpar, (p - b) * Q + b)];
           }
           if constexpr (CF) {
 #pragma unroll
