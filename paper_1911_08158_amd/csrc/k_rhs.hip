@@ -84,7 +84,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int P, int Q, int TY_, int NT_>
+template <typename T, int P, int Q, int TY_, int NT_, bool CF>
 struct RhsGeom {
   static constexpr int p = P - 1;
   static constexpr int G = 16;          // lanes per Gauss row (x-elements of the tile)
@@ -109,9 +109,12 @@ struct RhsGeom {
   static constexpr int H = HR + ((16 - HR % 32) + 32) % 32;
   static constexpr int SBC = 2 * H;     // one component plane
   static constexpr int TS = 2 * Q * P + (sizeof(T) == 4 ? (4 - (2 * Q * P) % 4) % 4 : 0);
-  // LDS: ring [P][NC], zc [NW][Q][2][NZW], sb [2][3][SBC], ty [EY][TS]
+  // channels of a Gauss row: three with a wave-speed field; two without
+  // (the collapsed form sums the y- and z-derivative channels)
+  static constexpr int NCH = CF ? 3 : 2;
+  // LDS: ring [P][NC], zc [NW][Q][2][NZW], sb [2][NCH][SBC], ty [EY][TS]
   static constexpr size_t lds_elems =
-      (size_t)P * NC + (size_t)NW * Q * 2 * NZW + 6ull * SBC + (size_t)EY * TS;
+      (size_t)P * NC + (size_t)NW * Q * 2 * NZW + 2ull * NCH * SBC + (size_t)EY * TS;
   static constexpr size_t lds_bytes = lds_elems * sizeof(T);
   static_assert(EY == WE * NW, "every wave owns WE y-elements");
   static_assert((WE * Q) % 4 == 0, "a wave's Gauss rows split over its four row groups");
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
-  using Gm = RhsGeom<T, P, Q, TY_, NT_>;
+  using Gm = RhsGeom<T, P, Q, TY_, NT_, CF>;
   constexpr int p = Gm::p, TX = Gm::TX, TY = Gm::TY, TXH = Gm::TXH, TYH = Gm::TYH, NC = Gm::NC, EY = Gm::EY,
                 NT = Gm::NT, NW = Gm::NW, WE = Gm::WE, NZW = Gm::NZW, NZ = Gm::NZ,
                 NF = Gm::NF, H = Gm::H, SBC = Gm::SBC, TS = Gm::TS;
@@ -136,8 +139,8 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* ring = reinterpret_cast<T*>(smem_raw);   // [P][NC]
   T* zcall = ring + P * NC;                    // [NW][Q][2][NZW]
-  T* sb = zcall + NW * Q * 2 * NZW;            // [2][3][SBC]
-  T* tyl = sb + 6 * SBC;                       // [EY][TS]: N[Q][P] then D[Q][P]
+  T* sb = zcall + NW * Q * 2 * NZW;            // [2][NCH][SBC]
+  T* tyl = sb + 2 * Gm::NCH * SBC;             // [EY][TS]: N[Q][P] then D[Q][P] (My, Ky without a field)
   auto rowpos = [](int r) { return (r & 1) * H + (r >> 1) * TXH; };
   // position of row r0 + k from that of row r0 (par = r0 & 1)
   auto rowstep = [](int pos0, int par, int k) {
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
       wave_sync();
 #pragma unroll 1
       for (int gz = 0; gz < Q; ++gz) {
-        T* sbb = sb + buf * 3 * SBC;
+        T* sbb = sb + buf * Gm::NCH * SBC;
         // (Y) y-contraction of this wave's y-elements: value, y-derivative,
         // z-derivative per y Gauss row
         {
@@ -790,7 +793,7 @@ int rhs_tile_y(int p, int mixed, int var) {
 // op 0: launch; op 1: *out = resident workgroups per CU (persistent grids)
 template <typename T, int P, int TY, int NT, bool CF>
 static hipError_t launch_one(const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
-  using Gm = RhsGeom<T, P, P, TY, NT>;
+  using Gm = RhsGeom<T, P, P, TY, NT, CF>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF>,
