@@ -216,16 +216,17 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
       // Without a field the y-forward and y-backward contractions of a
       // channel collapse as in x: per y-element the mass matrix
       // My = sum_g w_g N_g N_g^T, then the stiffness Ky = sum_g w_g D_g D_g^T
-      // (rows and columns 1..), formed in FP64 (zero outside the mesh).  Rows
-      // of the Gauss-row buffer then hold the local y-slots of an element.
-      constexpr int NM = P * P + (P - 1) * (P - 1);
+      // (columns 1.., acting on differences), formed in FP64 (zero outside
+      // the mesh).  Rows of the Gauss-row buffer then hold the local y-slots
+      // of an element.
+      constexpr int NM = P * P + P * (P - 1);
       static_assert(NM <= 2 * Q * P, "element matrices fit the table stride");
       for (int k = tid; k < EY * NM; k += NT) {
         const int eyl = k / NM, r = k - eyl * NM;
         const int ey = Y0 - p + eyl;
         const bool mass = r < P * P;
         const int rr = mass ? r : r - P * P;
-        const int a = mass ? rr / P : rr / (P - 1) + 1, b = mass ? rr % P : rr % (P - 1) + 1;
+        const int a = mass ? rr / P : rr / (P - 1), b = mass ? rr % P : rr % (P - 1) + 1;
         const long long tb = mass ? 0 : (long long)Ey * Q * P;
         double sm = 0.0;
         if (ey >= 0 && ey < Ey) {
@@ -283,13 +284,14 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
     // Without a wave-speed field nothing pointwise sits between the x-forward
     // and the x-backward contraction of a channel, so the pair is one 3x3
     // (PxP) element matrix: the x-stiffness Kx = sum_g w_g D_g D_g^T for the
-    // x-derivative channel (rows and columns 1.. only: its rows and columns
-    // sum to zero, as the derivative tables do) and the x-mass
-    // Mx = sum_g w_g N_g N_g^T for the other two; formed in FP64 per lane.
-    T Kx[P - 1][P - 1], Mx[P][P];
+    // x-derivative channel and the x-mass Mx = sum_g w_g N_g N_g^T for the
+    // others; formed in FP64 per lane.  Kx annihilates constants (the
+    // derivative tables sum to zero), so it acts on the differences
+    // d_b = c_b - c_0 and only its columns 1.. are kept: Kx[a][b-1].
+    T Kx[P][P - 1], Mx[P][P];
     if constexpr (!CF) {
       const gmem<double>* txg = gview(J.tab[0]);
-      double k[P - 1][P - 1] = {}, mm[P][P] = {};
+      double k[P][P - 1] = {}, mm[P][P] = {};
 #pragma unroll
       for (int g = 0; g < Q; ++g) {
         const double w = exv ? txg[2ll * Ex * Q * P + (long long)ex * Q + g] : 0.0;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
 #pragma unroll
           for (int b = 0; b < P; ++b) {
             mm[a][b] = fma(w * n[a], n[b], mm[a][b]);
-            if (a > 0 && b > 0) k[a - 1][b - 1] = fma(w * d[a], d[b], k[a - 1][b - 1]);
+            if (b > 0) k[a][b - 1] = fma(w * d[a], d[b], k[a][b - 1]);
           }
       }
 #pragma unroll
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
 #pragma unroll
         for (int b = 0; b < P; ++b) {
           Mx[a][b] = (T)mm[a][b];
-          if (a > 0 && b > 0) Kx[a - 1][b - 1] = (T)k[a - 1][b - 1];
+          if (b > 0) Kx[a][b - 1] = (T)k[a][b - 1];
         }
     }
     // backward x table entries at Gauss point gx
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
         // M_e, then K_e, [E][P][P]); the z-forward and z-backward
         // contractions collapse to them, and the loop over z Gauss points
         // below runs over the element's local z-slots instead
-        T mz[P][P], kz[P - 1][P - 1];
+        T mz[P][P], kz[P][P - 1];
         if constexpr (CF) {
 #pragma unroll
         for (int g = 0; g < Q; ++g)
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
 #pragma unroll
             for (int b = 0; b < P; ++b) {
               mz[a][b] = (T)tme[a * P + b];
-              if (a > 0 && b > 0) kz[a - 1][b - 1] = (T)tke[a * P + b];
+              if (b > 0) kz[a][b - 1] = (T)tke[a * P + b];
             }
         }
         const T* rs[P];
@@ -457,24 +459,16 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             }
             } else {
               // element matrices of the layer: slot s holds Mz r and Kz r
-              // (Kz from the differences; slot 0 minus the others)
-              T kd[P];
-              kd[0] = T(0);
-#pragma unroll
-              for (int s2 = 1; s2 < P; ++s2) {
-                T d = kz[s2 - 1][0] * dr[1];
-#pragma unroll
-                for (int a = 2; a < P; ++a) d = fma(kz[s2 - 1][a - 1], dr[a], d);
-                kd[s2] = d;
-                kd[0] -= d;
-              }
+              // (Kz annihilates constants: columns 1.. on the differences)
 #pragma unroll
               for (int s2 = 0; s2 < P; ++s2) {
-                T v = mz[s2][0] * r[0];
+                T v = mz[s2][0] * r[0], d = kz[s2][0] * dr[1];
 #pragma unroll
                 for (int a = 1; a < P; ++a) v = fma(mz[s2][a], r[a], v);
+#pragma unroll
+                for (int a = 2; a < P; ++a) d = fma(kz[s2][a - 1], dr[a], d);
                 zc[(2 * s2) * NZW + k] = v;
-                zc[(2 * s2 + 1) * NZW + k] = kd[s2];
+                zc[(2 * s2 + 1) * NZW + k] = d;
               }
             }
           }
@@ -517,34 +511,25 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             o[2 * SBC] = dzv;
           }
           } else {
-            // element matrices: row a (local y-slot) holds My av, Ky da
-            // (slot 0 minus the others), My bv
+            // element matrices: row a (local y-slot) holds My av and, with z
+            // collapsed too (every channel ends in the same sum), the y- and
+            // z-derivative channels that the x-mass matrix takes, added:
+            // Ky da + My bv
             const T* tM = tyl + yty;
             const T* tK = tM + P * P;
-            T ky[P];
-            ky[0] = T(0);
-#pragma unroll
-            for (int a = 1; a < P; ++a) {
-              T t = tK[(a - 1) * (P - 1)] * da[1];
-#pragma unroll
-              for (int b = 2; b < P; ++b) t = fma(tK[(a - 1) * (P - 1) + b - 1], da[b], t);
-              ky[a] = t;
-              ky[0] -= t;
-            }
-            // with z collapsed too, every channel ends in the same sum: the
-            // y- and z-derivative channels (both taken by the x-mass matrix)
-            // are added here, and the row holds two channels
 #pragma unroll
             for (int a = 0; a < P; ++a) {
-              T c = tM[a * P] * av[0], dzv = tM[a * P] * bv[0];
+              T c = tM[a * P] * av[0], d = tM[a * P] * bv[0];
 #pragma unroll
               for (int b = 1; b < P; ++b) {
                 c = fma(tM[a * P + b], av[b], c);
-                dzv = fma(tM[a * P + b], bv[b], dzv);
+                d = fma(tM[a * P + b], bv[b], d);
               }
+#pragma unroll
+              for (int b = 1; b < P; ++b) d = fma(tK[a * (P - 1) + b - 1], da[b], d);
               T* o = sbb + rowstep(ysb, ypar, a);
               o[0] = c;
-              o[SBC] = ky[a] + dzv;
+              o[SBC] = d;
             }
           }
         }
@@ -578,16 +563,6 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             T da[P];
 #pragma unroll
             for (int b = 1; b < P; ++b) da[b] = av[b] - av[0];
-            T kall = T(0), ka = T(0);
-#pragma unroll
-            for (int a = 1; a < P; ++a) {
-              T t = tK[(a - 1) * (P - 1)] * da[1];
-#pragma unroll
-              for (int b = 2; b < P; ++b) t = fma(tK[(a - 1) * (P - 1) + b - 1], da[b], t);
-              kall -= t;
-              if (a == xa) ka = t;
-            }
-            dyv = xa == 0 ? kall : ka;
             c = tM[xa * P] * av[0];
             dzv = tM[xa * P] * bv[0];
 #pragma unroll
@@ -595,6 +570,9 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
               c = fma(tM[xa * P + b], av[b], c);
               dzv = fma(tM[xa * P + b], bv[b], dzv);
             }
+#pragma unroll
+            for (int b = 1; b < P; ++b) dzv = fma(tK[xa * (P - 1) + b - 1], da[b], dzv);
+            dyv = T(0);
           }
           T* o = sbb + xsb;
           o[0] = c;
@@ -634,21 +612,16 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
           for (int a = 1; a < P; ++a) d0[a] = c0[a] - c0[0];
           T o0[P], o1[P], o2[P];
           if constexpr (!CF) {
-            // element matrices (see Kx, Mx): o0 = Kx d0, o1 = Mx c1 (c1: the
-            // y- and z-derivative channels summed by the y-stage)
-#pragma unroll
-            for (int a = 1; a < P; ++a) {
-              T s = Kx[a - 1][0] * d0[1];
-#pragma unroll
-              for (int b = 2; b < P; ++b) s = fma(Kx[a - 1][b - 1], d0[b], s);
-              o0[a] = s;
-            }
+            // element matrices (see Kx, Mx): o0 = Mx c1 + Kx d0 (c1: the y-
+            // and z-derivative channels summed by the y-stage), one chain
 #pragma unroll
             for (int a = 0; a < P; ++a) {
               T s1 = Mx[a][0] * c1[0];
 #pragma unroll
               for (int b = 1; b < P; ++b) s1 = fma(Mx[a][b], c1[b], s1);
-              o1[a] = s1;
+#pragma unroll
+              for (int b = 1; b < P; ++b) s1 = fma(Kx[a][b - 1], d0[b], s1);
+              o0[a] = s1;
             }
           } else {
 #pragma unroll
@@ -689,15 +662,15 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             }
           }
           }
-          // backward derivative tables sum to zero: slot 0 from the others
-          {
-            T s = o0[1];
-#pragma unroll
-            for (int a = 2; a < P; ++a) s += o0[a];
-            o0[0] = -s;
-          }
           // coefficient c = ex collects slot a of element ex - a (lane j - a)
           if constexpr (CF) {
+            // backward derivative tables sum to zero: slot 0 from the others
+            {
+              T s = o0[1];
+#pragma unroll
+              for (int a = 2; a < P; ++a) s += o0[a];
+              o0[0] = -s;
+            }
             const T r0v = horner_shift<P, T>(o0);
             const T r1v = horner_shift<P, T>(o1);
             const T r2v = horner_shift<P, T>(o2);
@@ -708,10 +681,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1)
             }
           } else {
             // all channels end in one sum: assembled once, one value per row
-            T o01[P];
-#pragma unroll
-            for (int a = 0; a < P; ++a) o01[a] = o0[a] + o1[a];
-            const T r01 = horner_shift<P, T>(o01);
+            const T r01 = horner_shift<P, T>(o0);
             if (j >= p) row[j - p] = r01;
           }
         }
