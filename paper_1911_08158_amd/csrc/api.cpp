@@ -1276,10 +1276,10 @@ struct ads_pool {
   hipGraphExec_t exec = nullptr;
   std::vector<hipEvent_t> ev;
   int nev = 0;
-  // right-hand-side tile variant per [p-2][mixed]: p=2 FP32 uses the 26-row
-  // tiles (fewer redundant y-elements on 128-wide meshes; measured faster in
-  // batches), the rest the 14/13-row ones
-  int var[2][2] = {{0, 1}, {0, 0}};
+  // right-hand-side tile variant per [p-2][mixed]: the 14/13-row tiles (for
+  // FP32 p=2 four-wave workgroups at five waves per SIMD, measured faster in
+  // batches than the 26-row tiles at 3.5)
+  int var[2][2] = {{0, 0}, {0, 0}};
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;

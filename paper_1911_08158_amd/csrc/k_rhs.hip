@@ -123,11 +123,12 @@ struct RhsGeom {
   static_assert(lds_bytes <= 160 * 1024, "LDS budget of one workgroup");
 };
 
-// FP32 p = 2: at least four waves per SIMD (three with a field).  CF: the jobs
-// carry a wave-speed field (a separate instantiation, so that the constant
-// coefficient kernels keep their registers).
+// FP32 p = 2: at least four waves per SIMD (three with a field; five for
+// the four-wave workgroups without one, whose LDS allows five per CU).  CF:
+// the jobs carry a wave-speed field (a separate instantiation, so that the
+// constant coefficient kernels keep their registers).
 template <typename T, int P, int Q, int TY_, int NT_, bool CF>
-__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : 4) : 1) void rhs_pwave_kernel(
+__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ == 256 ? 5 : 4)) : 1) void rhs_pwave_kernel(
     const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
