@@ -27,10 +27,20 @@
 //   * a z-layer is written once its last contributing element is done.
 // With a wave-speed field (c^2 at the Gauss points) the three point
 // gradients are scaled by it between the x-forward and x-backward stages.
+// Without one (CF false) nothing pointwise separates a channel's forward and
+// backward contraction in any direction, and each pair collapses to an
+// element matrix, M_d = sum_g w_g N_g N_g^T or K_d = sum_g w_g D_g D_g^T:
+// the element's contribution is (K_x(x)M_y(x)M_z + M_x(x)K_y(x)M_z +
+// M_x(x)M_y(x)K_z) w_e, the same sum up to rounding (q = p+1 is exact).
+// The stages keep their places: (Z) M_z r and K_z r per column, the loop
+// over z Gauss points runs over the element's local z-slots; (Y) M_y of the
+// z-value channel and K_y of it plus M_y of the z-derivative channel,
+// summed (both meet M_x next); (X) K_x and M_x in one chain, one assembled
+// value per row; (B) plain sums into the FP64 accumulators.
 // Derivative tables satisfy sum_a D_a = 0 on every element (partition of
 // unity), so the forward derivative contractions use differences against
 // the first coefficient and the backward x-derivative slot 0 is minus the
-// sum of the others.
+// sum of the others; likewise the stiffness matrices act on differences.
 // T is the contraction type: double (FP64 mode) or float (mixed mode: FP32
 // contractions, FP64 predictor, FP64 z-accumulation and assembly).
 #include "common.hpp"
@@ -681,9 +691,12 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ ==
               row[2 * SBC + j - p] = r2v;
             }
           } else {
-            // all channels end in one sum: assembled once, one value per row
+            // all channels end in one sum: assembled once, one value per row.
+            // Lanes j < p own no coefficient: they write to the spare columns
+            // TX + p + j of the row, which nothing reads afterwards, so that
+            // the rows of a slot form one block the scheduler can interleave
             const T r01 = horner_shift<P, T>(o0);
-            if (j >= p) row[j - p] = r01;
+            row[j >= p ? j - p : TX + p + j] = r01;
           }
         }
         // refill the ring slot of layer ez (its z stage is done in every
