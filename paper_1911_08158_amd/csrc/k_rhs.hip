@@ -138,7 +138,7 @@ struct RhsGeom {
 // the jobs carry a wave-speed field (a separate instantiation, so that the
 // constant coefficient kernels keep their registers).
 template <typename T, int P, int Q, int TY_, int NT_, bool CF>
-__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ == 256 ? 5 : 4)) : 1) void rhs_pwave_kernel(
+__global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <= 256 ? 5 : 4)) : 1) void rhs_pwave_kernel(
     const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ ==
 struct RhsVariant {
   int TY, NT;
 };
-static const RhsVariant kVarP2F[] = {{14, 256}, {26, 448}, {46, 768}};
+static const RhsVariant kVarP2F[] = {{14, 256}, {26, 448}, {10, 192}};
 static const RhsVariant kVarP2D[] = {{14, 256}, {30, 512}, {22, 384}};
 static const RhsVariant kVarP3F[] = {{13, 256}, {29, 512}, {21, 384}};
 static const RhsVariant kVarP3D[] = {{13, 256}, {21, 384}, {9, 192}};
@@ -798,7 +798,7 @@ static hipError_t launch_f(int p, int var, const LaunchHdr* d_hdr, int grid, hip
     switch (var) {
       case 0: return launch_one<float, 3, 14, 256, CF>(d_hdr, grid, s, op, out);
       case 1: return launch_one<float, 3, 26, 448, CF>(d_hdr, grid, s, op, out);
-      default: return launch_one<float, 3, 46, 768, CF>(d_hdr, grid, s, op, out);
+      default: return launch_one<float, 3, 10, 192, CF>(d_hdr, grid, s, op, out);
     }
   }
   switch (var) {
