@@ -256,9 +256,11 @@ void carve(ads_sim* s, Carver& c) {
   const long long nfr = s->nfree;
   const int P = s->P, q = s->q, p = s->p;
   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P], then the
-  // element mass and stiffness matrices sum_g W N N^T, sum_g W D D^T [E][P][P]
+  // element mass and stiffness matrices sum_g W N N^T, sum_g W D D^T [E][P][P],
+  // then the assembled matrices M, K of the free coefficients [nf][2p+1]
   for (int d = 0; d < 3; ++d)
-    s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q + (size_t)2 * s->E[d] * P * P);
+    s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q + (size_t)2 * s->E[d] * P * P +
+                        (size_t)2 * s->nf[d] * (2 * p + 1));
   auto fac = [&](DevFactor& f, int d) {
     f.m = s->nf[d];
     f.L = c.dbl((size_t)f.m * p);
@@ -434,7 +436,9 @@ void set_kron_zchunks(KronJob& K, int k) {
 
 // Tiling of one right-hand-side job.  resident > 0: z-chunks chosen for that
 // many resident workgroups; otherwise enough tiles to cover the chip twice.
-void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident = 0) {
+// halo: source layers a tile reads beyond its outputs (p, or 2p for the
+// Kronecker form).
+void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident = 0, int halo = -1) {
   J.tiles[0] = (s->nf[0] + TX - 1) / TX;
   J.tiles[1] = (s->nf[1] + TY - 1) / TY;
   const int xy = J.tiles[0] * J.tiles[1];
@@ -446,13 +450,17 @@ void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident =
     return;
   }
   if (resident > 0) {
-    set_zchunks(J, s->nf[2], best_zchunks({{xy, s->nf[2]}}, s->p, resident));
+    set_zchunks(J, s->nf[2], best_zchunks({{xy, s->nf[2]}}, halo < 0 ? s->p : halo, resident));
     return;
   }
   const int want = std::max(1, (1024 + xy - 1) / xy);
   const int chunks = std::min(want, std::max(1, s->nf[2] / 8));
   set_zchunks(J, s->nf[2], chunks);
 }
+
+// Variant actually run: the Kronecker form (3) has no wave-speed field, so
+// jobs with one take the quadrature kernel's variant 0 instead.
+int rhs_form_var(int var, bool coef) { return (coef && var == 3) ? 0 : var; }
 
 RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift, int mixed, int var) {
   RhsJob J{};
@@ -471,8 +479,10 @@ RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_
   J.rscale = 1.0;
   J.coef = s->coef;
   fill_tables(s, J);
-  rhs_tiles(s, J, rhs_tile_x(s->p), rhs_tile_y(s->p, mixed, var),
-            (long long)rhs_blocks_per_cu(s->p, mixed, var, s->coef != nullptr) * s->ncu);
+  var = rhs_form_var(var, s->coef != nullptr);
+  rhs_tiles(s, J, rhs_tile_x(s->p, var), rhs_tile_y(s->p, mixed, var),
+            (long long)rhs_blocks_per_cu(s->p, mixed, var, s->coef != nullptr) * s->ncu,
+            var == 3 ? 2 * s->p : s->p);
   return J;
 }
 
@@ -674,7 +684,8 @@ ads_status build_launches(ads_sim* s) {
       d = s->arena.add(std::vector<RhsJob>{pj}, err);
       if (!d) return fail(ADS_ENOMEM, err);
       s->step_l.push_back(
-          Launch{Launch::RHS_P, d, 1, pj.ntiles, 0, s->p, -1, s->rhs_var, s->mixed ? 1 : 0, as_bytes(pj)});
+          Launch{Launch::RHS_P, d, 1, pj.ntiles, 0, s->p, -1, rhs_form_var(s->rhs_var, s->coef != nullptr),
+                 s->mixed ? 1 : 0, as_bytes(pj)});
       s->step_l.back().coef = s->coef != nullptr;
     }
     SweepJob z{};
@@ -820,7 +831,7 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   geometry(s);
   s->ncu = ncu;
   if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
-  if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(2, std::atoi(e)));
+  if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(3, std::atoi(e)));
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
   Carver c{(char*)ws};
   carve(s, c);
@@ -852,6 +863,8 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
             }
             buf.push_back(m);
           }
+    buf.insert(buf.end(), s->Mf[d].a.begin(), s->Mf[d].a.end());
+    buf.insert(buf.end(), s->Kf[d].a.begin(), s->Kf[d].a.end());
     if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return st;
     if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return st;
     if (s->elastic) {
@@ -1088,7 +1101,7 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   static std::map<std::string, int> cache;
   const std::string key = std::to_string(s->p) + "/" + std::to_string(s->mixed) + "/" + std::to_string(s->nf[0]) +
                           "x" + std::to_string(s->nf[1]) + "x" + std::to_string(s->nf[2]);
-  const int nv = rhs_num_variants(s->p);
+  const int nv = rhs_num_variants(s->p, s->coef != nullptr);
   int best = -1;
   auto it = cache.find(key);
   if (it != cache.end()) {
@@ -1309,7 +1322,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   for (int p = 2; p <= 3; ++p)
     for (int mixed = 0; mixed <= 1; ++mixed)
       for (int coef = 0; coef <= 1; ++coef) {
-        int var = P->var[p - 2][mixed];
+        int var = rhs_form_var(P->var[p - 2][mixed], coef != 0);
         add(Launch::RHS_P, p, mixed, var, coef, 0, rhs_blocks_per_cu(p, mixed, var, coef) * ncu, sizeof(RhsJob));
       }
   for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
@@ -1349,7 +1362,7 @@ ads_status pool_rebuild(ads_pool* P) {
         const RhsJob* r = (const RhsJob*)j.data();
         xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nf[2]});
       }
-      const int k = best_zchunks(xy_nfz, L.p, L.grid);
+      const int k = best_zchunks(xy_nfz, L.var == 3 ? 2 * L.p : L.p, L.grid);
       for (auto& j : sel) {
         RhsJob* r = (RhsJob*)j.data();
         set_zchunks(*r, r->nf[2], k);
@@ -1471,7 +1484,7 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
   P->use_graph = use_graph != 0;
   P->slots.resize(max_slots);
   if (const char* e = std::getenv("ADS_POOL_RHS_VAR")) {
-    int v = std::max(0, std::min(2, std::atoi(e)));
+    int v = std::max(0, std::min(3, std::atoi(e)));
     for (auto& r : P->var) r[0] = r[1] = v;
   }
   P->ncu = ncu;

@@ -44,6 +44,7 @@
 // T is the contraction type: double (FP64 mode) or float (mixed mode: FP32
 // contractions, FP64 predictor, FP64 z-accumulation and assembly).
 #include "common.hpp"
+#include "launch.hpp"
 
 namespace ads {
 
@@ -766,9 +767,12 @@ static const RhsVariant kVarP2D[] = {{14, 256}, {30, 512}, {22, 384}};
 static const RhsVariant kVarP3F[] = {{13, 256}, {29, 512}, {21, 384}};
 static const RhsVariant kVarP3D[] = {{13, 256}, {21, 384}, {9, 192}};
 
-int rhs_num_variants(int) { return 3; }
-int rhs_tile_x(int p) { return 16 - p; }
+// variant 3: the Kronecker (assembled band) form of k_rhs_band.hip, for
+// jobs without a wave-speed field
+int rhs_num_variants(int, int coef) { return coef ? 3 : 4; }
+int rhs_tile_x(int p, int var) { return var == 3 ? rhs_band_tile_x() : 16 - p; }
 int rhs_tile_y(int p, int mixed, int var) {
+  if (var == 3) return rhs_band_tile_y();
   if (var < 0 || var > 2) var = 0;
   if (p == 2) return mixed ? kVarP2F[var].TY : kVarP2D[var].TY;
   return mixed ? kVarP3F[var].TY : kVarP3D[var].TY;
@@ -833,13 +837,16 @@ static hipError_t dispatch(int p, int mixed, int var, int coef, const LaunchHdr*
 hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (p != 2 && p != 3) return hipErrorInvalidValue;
+  if (var == 3) return coef ? hipErrorInvalidValue : launch_rhs_band(p, mixed, d_hdr, grid, s);
   if (var < 0 || var > 2) var = 0;
   return dispatch(p, mixed, var, coef, d_hdr, grid, s, 0, nullptr);
 }
 
 int rhs_blocks_per_cu(int p, int mixed, int var, int coef) {
+  if (var == 3 && !coef) return rhs_band_blocks_per_cu(p, mixed);
+  if (var < 0 || var > 2) var = 0;
   int n = 1;
-  dispatch(p, mixed, var, coef, nullptr, 0, nullptr, 1, &n);
+  (void)dispatch(p, mixed, var, coef, nullptr, 0, nullptr, 1, &n);
   return n < 1 ? 1 : n;
 }
 

@@ -21,12 +21,19 @@ bool plane_fits(int nx, int ny, int p);
 int plane_blocks_per_cu(size_t lds_bytes);
 hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, hipStream_t s);
 
-int rhs_num_variants(int p);
-int rhs_tile_x(int p);
+// P-wave right-hand side: variants 0-2 are tile shapes of the quadrature
+// kernel; variant 3 is the Kronecker (assembled band) form, for jobs
+// without a wave-speed field only.  coef: the jobs carry a wave-speed
+// field (RhsJob::coef).
+int rhs_num_variants(int p, int coef);
+int rhs_tile_x(int p, int var);
 int rhs_tile_y(int p, int mixed, int var);
 int rhs_blocks_per_cu(int p, int mixed, int var, int coef);
-// coef: the jobs carry a wave-speed field (RhsJob::coef)
 hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s);
+int rhs_band_tile_x();
+int rhs_band_tile_y();
+int rhs_band_blocks_per_cu(int p, int mixed);
+hipError_t launch_rhs_band(int p, int mixed, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int rhs_el_tile_x(int p);
 int rhs_el_tile_y(int p);
 hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s);

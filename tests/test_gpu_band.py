@@ -1,0 +1,182 @@
+"""GPU parity of the Kronecker form of the P-wave right-hand side (tile
+variant 3: assembled 1D band matrices, K = K_x(x)M_y(x)M_z + M_x(x)K_y(x)M_z
++ M_x(x)M_y(x)K_z) against the CPU oracle, through the C-ABI.  Bars as for
+the quadrature kernel: relative L2 <= 1e-12 in FP64 mode, <= 1e-6 with FP32
+band passes (mixed).  The form is rounding-different from the quadrature,
+so it is held to the oracle, not bitwise to the other variants."""
+import numpy as np
+import pytest
+
+import workloads as W
+from runners import gpu_sim, oracle_pwave, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture
+def band(monkeypatch):
+    monkeypatch.setenv("ADS_RHS_VAR", "3")
+    yield
+    monkeypatch.delenv("ADS_RHS_VAR")
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C1.with_(steps=5),
+    W.C1.with_(nelem=(37, 41, 35), steps=4, init="noise"),      # 32 x 8 tiles with ragged tails
+    W.C1.with_(nelem=(70, 9, 40), steps=3, init="noise"),       # several x-tiles, z-chunks
+    W.C1.with_(nelem=(29, 17, 23), p=3, q=4, tau=0.02, steps=4),
+    W.C1.with_(nelem=(1, 2, 1), steps=3, init="noise"),         # one free coefficient per line
+    W.C1.with_(nelem=(3, 1, 4), p=3, q=4, steps=3, init="noise"),
+    W.C1.with_(nelem=(9, 7, 11), steps=4, bc="natural"),        # no elimination
+    W.C1.with_(nelem=(6, 13, 5), p=3, q=4, steps=3, tau=0.02, bc="natural"),
+    W.C1.with_(nelem=(2, 3, 2), steps=3, init="noise", bc="natural"),
+    W.C1.with_(tau=50.0, steps=4),                               # stiff: tau^2 lambda >> 1
+], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
+def test_band_form_matches_oracle(cfg, band):
+    _cuda()
+    pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0_ref))
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, a = sim.get_state()
+        errs = [rel_l2(x.cpu().numpy(), pw.to_full(r)) for x, r in zip((u, v, a), hist[k])]
+        assert max(errs) <= TOL, (k, errs)
+        if cfg.bc == "dirichlet":
+            un = u.cpu().numpy()
+            assert np.all(un[0] == 0) and np.all(un[-1] == 0) and np.all(un[:, 0] == 0) and np.all(un[:, :, -1] == 0)
+    sim.close()
+
+
+def test_band_form_point_source(band):
+    """p = 3 with the Ricker point source (load vector and amplitude table),
+    z-chunks of a ragged mesh."""
+    _cuda()
+    cfg = W.C2.with_(nelem=(14, 12, 17), steps=30)
+    pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0_ref))
+    sim.factor()
+    done = 0
+    for k in (1, 10, 30):
+        sim.step(k - done)
+        done = k
+        errs = [rel_l2(x.cpu().numpy(), pw.to_full(r)) for x, r in zip(sim.get_state(), hist[k])]
+        assert max(errs) <= TOL, (k, errs)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+@pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
+                                 W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
+                         ids=["p2", "p3"])
+def test_band_form_mixed(cfg, precision, band):
+    _cuda()
+    pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0))
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, _, _ = sim.get_state()
+        e = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
+        assert e <= 1e-6, (k, e)
+    sim.close()
+
+
+def test_band_form_c3_fp64_and_mixed(band):
+    """C3 size (128^3, p = 2): 10 FP64 steps compared in full; the FP32 band
+    passes within 1e-6 after the same steps."""
+    _cuda()
+    cfg = W.C3.with_(precision="fp64")
+    n = 10
+    pw, u0_ref, (u_ref, v_ref, a_ref) = oracle_pwave(cfg, n)
+    for precision, tol in (("fp64", TOL), ("mixed_fp32", 1e-6)):
+        sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0_ref))
+        sim.factor()
+        sim.step(n)
+        u, v, a = sim.get_state()
+        errs = (rel_l2(u.cpu().numpy(), pw.to_full(u_ref)), rel_l2(v.cpu().numpy(), pw.to_full(v_ref)),
+                rel_l2(a.cpu().numpy(), pw.to_full(a_ref)))
+        print(f"C3 band {precision} step {n}: rel L2 u {errs[0]:.2e} v {errs[1]:.2e} a {errs[2]:.2e}", flush=True)
+        assert (max(errs) if precision == "fp64" else errs[0]) <= tol, errs
+        sim.close()
+
+
+def test_band_form_z_chunks_bitwise(band, monkeypatch):
+    """Every output is computed by one thread with the same operation order
+    whatever the z-chunking, so results are bitwise identical."""
+    _cuda()
+    cfg = W.C1.with_(nelem=(37, 20, 33), steps=3, init="noise")
+    pw, u0, _ = oracle_pwave(cfg, 0)
+    outs = []
+    for tz in (0, 1, 5, 40):
+        monkeypatch.setenv("ADS_RHS_TZ", str(tz))
+        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+        sim.factor()
+        sim.step(cfg.steps)
+        outs.append([t.cpu().numpy() for t in sim.get_state()])
+        sim.close()
+    monkeypatch.delenv("ADS_RHS_TZ")
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+
+
+def test_band_form_with_field_takes_quadrature(band):
+    """A wave-speed field has no Kronecker form: with variant 3 asked for,
+    such a simulation runs the quadrature kernel (variant 0), bitwise."""
+    _cuda()
+    import os
+    import torch
+    from runners import oracle_bc
+    from oracle import pwave
+    cfg = W.C1.with_(nelem=(9, 7, 8), tau=0.02, steps=3)
+    base = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
+    xs = [base.quad_points(d) for d in range(3)]
+    c2 = W.wave_speed_field(*xs)
+    u0 = base.project(W.initial_values(cfg, *xs))
+    outs = []
+    for var in ("3", "0"):
+        os.environ["ADS_RHS_VAR"] = var
+        sim, _ = gpu_sim(cfg, u0_full=base.to_full(u0))
+        sim.set_coefficient(torch.from_numpy(c2).cuda(), 1.5)
+        sim.factor()
+        sim.step(cfg.steps)
+        outs.append([t.cpu().numpy() for t in sim.get_state()])
+        sim.close()
+    os.environ["ADS_RHS_VAR"] = "3"
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
+def test_band_form_pooled(monkeypatch):
+    """Pooled simulations on the Kronecker form (FP64 and mixed, two
+    degrees, one batch) against the oracle."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool
+    monkeypatch.setenv("ADS_POOL_RHS_VAR", "3")
+    cfgs = [W.C1.with_(nelem=(18, 20, 16), tau=0.01, steps=10),
+            W.C1.with_(nelem=(11, 9, 13), p=3, q=4, tau=0.01, steps=10)]
+    refs = [oracle_pwave(c, c.steps) for c in cfgs]
+    pool = Pool(256 << 20, max_slots=4)
+    sims = []
+    for c, (pw, u0, _) in zip(cfgs, refs):
+        for prec in ("fp64", "mixed_fp32"):
+            s = pool.admit(c, precision=prec)
+            s.set_state(torch.from_numpy(pw.to_full(u0)).cuda(), None, None, 0)
+            s.factor()
+            pool.activate(s)
+            sims.append((s, pw, prec))
+    pool.step(cfgs[0].steps)
+    for i, (s, pw, prec) in enumerate(sims):
+        ur = refs[i // 2][2][0]
+        e = rel_l2(s.get_state()[0].cpu().numpy(), pw.to_full(ur))
+        assert e <= (1e-12 if prec == "fp64" else 1e-6), (i, prec, e)
+    pool.close()
