@@ -46,24 +46,27 @@ def rhs_flops_per_element(p, q=None):
 SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_xy": 16,   # per free DOF; x and y in one in-plane launch: 16
                "sweep_z": 56}                                 # z fused with the Newmark update
 
-# HBM traffic of one batched right-hand-side launch (4 simulations), from
+RHS_BYTES = 32   # per free DOF: reads u, u', u'', writes R
+
+# HBM traffic per launch of the batched step's kernels (4 simulations), from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same counters
-# read for a 512 MiB device copy (profiles/rhs_pwave128_p2_batch4_hbm_traffic.md).
-# Valid only for the kernel source it was measured on: reported as null
-# once the right-hand-side sources hash differently.
-RHS_TRAFFIC = {
-    "sources": ["paper_1911_08158_amd/csrc/k_rhs.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-    "sha256": "d1ad994c148f93f8811373f4fd1d907f56921927107695c7f793a7dbc809fdb0",
-    "fetch_kib": 299267.9, "fetch_scale": 2.0,
-    "write_kib": 94976.0, "write_scale": 1.0,
+# read for a 512 MiB device copy (profiles/pwave128_p2_batch4_hbm_traffic.md).
+# Each record is valid only for the kernel source it was measured on: a
+# launch's traffic is reported as null once its sources hash differently.
+TRAFFIC = {
+    "rhs": {"sources": ["paper_1911_08158_amd/csrc/k_rhs_band.hip", "paper_1911_08158_amd/csrc/common.hpp"],
+            "sha256": "0", "fetch_kib": 0.0, "write_kib": 0.0},
+    "sweep_z": {"sources": ["paper_1911_08158_amd/csrc/k_sweep.hip", "paper_1911_08158_amd/csrc/common.hpp"],
+                "sha256": "0", "fetch_kib": 0.0, "write_kib": 0.0},
+    "fetch_scale": 2.0, "write_scale": 1.0,
     "batch": 4,
 }
 
 
-def rhs_traffic(batch):
+def kernel_traffic(kind, batch):
     import hashlib
-    t = RHS_TRAFFIC
-    if batch != t["batch"]:
+    t = TRAFFIC.get(kind)
+    if t is None or batch != TRAFFIC["batch"]:
         return None
     h = hashlib.sha256()
     for f in t["sources"]:
@@ -71,7 +74,39 @@ def rhs_traffic(batch):
             h.update(fh.read())
     if h.hexdigest() != t["sha256"]:
         return None
-    return int(round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024))
+    return int(round((t["fetch_kib"] * TRAFFIC["fetch_scale"] + t["write_kib"] * TRAFFIC["write_scale"]) * 1024))
+
+
+KERNEL_NAMES = {
+    "rhs": "rhs_band_kernel (Kronecker form of the right-hand side)",
+    "sweep_xy": "sweep_plane_kernel (x- and y-sweeps of a z-plane in LDS)",
+    "sweep_z": "sweep_kernel (z-sweep fused with the Newmark update)",
+}
+
+
+def roofline_entry(k, cfg, batch, band, fp32):
+    """Roofline of one launch kind: HBM for the sweeps and the Kronecker-form
+    right-hand side (algorithmic bytes), FP32 / FP64 ALU for the quadrature
+    right-hand side (nominal flops)."""
+    nfree = int(np.prod([n - 2 for n in cfg.n])) * batch
+    if k["kernel"] == "rhs" and not band:
+        peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+        return {"bound": "alu", "achieved": k["tflops"], "peak": peak, "unit": "TFLOP/s",
+                "frac": round(k["tflops"] / peak, 4), "traffic": None,
+                "kernel": "rhs_pwave_kernel (sum-factorized quadrature)",
+                "per_launch": f"{rhs_flops_per_element(cfg.p)} flops/element x {int(np.prod(cfg.nelem))} elements "
+                              f"x {batch} simulations"}
+    per = RHS_BYTES if k["kernel"] == "rhs" else SWEEP_BYTES[k["kernel"]]
+    e = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(k["gbs"] / HBM_PEAK_GBS, 4), "traffic": kernel_traffic(k["kernel"], batch),
+         "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
+         "kernel": KERNEL_NAMES.get(k["kernel"], k["kernel"]),
+         "per_launch": f"{per} B per free DOF x {nfree} free DOFs ({batch} simulations)"}
+    if k["kernel"] == "rhs":
+        e["nominal_tflops"] = k["tflops"]
+        e["note"] = ("7(2p+1) = 35 multiply-adds per coefficient at p = 2; the nominal sum-factorized quadrature "
+                     f"({rhs_flops_per_element(cfg.p)} flops per element) would be {k['tflops']} TFLOP/s")
+    return e
 
 
 def workspace_bytes_of(cfg):
@@ -108,7 +143,9 @@ def kernel_table(entries, cfg, batch, mixed_peak=False):
         e = {"kernel": k, "ms": round(float(m), 5)}
         if k == "rhs":
             fl = rhs_flops_per_element(cfg.p) * nel
-            e.update(algorithmic_flops=fl, tflops=round(fl / (m * 1e-3) / 1e12, 3))
+            by = RHS_BYTES * nfree
+            e.update(algorithmic_flops=fl, tflops=round(fl / (m * 1e-3) / 1e12, 3),
+                     algorithmic_bytes=by, gbs=round(by / (m * 1e-3) / 1e9, 1))
         elif k in SWEEP_BYTES:
             by = SWEEP_BYTES[k] * nfree
             e.update(algorithmic_bytes=by, gbs=round(by / (m * 1e-3) / 1e9, 1))
@@ -420,17 +457,14 @@ def main():
         return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
-    rhs = next(k for k in batched["kernels"] if k["kernel"] == "rhs")
-    roof = {"bound": "alu", "achieved": rhs["tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(rhs["tflops"] / FP32_PEAK_TFLOPS, 4), "traffic": rhs_traffic(args.batch),
-            "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
-            "kernel": "rhs_pwave_kernel<float,3,3,..> (FP32 contractions, batched)",
-            "per_launch": f"{rhs_flops_per_element(cfg.p)} flops/element x {int(np.prod(cfg.nelem))} elements "
-                          f"x {args.batch} simulations",
-            "note": "algorithmic flops = the nominal tile-shared sum factorization (765 FMAs per element at p=2); "
-                    "without a wave-speed field the kernel applies the collapsed element matrices, 222 FMAs per "
-                    "element"}
+    # the Kronecker form (variant 3) runs in the pool unless ADS_POOL_RHS_VAR asks otherwise
+    band_b = os.environ.get("ADS_POOL_RHS_VAR", "3") == "3"
+    dom = max(batched["kernels"], key=lambda k: k["ms"])
+    roof = roofline_entry(dom, cfg, args.batch, band_b, True)
+    roof["dominant"] = f"{dom['kernel']}: the longest launch of the batched step"
+    rhs_b = next(k for k in batched["kernels"] if k["kernel"] == "rhs")
     rhs64 = next(k for k in plain["kernels"] if k["kernel"] == "rhs")
+    band_p = plain["rhs_variant"] == 3
     out = {
         "metric": METRIC,
         "value": batched["dof_steps_per_s"],
@@ -442,7 +476,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (right-hand-side contractions) + f64 (predictor, assembly, factors, sweeps, update)",
+        "dtype": "f32 (right-hand-side x- and y-band passes) + f64 (predictor, z-accumulation, factors, sweeps, update)",
         "data": "synthetic",
         "config": {"workload": f"{args.batch} x P-wave 128^3 elements p=2 (130^3 DOFs each) tau=2e-3, "
                                "batched in one pool, mixed-precision right-hand side, graph replay",
@@ -453,8 +487,8 @@ def main():
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": batched["dof_steps_per_s"] / plain["dof_steps_per_s"],
         "roofline": roof,
-        "roofline_plain_fp64_rhs": {"bound": "alu", "achieved": rhs64["tflops"], "peak": FP64_PEAK_TFLOPS,
-                                    "unit": "TFLOP/s", "frac": round(rhs64["tflops"] / FP64_PEAK_TFLOPS, 4)},
+        "roofline_batched_rhs": roofline_entry(rhs_b, cfg, args.batch, band_b, True),
+        "roofline_plain_fp64_rhs": roofline_entry(rhs64, cfg, 1, band_p, False),
         "gpu": gpu_info(),
     }
     out["accuracy"] = measure_accuracy(cfg, 100)

@@ -56,14 +56,18 @@ typedef enum {
 
 typedef enum { ADS_PWAVE = 0, ADS_ELASTIC = 1 } ads_problem;
 
-/* Arithmetic of the right-hand-side quadrature.  Sweeps, factors and the
- * time update are FP64 in every mode.  ADS_MIXED_BF16 contracts the
+/* Arithmetic of the right-hand side.  Without a wave-speed field it is the
+ * Kronecker form of eq. pwave2 (assembled 1D band matrices, three band
+ * passes, HBM-bound; the default); with one, the sum-factorized Gauss
+ * quadrature.  The mixed modes run the x- and y-passes (the quadrature's
+ * contractions) in FP32, the z-accumulation in FP64.  Sweeps, factors and
+ * the time update are FP64 in every mode.  ADS_MIXED_BF16 contracts the
  * predictor rounded to BF16 (the inputs a BF16 matrix unit would take; the
  * basis tables stay FP32), then a second pass contracts the FP64 remainder
  * and adds it (one correction step), FP32 arithmetic in both: two
  * right-hand-side launches per step, P-wave only, not accepted by pools. */
 typedef enum {
-  ADS_FP64 = 0,        /* FP64 sum-factorized quadrature                     */
+  ADS_FP64 = 0,        /* FP64 band passes / sum-factorized quadrature       */
   ADS_MIXED_FP32 = 1,  /* FP32 contractions, FP64 combination and assembly   */
   ADS_MIXED_BF16 = 2   /* BF16 inputs + FP64-remainder correction pass       */
 } ads_precision;
@@ -169,8 +173,8 @@ ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
 /* Discrete energy of the current state (synchronous; one double written to
  * host memory).  P-wave:
  *   E = 1/2 u'.(G - tau^2/4 K) u' + 1/2 u.K u,
- * G the direction-split operator of eq. pwave2, K the stiffness (quadrature,
- * as in the step).  Elasticity, with V = (U^n - U^{n-1})/tau and
+ * G the direction-split operator of eq. pwave2, K the stiffness (by FP64
+ * quadrature).  Elasticity, with V = (U^n - U^{n-1})/tau and
  * W = (U^n + U^{n-1})/2:
  *   E = 1/2 V.(D - tau^2/4 Upsilon) V + 1/2 W.Upsilon W,
  * D = L (rho M)^{-1} L^T the alternating-triangular operator of eq. pre /
@@ -184,12 +188,15 @@ ads_status ads_energy(ads_sim* sim, double* host_energy);
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 
-/* Autotuner of the right-hand-side tiling (measurement-driven, P-wave):
- * times every tile-shape variant of the quadrature kernel on this mesh
- * (HIP events, a few launches each; synchronizes), keeps the fastest and
- * caches the choice per (degree, precision, mesh) for later simulations in
- * the process.  *chosen receives the variant index, host_ms (may be NULL,
- * up to cap entries) the mean ms per variant.  Call after ads_factor.
+/* Autotuner of the right-hand side (measurement-driven, P-wave): times
+ * every variant on this mesh (HIP events, a few launches each;
+ * synchronizes): 0-2 are tile shapes of the quadrature kernel, 3 is the
+ * Kronecker form (the default; not offered with a wave-speed field), keeps
+ * the fastest and caches the choice per (degree, precision, mesh) for later
+ * simulations in the process.  *chosen receives the variant index, host_ms
+ * (may be NULL, up to cap entries) the mean ms per variant.  Call after
+ * ads_factor.  The environment variable ADS_RHS_VAR (0-3) sets the variant
+ * of a new simulation, ADS_POOL_RHS_VAR that of a new pool's launches.
  * Elasticity: no variants, returns ADS_OK with *chosen = 0. */
 ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);
 

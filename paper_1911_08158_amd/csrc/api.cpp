@@ -148,7 +148,9 @@ struct ads_sim {
   int namp = 0;
   int tz = 0;
   int ncu = 0;          // compute units of the device (tiling of the right-hand side)
-  int rhs_var = 0;      // tile variant of the P-wave right-hand side (autotuned)
+  // P-wave right-hand side: 3 = the Kronecker form (jobs with a wave-speed
+  // field take the quadrature kernel's variant 0); ads_tune may choose another
+  int rhs_var = 3;
   bool mixed = false;   // FP32 contractions in the right-hand side
   bool bf16 = false;    // ... on BF16 inputs, plus a correction pass on the remainder
   bool literal = false; // P-wave: the printed coefficient set (diagnostic)
@@ -863,8 +865,20 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
             }
             buf.push_back(m);
           }
+    // band matrices of the Kronecker form: M, then K; in x and y the
+    // diagonal slot of K holds the row sum (the x- and y-passes apply K to
+    // differences to the diagonal, so that FP32-rounded entries still
+    // annihilate constants); z keeps K itself (its pass is FP64)
     buf.insert(buf.end(), s->Mf[d].a.begin(), s->Mf[d].a.end());
-    buf.insert(buf.end(), s->Kf[d].a.begin(), s->Kf[d].a.end());
+    {
+      const Band& K = s->Kf[d];
+      const int B = 2 * K.p + 1;
+      for (int i = 0; i < K.n; ++i) {
+        double rs = 0.0;
+        for (int k = 0; k < B; ++k) rs += K.a[(size_t)i * B + k];
+        for (int k = 0; k < B; ++k) buf.push_back(k == K.p && d < 2 ? rs : K.a[(size_t)i * B + k]);
+      }
+    }
     if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return st;
     if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return st;
     if (s->elastic) {
@@ -1289,10 +1303,10 @@ struct ads_pool {
   hipGraphExec_t exec = nullptr;
   std::vector<hipEvent_t> ev;
   int nev = 0;
-  // right-hand-side tile variant per [p-2][mixed]: the 14/13-row tiles (for
-  // FP32 p=2 four-wave workgroups at five waves per SIMD, measured faster in
-  // batches than the 26-row tiles at 3.5)
-  int var[2][2] = {{0, 0}, {0, 0}};
+  // right-hand-side variant per [p-2][mixed]: the Kronecker form, bound by
+  // HBM (launches of simulations with a wave-speed field take the
+  // quadrature kernel's 14/13-row tiles, variant 0)
+  int var[2][2] = {{3, 3}, {3, 3}};
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;

@@ -7,7 +7,8 @@
 //   K = K_x(x)M_y(x)M_z + M_x(x)K_y(x)M_z + M_x(x)M_y(x)K_z,
 //   R = rscale * ( amp * b - K w ),   w = cu*u + cv*v + ca*a,
 //
-// applied as three band passes with two channels each:
+// applied as three band passes with two channels each (the stiffness
+// bands of the x- and y-passes in difference form, see band_table):
 //   x:  X1 = K_x w,            X2 = M_x w
 //   y:  YM = M_y X1 + K_y X2,  YK = M_y X2
 //   z:  K w = M_z YM + K_z YK
@@ -20,13 +21,14 @@
 // outputs and marches over the source layers that reach them (TZ + 2p).
 // Per source layer: the predictor of the layer with a p-halo in x and y
 // (formed in FP64 from the three fields, coalesced rows) goes to LDS, the
-// next layer's loads already in flight; the x-pass runs over the halo rows
+// next kDepth layers' loads already in flight; the x-pass runs over the halo rows
 // (LDS -> LDS, one thread per column, its band rows in registers); the
 // y-pass gives each owned column its two channels, which the z-band
 // scatters into 2p+1 FP64 accumulators (outputs s-p .. s+p of source
 // layer s; the z-band entries are wave-uniform scalar loads).  The oldest
 // accumulator is complete after each layer and is written.  Two barriers
-// per layer, no atomics, each output computed by one thread.
+// per layer, no atomics, each output computed by one thread.  Tiles are
+// spread over the XCDs in contiguous ranges (halo re-reads hit the L2).
 // T is the type of the x- and y-passes (double, or float in mixed mode);
 // the predictor, the z-accumulation and the output are FP64.
 #include "common.hpp"
@@ -35,6 +37,7 @@
 namespace ads {
 
 constexpr int BTX = 32, BTY = 8, BNT = BTX * BTY;
+constexpr int kDepth = 2;   // source layers whose loads are in flight
 
 template <typename T, int p>
 struct BandGeom {
@@ -64,15 +67,21 @@ __device__ __forceinline__ float bf16_round_band(float x) {
 
 // Assembled 1D matrices of direction d after the element tables of that
 // direction: M [nf][2p+1], then K [nf][2p+1]; entry (i, j) at
-// i*(2p+1) + (j - i + p), zero where j leaves the free range.
+// i*(2p+1) + (j - i + p), zero where j leaves the free range.  In x and y
+// the diagonal slot of K holds the row sum s_i instead, for the difference
+// form
+//   (K v)_i = s_i v_i + sum_{j != i} K_ij (v_j - v_i),
+// in which FP32-rounded entries still annihilate constants (s_i is zero
+// away from eliminated boundary coefficients); z keeps K (FP64 pass).
 template <int p>
 __device__ __forceinline__ const double* band_table(const double* tab, int E) {
   constexpr int P = p + 1, Q = p + 1;
   return tab + (4ll * E * Q * P + (long long)E * Q + 2ll * E * P * P);
 }
 
+// waves per SIMD: five (FP32) or four (FP64) at p = 2, four or three at p = 3
 template <typename T, int p>
-__global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T) == 4 ? 4 : 3)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
   using Gm = BandGeom<T, p>;
   constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NXI = Gm::NXI;
   __shared__ T smem[Gm::LDS];
@@ -83,7 +92,14 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
   const int tid = threadIdx.x, lx = tid % BTX, ly = tid / BTX;
 
-  for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+  // Workgroups are dispatched to the eight XCDs in turn (block b on XCD
+  // b mod 8), each XCD with its own L2: work item w is mapped so that every
+  // XCD takes one contiguous range of tiles (x fastest, then y, then the
+  // z-chunk), whose neighbours share their halo rows in that L2.  The
+  // remainder of total_tiles mod 8 keeps its order.
+  const int full = total_tiles & ~7;
+  for (int wi = blockIdx.x; wi < total_tiles; wi += gridDim.x) {
+    const int tile = wi >= full ? wi : (wi & 7) * (full >> 3) + (wi >> 3);
     const RhsJob& J = jobs[find_job_band(jobs, njobs, tile)];
     const int t = tile - J.tile0;
     const int tx = t % J.tiles[0];
@@ -143,9 +159,14 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
     const bool own = x0 + lx < nfx && y0 + ly < nfy;
     const long long ocol = own ? (long long)(y0 + ly) * nfx + (x0 + lx) : 0;
 
-    double pf[NS];
-    double pld = 0.0, prr = 0.0;   // load vector and previous R of the next output
-    auto prefetch = [&](int s) {
+    // kDepth layers of loads in flight: register set d holds the layers
+    // s = sb + d (mod kDepth), with the load vector and the previous R of
+    // the output its layer completes
+    double pf[kDepth][NS];
+    double pld[kDepth], prr[kDepth];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) pld[d] = prr[d] = 0.0;
+    auto prefetch = [&](int s, double (&pf)[NS], double& pld, double& prr) {
       const long long zo = (long long)s * sxy;
       long long gi[NS];
 #pragma unroll
@@ -167,7 +188,9 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
       if (LD != nullptr) pld = ov ? LD[go] : 0.0;
       if (accumulate) prr = ov ? R[go] : 0.0;
     };
-    auto commit = [&]() {
+    // W is free when a layer is committed: every thread passed the second
+    // barrier of the previous layer after its x-pass
+    auto commit = [&](const double (&pf)[NS]) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         const int k = tid + i * BNT;
@@ -189,14 +212,8 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
     double acc[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = 0.0;
-    const int sb = max(0, Z0 - p), se = min(nfz - 1, Zend - 1 + p);
-    prefetch(sb);
-    for (int s = sb; s <= se; ++s) {
-      // W is free: every thread passed the second barrier of the previous
-      // layer after its x-pass
-      commit();
-      const double ldv = pld, rv = prr;
-      if (s < se) prefetch(s + 1);
+    // x-, y- and z-passes of committed source layer s
+    auto process = [&](int s, double ldv, double rv) {
       __syncthreads();
       // x-pass over the halo rows
 #pragma unroll
@@ -204,11 +221,12 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
         const int r = ly + i * (BNT / BTX);
         if (r < SY) {
           const T* w = Wl + r * SX + lx;
-          T a1 = kx[0] * w[0], a2 = mx[0] * w[0];
+          const T wc = w[p];
+          T a1 = kx[p] * wc, a2 = mx[0] * w[0];
 #pragma unroll
-          for (int k = 1; k < B; ++k) {
-            a1 = fma(kx[k], w[k], a1);
-            a2 = fma(mx[k], w[k], a2);
+          for (int k = 0; k < B; ++k) {
+            if (k != p) a1 = fma(kx[k], w[k] - wc, a1);
+            if (k > 0) a2 = fma(mx[k], w[k], a2);
           }
           X1[r * BTX + lx] = a1;
           X2[r * BTX + lx] = a2;
@@ -219,14 +237,17 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
       {
         const T* c1 = X1 + ly * BTX + lx;
         const T* c2 = X2 + ly * BTX + lx;
+        const T v2c = c2[p * BTX];
         T ym = my[0] * c1[0], yk = my[0] * c2[0];
-        ym = fma(ky[0], c2[0], ym);
+        ym = fma(ky[p], v2c, ym);
 #pragma unroll
-        for (int k = 1; k < B; ++k) {
+        for (int k = 0; k < B; ++k) {
           const T v1 = c1[k * BTX], v2 = c2[k * BTX];
-          ym = fma(my[k], v1, ym);
-          ym = fma(ky[k], v2, ym);
-          yk = fma(my[k], v2, yk);
+          if (k > 0) {
+            ym = fma(my[k], v1, ym);
+            yk = fma(my[k], v2, yk);
+          }
+          if (k != p) ym = fma(ky[k], v2 - v2c, ym);
         }
         const double dym = (double)ym, dyk = (double)yk;
         // output o = s - p + k takes column s of its z-band rows: entry
@@ -244,6 +265,22 @@ __global__ __launch_bounds__(BNT) void rhs_band_kernel(const LaunchHdr* __restri
 #pragma unroll
       for (int k = 0; k < B - 1; ++k) acc[k] = acc[k + 1];
       acc[B - 1] = 0.0;
+    };
+
+    const int sb = max(0, Z0 - p), se = min(nfz - 1, Zend - 1 + p);
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d)
+      if (sb + d <= se) prefetch(sb + d, pf[d], pld[d], prr[d]);
+    for (int s0 = sb; s0 <= se; s0 += kDepth) {
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) {
+        const int s = s0 + d;
+        if (s > se) break;
+        commit(pf[d]);
+        const double ldv = pld[d], rv = prr[d];
+        if (s + kDepth <= se) prefetch(s + kDepth, pf[d], pld[d], prr[d]);
+        process(s, ldv, rv);
+      }
     }
     // outputs se - p + 1 .. se + p: loads at store time (the tail of the range)
 #pragma unroll

@@ -42,3 +42,23 @@ def test_more_than_one_gpu_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_rhs_bytes_and_roofline_entries():
+    """Algorithmic bytes of the Kronecker-form right-hand side (u, u', u''
+    in, R out) and the roofline entries built from a kernel-table row."""
+    import workloads as W
+    assert bench.RHS_BYTES == 3 * 8 + 8
+    cfg = W.C3
+    nfree = 128 ** 3 * 4
+    row = {"kernel": "sweep_z", "ms": 0.1, "gbs": round(56 * nfree / 1e-4 / 1e9, 1)}
+    e = bench.roofline_entry(row, cfg, 4, True, True)
+    assert e["bound"] == "hbm" and e["unit"] == "GB/s" and e["peak"] == 8000.0
+    assert abs(e["frac"] - 56 * nfree / 1e-4 / 1e9 / 8000.0) < 1e-4
+    row = {"kernel": "rhs", "ms": 0.1, "gbs": 100.0, "tflops": 1.0}
+    assert bench.roofline_entry(row, cfg, 4, True, True)["bound"] == "hbm"
+    q = bench.roofline_entry(row, cfg, 4, False, True)
+    assert q["bound"] == "alu" and q["peak"] == bench.FP32_PEAK_TFLOPS
+    assert bench.roofline_entry(row, cfg, 1, False, False)["peak"] == bench.FP64_PEAK_TFLOPS
+    # a traffic record only counts for the sources it was measured on
+    assert bench.kernel_traffic("sweep_xy", 4) is None and bench.kernel_traffic("rhs", 1) is None

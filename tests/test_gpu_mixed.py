@@ -1,7 +1,8 @@
-"""Mixed-precision right-hand side (FP32 contractions, FP64 predictor,
-z-accumulation, assembly, factors, sweeps and update) against the FP64
-oracle: relative L2 error of u reported per step; target <= 1e-6 after 100
-steps on C3 (128^3 elements, p = 2).  The BF16-input mode (predictor rounded
+"""Mixed-precision right-hand side (FP32 contractions or band passes, FP64
+predictor, z-accumulation, assembly, factors, sweeps and update), in both
+forms (Kronecker band passes and quadrature), against the FP64 oracle:
+relative L2 error of u reported per step; target <= 1e-6 after 100 steps on
+C3 (128^3 elements, p = 2).  The BF16-input mode (predictor rounded
 to BF16, then a correction pass on the FP64 remainder) is held to the same
 bar."""
 import numpy as np
@@ -22,8 +23,10 @@ def _cuda():
 @pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
                                  W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
                          ids=["p2", "p3"])
-def test_mixed_small_meshes(cfg):
+@pytest.mark.parametrize("form", ["band", "quadrature"])
+def test_mixed_small_meshes(cfg, form, monkeypatch):
     _cuda()
+    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
     sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0))
     sim.factor()
@@ -38,8 +41,10 @@ def test_mixed_small_meshes(cfg):
 @pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
                                  W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
                          ids=["p2", "p3"])
-def test_bf16_inputs_small_meshes(cfg):
+@pytest.mark.parametrize("form", ["band", "quadrature"])
+def test_bf16_inputs_small_meshes(cfg, form, monkeypatch):
     _cuda()
+    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
     sim, _ = gpu_sim(cfg, precision="mixed_bf16", u0_full=pw.to_full(u0))
     sim.factor()

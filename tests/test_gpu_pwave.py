@@ -37,8 +37,12 @@ def _cuda():
     W.C1.with_(nelem=(6, 13, 5), p=3, q=4, steps=4, tau=0.02, bc="natural"),
     W.C1.with_(nelem=(1, 2, 1), steps=3, init="noise", bc="natural"),
 ], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
-def test_pwave_run_matches_oracle(cfg):
+@pytest.mark.parametrize("form", ["band", "quadrature"])
+def test_pwave_run_matches_oracle(cfg, form, monkeypatch):
+    """Both right-hand-side forms: the Kronecker band passes (variant 3, the
+    default) and the sum-factorized quadrature (variant 0)."""
     _cuda()
+    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
     pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
     sim, u0 = gpu_sim(cfg)
     # projection (projection contractions + mass sweeps)
