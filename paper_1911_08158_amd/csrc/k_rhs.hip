@@ -191,7 +191,12 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
   // b-stage rows of the owned column: cyo*Q + (p - b)*Q + gy
   const int brow0 = rowpos(cyo * Q) + cxo, bpar = (cyo * Q) & 1;
 
-  for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+  // each XCD (block b runs on XCD b mod 8) takes one contiguous range of
+  // tiles, whose neighbours share their halo columns in its L2; the
+  // remainder of total_tiles mod 8 keeps its order
+  const int full = total_tiles & ~7;
+  for (int wi = blockIdx.x; wi < total_tiles; wi += gridDim.x) {
+    const int tile = wi >= full ? wi : (wi & 7) * (full >> 3) + (wi >> 3);
     const RhsJob& J = jobs[find_job_rhs(jobs, njobs, tile)];
     const int t = tile - J.tile0;
     const int tx = t % J.tiles[0];
