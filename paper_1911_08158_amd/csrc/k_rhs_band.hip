@@ -25,7 +25,9 @@
 // (LDS -> LDS, one thread per column, its band rows in registers); the
 // y-pass gives each owned column its two channels, which the z-band
 // scatters into 2p+1 FP64 accumulators (outputs s-p .. s+p of source
-// layer s; the z-band entries are wave-uniform scalar loads).  The oldest
+// layer s; the layer's z-band entries are one vector load per wave issued
+// with its predictor, one entry per lane, broadcast by readlane, since
+// scalar loads would share their wait counter with the LDS traffic).  The oldest
 // accumulator is complete after each layer and is written.  Two barriers
 // per layer, no atomics, each output computed by one thread.  Tiles are
 // spread over the XCDs in contiguous ranges (halo re-reads hit the L2).
@@ -136,7 +138,14 @@ __global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T)
         ky[k] = vy ? (T)by[(long long)nfy * B + iy + k] : T(0);
       }
     }
-    const cmem<double>* bz = cview(band_table<p>(J.tab[2], J.E[2]));
+    // z-band entries of a source layer s, one per lane of every wave: lane
+    // k < 2p+1 holds M_z(s-p+k, s), lane 2p+1+k holds K_z(s-p+k, s) (zero
+    // outside the free range); loaded with the layer's predictor and read
+    // back with readlane
+    const gmem<double>* bzg = gview(band_table<p>(J.tab[2], J.E[2]));
+    const int zlane = threadIdx.x & 63;
+    const int zk = zlane < B ? zlane : zlane - B;
+    const long long zoff = zlane < B ? 0ll : (long long)nfz * B;
     double ampv = 0.0;
     if (J.load != nullptr && J.amp != nullptr) {
       long long ai = (long long)(*gview(J.counter)) + J.amp_shift;
@@ -163,10 +172,16 @@ __global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T)
     // s = sb + d (mod kDepth), with the load vector and the previous R of
     // the output its layer completes
     double pf[kDepth][NS];
-    double pld[kDepth], prr[kDepth];
+    double pld[kDepth], prr[kDepth], pzb[kDepth];
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) pld[d] = prr[d] = 0.0;
-    auto prefetch = [&](int s, double (&pf)[NS], double& pld, double& prr) {
+    auto prefetch = [&](int s, double (&pf)[NS], double& pld, double& prr, double& pzb) {
+      {
+        const int o = s - p + zk;
+        const bool ok = zlane < 2 * B && o >= 0 && o < nfz;
+        pzb = bzg[ok ? zoff + (long long)o * B + (2 * p - zk) : 0];
+        pzb = ok ? pzb : 0.0;
+      }
       const long long zo = (long long)s * sxy;
       long long gi[NS];
 #pragma unroll
@@ -213,7 +228,7 @@ __global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T)
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = 0.0;
     // x-, y- and z-passes of committed source layer s
-    auto process = [&](int s, double ldv, double rv) {
+    auto process = [&](int s, double ldv, double rv, double zbv) {
       __syncthreads();
       // x-pass over the halo rows
 #pragma unroll
@@ -252,14 +267,15 @@ __global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T)
         const double dym = (double)ym, dyk = (double)yk;
         // output o = s - p + k takes column s of its z-band rows: entry
         // (o, s) at o*(2p+1) + (s - o + p) = o*(2p+1) + 2p - k
+        const long long zbb = __double_as_longlong(zbv);
+        const int zlo = (int)(zbb & 0xffffffffll), zhi = (int)(zbb >> 32);
+        auto lane_d = [&](int l) {
+          const unsigned lo = (unsigned)__builtin_amdgcn_readlane(zlo, l);
+          const unsigned hi = (unsigned)__builtin_amdgcn_readlane(zhi, l);
+          return __longlong_as_double(((long long)hi << 32) | lo);
+        };
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int o = s - p + k;
-          const bool ok = o >= 0 && o < nfz;
-          const long long e = ok ? (long long)o * B + (2 * p - k) : 0;
-          const double mz = ok ? bz[e] : 0.0, kz = ok ? bz[(long long)nfz * B + e] : 0.0;
-          acc[k] = fma(mz, dym, fma(kz, dyk, acc[k]));
-        }
+        for (int k = 0; k < B; ++k) acc[k] = fma(lane_d(k), dym, fma(lane_d(B + k), dyk, acc[k]));
       }
       store(s - p, acc[0], ldv, rv);
 #pragma unroll
@@ -270,16 +286,16 @@ __global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T)
     const int sb = max(0, Z0 - p), se = min(nfz - 1, Zend - 1 + p);
 #pragma unroll
     for (int d = 0; d < kDepth; ++d)
-      if (sb + d <= se) prefetch(sb + d, pf[d], pld[d], prr[d]);
+      if (sb + d <= se) prefetch(sb + d, pf[d], pld[d], prr[d], pzb[d]);
     for (int s0 = sb; s0 <= se; s0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
         const int s = s0 + d;
         if (s > se) break;
         commit(pf[d]);
-        const double ldv = pld[d], rv = prr[d];
-        if (s + kDepth <= se) prefetch(s + kDepth, pf[d], pld[d], prr[d]);
-        process(s, ldv, rv);
+        const double ldv = pld[d], rv = prr[d], zbv = pzb[d];
+        if (s + kDepth <= se) prefetch(s + kDepth, pf[d], pld[d], prr[d], pzb[d]);
+        process(s, ldv, rv, zbv);
       }
     }
     // outputs se - p + 1 .. se + p: loads at store time (the tail of the range)
