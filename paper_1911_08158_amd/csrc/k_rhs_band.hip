@@ -81,9 +81,10 @@ __device__ __forceinline__ const double* band_table(const double* tab, int E) {
   return tab + (4ll * E * Q * P + (long long)E * Q + 2ll * E * P * P);
 }
 
-// waves per SIMD: five (FP32) or four (FP64) at p = 2, four or three at p = 3
+// waves per SIMD: four at p = 2 (FP32 at five spills registers and runs
+// slower), four (FP32) or three (FP64) at p = 3
 template <typename T, int p>
-__global__ __launch_bounds__(BNT, p == 2 ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T) == 4 ? 4 : 3)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
   using Gm = BandGeom<T, p>;
   constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NXI = Gm::NXI;
   __shared__ T smem[Gm::LDS];
