@@ -192,10 +192,10 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * every variant on this mesh (HIP events, a few launches each;
  * synchronizes): 0-2 are tile shapes of the quadrature kernel, 3 is the
  * Kronecker form (the default; not offered with a wave-speed field), keeps
- * the fastest and caches the choice per (degree, precision, mesh) for later
- * simulations in the process.  *chosen receives the variant index, host_ms
- * (may be NULL, up to cap entries) the mean ms per variant.  Call after
- * ads_factor.  The environment variable ADS_RHS_VAR (0-3) sets the variant
+ * the fastest and caches the choice per (degree, precision, field or none,
+ * mesh) for later simulations in the process.  *chosen receives the variant
+ * index, host_ms (may be NULL, up to cap entries) the mean ms per variant.
+ * Call after ads_factor.  The environment variable ADS_RHS_VAR (0-3) sets the variant
  * of a new simulation, ADS_POOL_RHS_VAR that of a new pool's launches.
  * Elasticity: no variants, returns ADS_OK with *chosen = 0. */
 ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);

@@ -1113,7 +1113,10 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
     return ADS_OK;
   }
   static std::map<std::string, int> cache;
-  const std::string key = std::to_string(s->p) + "/" + std::to_string(s->mixed) + "/" + std::to_string(s->nf[0]) +
+  // the wave-speed field is part of the key: without one the Kronecker form
+  // is a candidate, with one it is not
+  const std::string key = std::to_string(s->p) + "/" + std::to_string(s->mixed) + "/" +
+                          std::to_string(s->coef != nullptr) + "/" + std::to_string(s->nf[0]) +
                           "x" + std::to_string(s->nf[1]) + "x" + std::to_string(s->nf[2]);
   const int nv = rhs_num_variants(s->p, s->coef != nullptr);
   int best = -1;
