@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the per-step hot path on one MI355X.
 
-A "step" is one pass of the whole hot path over the batch: right-hand side
-by sum-factorized Gauss quadrature, x-, y- and z-sweeps of the banded LU
-factors, Newmark update (fused into the z-sweep).  Workload: the 3D P-wave
-with 128^3 elements, p = 2 (130^3 DOFs), tau = 2e-3.
+A "step" is one pass of the whole hot path over the batch: the right-hand
+side F - K w of the Newmark predictor w, the x-, y- and z-line solves with
+the banded LU factors of the direction-split operator, and the Newmark
+update (fused into the z-sweep).  Without a wave-speed field the
+right-hand side is the Kronecker form of the stiffness (three assembled 1D
+band passes, eq. pwave2 in 3D); with one (the ``quadrature_rhs`` leg) it is
+the sum-factorized Gauss quadrature.  Workload: the 3D P-wave with 128^3
+elements, p = 2 (130^3 DOFs), tau = 2e-3.
 
-Two forms are timed (the metric compares them):
+Forms timed (the metric compares the first two):
   plain_fp64     one simulation, FP64 right-hand side, per-kernel launches
-  batched_mixed  a batch of B such simulations in one pool, FP32
-                 contractions in the right-hand side (FP64 everything else),
-                 one graph replay per step (persistent kernels over job tables)
+  batched_mixed  a batch of B such simulations in one pool, FP32 stiffness
+                 passes in the right-hand side (FP64 everything else), one
+                 graph replay per step (persistent kernels over job tables)
 ``value`` is the batched mixed form's DOF-steps/s (n^3 DOFs per simulation,
-boundary DOFs included; inputs resident in HBM).  Kernel durations come from
-HIP events on the library's stream: for the plain form inside its timed
-steps, for the batched form in a profiled pass of the same batch with direct
-launches.  The CPU oracle is timed on this host on a bounded sample.
+boundary DOFs included; inputs resident in HBM).  Timed regions carry no
+per-kernel events; kernel durations come from HIP events on the library's
+stream in a separate profiled pass of the same form.  The CPU oracle is
+timed on this host on a bounded sample, and gives the reference of the
+``accuracy`` entry (u, u', u'' after 100 steps).
 """
 import argparse
 import json
@@ -84,10 +89,18 @@ KERNEL_NAMES = {
 }
 
 
+def band_fmas_per_dof(p):
+    """Multiply-adds the Kronecker-form right-hand side executes per free
+    coefficient: 7 band applications of width 2p+1 (x: K, M; y: M, K, M;
+    z: M, K)."""
+    return 7 * (2 * p + 1)
+
+
 def roofline_entry(k, cfg, batch, band, fp32):
     """Roofline of one launch kind: HBM for the sweeps and the Kronecker-form
-    right-hand side (algorithmic bytes), FP32 / FP64 ALU for the quadrature
-    right-hand side (nominal flops)."""
+    right-hand side (algorithmic bytes), FP32 / FP64 vector ALU for the
+    quadrature right-hand side (algorithmic flops of the tile-shared sum
+    factorization)."""
     nfree = int(np.prod([n - 2 for n in cfg.n])) * batch
     if k["kernel"] == "rhs" and not band:
         peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
@@ -103,9 +116,9 @@ def roofline_entry(k, cfg, batch, band, fp32):
          "kernel": KERNEL_NAMES.get(k["kernel"], k["kernel"]),
          "per_launch": f"{per} B per free DOF x {nfree} free DOFs ({batch} simulations)"}
     if k["kernel"] == "rhs":
-        e["nominal_tflops"] = k["tflops"]
-        e["note"] = ("7(2p+1) = 35 multiply-adds per coefficient at p = 2; the nominal sum-factorized quadrature "
-                     f"({rhs_flops_per_element(cfg.p)} flops per element) would be {k['tflops']} TFLOP/s")
+        f = band_fmas_per_dof(cfg.p)
+        e["executed_tflops"] = round(2 * f * nfree / (k["ms"] * 1e-3) / 1e12, 3)
+        e["note"] = f"executes {f} multiply-adds per free coefficient (7 band passes of width 2p+1)"
     return e
 
 
@@ -134,7 +147,10 @@ def setup_sim(sim, cfg):
     sim.factor()
 
 
-def kernel_table(entries, cfg, batch, mixed_peak=False):
+def kernel_table(entries, cfg, batch, band=True):
+    """Per-kernel figures: algorithmic bytes and GB/s for every launch; for
+    the right-hand side also its flops (executed band multiply-adds for the
+    Kronecker form, tile-shared quadrature flops for the quadrature form)."""
     nx, ny, nz = cfg.n
     nfree = (nx - 2) * (ny - 2) * (nz - 2) * batch
     nel = int(np.prod(cfg.nelem)) * batch
@@ -142,9 +158,10 @@ def kernel_table(entries, cfg, batch, mixed_peak=False):
     for k, m in entries:
         e = {"kernel": k, "ms": round(float(m), 5)}
         if k == "rhs":
-            fl = rhs_flops_per_element(cfg.p) * nel
+            fl = 2 * band_fmas_per_dof(cfg.p) * nfree if band else rhs_flops_per_element(cfg.p) * nel
             by = RHS_BYTES * nfree
             e.update(algorithmic_flops=fl, tflops=round(fl / (m * 1e-3) / 1e12, 3),
+                     flops_counted="band multiply-adds" if band else "tile-shared sum-factorized quadrature",
                      algorithmic_bytes=by, gbs=round(by / (m * 1e-3) / 1e9, 1))
         elif k in SWEEP_BYTES:
             by = SWEEP_BYTES[k] * nfree
@@ -153,33 +170,43 @@ def kernel_table(entries, cfg, batch, mixed_peak=False):
     return out
 
 
-def measure_plain(cfg, steps, warmup, precision="fp64"):
+def measure_plain(cfg, steps, warmup, precision="fp64", coef=False, tune=True):
     """Plain per-simulation form (FP64 unless asked): one simulation,
-    per-kernel launches."""
+    per-kernel launches.  The timed steps carry no events; kernel times come
+    from a separate profiled pass (HIP events around every kernel).  coef:
+    a smooth wave-speed field (the quadrature right-hand side)."""
     import torch
     from paper_1911_08158_amd import Sim
     sim = Sim(cfg, device="cuda:0", precision=precision)
+    if coef:
+        import workloads as W
+        xs = [sim.quad_points(d) for d in range(3)]
+        sim.set_coefficient(torch.from_numpy(W.wave_speed_field(*xs)).to("cuda:0"), 1.5)
     setup_sim(sim, cfg)
-    tune = sim.tune()
+    var = int(sim.tune()[0]) if tune else None
     sim.step(warmup)
     torch.cuda.synchronize()
-    sim.profile(True)
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms, kinds, step_ms = sim.profile_read(steps)
+    nprof = max(5, min(steps, 50))
+    sim.profile(True)
+    sim.step(nprof)
+    ms, kinds, step_ms = sim.profile_read(nprof)
+    sim.profile(False)
     sim.check_finite()
     sim.close()
     wall = t1 - t0
     return {
         "dof_steps_per_s": cfg.dofs() * steps / wall,
         "ms_per_step": wall / steps * 1e3,
-        "kernels": kernel_table(list(zip(kinds, ms)), cfg, 1),
+        "kernels": kernel_table(list(zip(kinds, ms)), cfg, 1, band=(var == 3)),
         "step_ms_p50": float(np.percentile(step_ms, 50)),
         "step_ms_p99": float(np.percentile(step_ms, 99)),
-        "rhs_variant": int(tune[0]),
-        "timing": "HIP events around every kernel inside the timed steps",
+        "rhs_variant": var,
+        "timing": f"wall clock over {steps} steps without events; kernels and per-step latency from HIP events "
+                  f"in {nprof} profiled steps",
     }
 
 
@@ -258,27 +285,38 @@ def measure_small_latency(cfg, steps, warmup):
 
 
 def measure_accuracy(cfg, steps):
-    """Error of the reduced-precision forms: relative L2 of u after `steps`
-    steps of the mixed FP32 and the BF16-input forms against the FP64 form,
-    all three started from the same projected initial state (the FP64 form
-    itself matches the FP64 oracle to <= 1e-12 in the parity tests)."""
+    """Error of every form against the FP64 oracle: relative L2 (and the
+    pointwise maximum relative to the largest entry) of u, u' and u'' after
+    `steps` steps, the GPU forms started from the oracle's projected
+    coefficients (the oracle run takes about a minute on the host)."""
     import torch
+
+    import workloads as W
+    from oracle import pwave
     from paper_1911_08158_amd import Sim
-    ref, out = None, {}
+    t0 = time.perf_counter()
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau)
+    u0 = pw.project(W.initial_values(cfg, *[pw.quad_points(d) for d in range(3)]))
+    ref = [pw.to_full(x) for x in pw.run(u0, None, steps)]
+    t_oracle = time.perf_counter() - t0
+    u0_full = torch.from_numpy(np.ascontiguousarray(pw.to_full(u0))).to("cuda:0")
+    out = {}
     for prec in ("fp64", "mixed_fp32", "mixed_bf16"):
         sim = Sim(cfg, device="cuda:0", precision=prec)
-        setup_sim(sim, cfg)
+        sim.set_state(u0_full, None, None, 0)
+        sim.factor()
         sim.step(steps)
-        u = sim.get_state()[0].to(torch.float64)
+        st = [t.cpu().numpy() for t in sim.get_state()]
         sim.close()
-        if ref is None:
-            ref = u
-        else:
-            out[prec] = float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
-    return {"workload": f"P-wave 128^3 elements p=2, one simulation per form, {steps} steps",
-            "rel_l2_u_vs_fp64": out,
-            "reference": "the FP64 form from the same initial coefficients (within 1e-12 of the FP64 oracle "
-                         "in the parity tests)"}
+        ent = {}
+        for name, x, r in zip(("u", "v", "a"), st, ref):
+            ent[name] = float(np.linalg.norm(x - r) / np.linalg.norm(r))
+            ent[name + "_max"] = float(np.abs(x - r).max() / np.abs(r).max())
+        out[prec] = ent
+    return {"workload": f"P-wave 128^3 elements p=2 tau=2e-3, one simulation per form, {steps} steps",
+            "reference": "CPU FP64 oracle (same projected initial coefficients)",
+            "metric": "relative L2 over all coefficients; *_max: largest pointwise error / largest entry",
+            "v": "u'", "a": "u''", "oracle_seconds": round(t_oracle, 1), "errors": out}
 
 
 def measure_elastic(cfg, steps, warmup):
@@ -426,7 +464,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy"], default=None,
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature"], default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -452,6 +490,11 @@ def main():
     if args.only == "elastic":
         print(json.dumps({"form": "elastic", **measure_elastic(W.C4, args.steps, args.warmup)}), flush=True)
         return
+    if args.only == "quadrature":
+        for prec in ("fp64", "mixed_fp32"):
+            q = measure_plain(cfg.with_(precision=prec), args.steps, args.warmup, precision=prec, coef=True)
+            print(json.dumps({"form": f"quadrature_{prec}", **q}), flush=True)
+        return
     if args.only == "accuracy":
         print(json.dumps({"form": "accuracy", **measure_accuracy(cfg, args.steps)}), flush=True)
         return
@@ -476,7 +519,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (right-hand-side x- and y-band passes) + f64 (predictor, z-accumulation, factors, sweeps, update)",
+        "dtype": "f32 (right-hand-side x- and y-stiffness passes on f64 differences) + f64 (predictor, mass channel, "
+                 "z-accumulation, factors, sweeps, update)",
         "data": "synthetic",
         "config": {"workload": f"{args.batch} x P-wave 128^3 elements p=2 (130^3 DOFs each) tau=2e-3, "
                                "batched in one pool, mixed-precision right-hand side, graph replay",
@@ -492,6 +536,16 @@ def main():
         "gpu": gpu_info(),
     }
     out["accuracy"] = measure_accuracy(cfg, 100)
+    # the quadrature right-hand side (a wave-speed field), FP64 and mixed
+    quad = {}
+    for prec in ("fp64", "mixed_fp32"):
+        q = measure_plain(cfg.with_(precision=prec), args.steps, args.warmup, precision=prec, coef=True)
+        rk = next(k for k in q["kernels"] if k["kernel"] == "rhs")
+        q["roofline_rhs"] = roofline_entry(rk, cfg, 1, False, prec != "fp64")
+        quad[prec] = q
+    out["quadrature_rhs"] = {"workload": "P-wave 128^3 elements p=2 tau=2e-3 with the wave-speed field "
+                                         "c^2 = 1 + 0.5 sin(2 pi x) cos(2 pi y) sin(2 pi z + 0.3) at the Gauss points "
+                                         "(c2ref = 1.5), one simulation", **quad}
     out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup)
     c2 = W.C2.with_(precision="fp64")
     out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
@@ -499,7 +553,7 @@ def main():
     out["c1_latency"] = measure_small_latency(W.C1, 200, 20)
     out["bf16_inputs"] = {"workload": "P-wave 128^3 elements p=2, one simulation, right-hand side on the predictor "
                                       "rounded to BF16 plus a correction pass on the FP64 remainder (FP32 "
-                                      "contractions; two right-hand-side launches per step)",
+                                      "stiffness passes; two right-hand-side launches per step)",
                           **measure_plain(cfg.with_(precision="mixed_bf16"), args.steps, args.warmup,
                                           precision="mixed_bf16")}
     if args.large_batch > 0:

@@ -197,7 +197,8 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * index, host_ms (may be NULL, up to cap entries) the mean ms per variant.
  * Call after ads_factor.  The environment variable ADS_RHS_VAR (0-3) sets the variant
  * of a new simulation, ADS_POOL_RHS_VAR that of a new pool's launches.
- * Elasticity: no variants, returns ADS_OK with *chosen = 0. */
+ * Elasticity: no variants, returns ADS_OK with *chosen = 0.  ADS_ESTATE for
+ * a simulation owned by a pool (the pool fixes the launch classes). */
 ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);
 
 /* Copy the state out (full layout; asynchronous on the sim's stream).

@@ -74,6 +74,17 @@ class Params(ctypes.Structure):
         nx, ny, nz = self.n
         return ((3,) if self.comps == 3 else ()) + (nz, ny, nx)
 
+    @property
+    def full_numel(self):
+        return int(np.prod(self.full_shape))
+
+    @property
+    def gauss_numel(self):
+        """Gauss points of one component ([(E_z q)][(E_y q)][(E_x q)]; the
+        flat z-direction of a two-dimensional problem has one element)."""
+        q = int(self.p) + 1
+        return int(np.prod([max(int(self.nelem[d]), 1) * q for d in range(3)]))
+
 
 def lib_path() -> str:
     return os.path.join(_HERE, "lib", "libads.so")
@@ -153,11 +164,17 @@ def quad_points(prm: Params, d: int) -> np.ndarray:
     return out
 
 
-def _ptr(t):
+def _ptr(t, numel=None, what="tensor"):
+    """Device address of an FP64 contiguous device tensor holding exactly
+    ``numel`` entries (a wrongly sized array would make the kernels read or
+    write past its end).  None passes through."""
     if t is None:
         return None
     import torch
-    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "FP64 contiguous device tensor"
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{what}: an FP64 contiguous device tensor is required")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} entries, {numel} expected")
     return t.data_ptr()
 
 
@@ -176,8 +193,9 @@ class Sim:
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         h = c_void_p()
-        _check(L.ads_create(byref(self.prm), self._ws_ptr, nb, self.stream.cuda_stream, _ptr(u0), _ptr(v0),
-                            byref(h)))
+        nf = self.prm.full_numel
+        _check(L.ads_create(byref(self.prm), self._ws_ptr, nb, self.stream.cuda_stream, _ptr(u0, nf, "u0"),
+                            _ptr(v0, nf, "v0"), byref(h)))
         self._h = h
 
     # -- helpers ----------------------------------------------------------
@@ -215,14 +233,16 @@ class Sim:
         out = self._empty_full()
         vals = vals.to(self.device, torch.float64).contiguous()
         self._pre()
-        _check(L.ads_project(self._h, _ptr(vals), _ptr(out), scratch.data_ptr(), n.value))
+        _check(L.ads_project(self._h, _ptr(vals, self.prm.gauss_numel * self.prm.comps, "vals"),
+                             _ptr(out, self.prm.full_numel, "out"), scratch.data_ptr(), n.value))
         self._post()
         return out
 
     def set_load(self, b, amps):
         amps = np.ascontiguousarray(amps, dtype=np.float64)
         self._pre()
-        _check(load_library().ads_set_load(self._h, _ptr(b), amps.ctypes.data, int(amps.size)))
+        _check(load_library().ads_set_load(self._h, _ptr(b, self.prm.full_numel, "load"), amps.ctypes.data,
+                                           int(amps.size)))
 
     def set_point_load(self, xs, amps):
         xs = np.ascontiguousarray(xs, dtype=np.float64)
@@ -239,7 +259,7 @@ class Sim:
             c2 = c2.to(self.device, torch.float64).contiguous()
         self._coef = c2
         self._pre()
-        _check(load_library().ads_set_coefficient(self._h, _ptr(c2), float(c2ref)))
+        _check(load_library().ads_set_coefficient(self._h, _ptr(c2, self.prm.gauss_numel, "c2"), float(c2ref)))
 
     SCHEMES = {"newmark": 0, "literal": 1}
 
@@ -265,13 +285,16 @@ class Sim:
         u, v = self._empty_full(), self._empty_full()
         a = self._empty_full() if self.prm.comps == 1 else None
         self._pre()
-        _check(load_library().ads_get_state(self._h, _ptr(u), _ptr(v), _ptr(a)))
+        nf = self.prm.full_numel
+        _check(load_library().ads_get_state(self._h, _ptr(u, nf, "u"), _ptr(v, nf, "v"), _ptr(a, nf, "a")))
         self.stream.synchronize()
         return u, v, a
 
     def set_state(self, u, v=None, a=None, step=0):
         self._pre()
-        _check(load_library().ads_set_state(self._h, _ptr(u), _ptr(v), _ptr(a), int(step)))
+        nf = self.prm.full_numel
+        _check(load_library().ads_set_state(self._h, _ptr(u, nf, "u"), _ptr(v, nf, "v"), _ptr(a, nf, "a"),
+                                            int(step)))
 
     def step_index(self):
         s = c_int64()

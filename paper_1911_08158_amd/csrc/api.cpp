@@ -154,6 +154,8 @@ struct ads_sim {
   bool mixed = false;   // FP32 contractions in the right-hand side
   bool bf16 = false;    // ... on BF16 inputs, plus a correction pass on the remainder
   bool literal = false; // P-wave: the printed coefficient set (diagnostic)
+  bool pooled = false;  // owned by a pool: its launch shapes are the pool's
+  bool* pool_dirty = nullptr;   // the owning pool's flag: its tables copy this sim's jobs
   const double* coef = nullptr;   // P-wave: caller's c^2 at the Gauss points, or null
   double c2ref = 1.0;             // P-wave: c^2 of the split left-hand side
   // kernel timing (measurement support)
@@ -769,9 +771,15 @@ ads_status build_launches(ads_sim* s) {
   // mass solve used by the projection: R -> R (per component, offset applied at launch)
   if (!add_ads_solve(s, s->projM_l, s->fM, s->R, s->R, s->R, 1.0, plain_epi(), err))
     return fail(ADS_ENOMEM, err);
+  // a pool holds copies of the step's jobs: they are gathered again
+  if (s->pool_dirty) *s->pool_dirty = true;
   return upload(s, s->arena.d_base, s->arena.host.data(), s->arena.host.size());
 }
 
+}  // namespace
+
+namespace {
+ads_status project_impl(ads_sim* s, const double* vals, double* coef, void* scratch);
 }  // namespace
 
 // ============================================================================
@@ -912,6 +920,16 @@ ads_status ads_project(ads_sim* s, const double* vals, double* coef, void* scrat
   size_t need = 0;
   ads_project_scratch_bytes(&s->prm, &need);
   if (scratch_bytes < need) return fail(ADS_ENOMEM, "projection scratch too small");
+  return project_impl(s, vals, coef, scratch);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The projection's contractions and mass sweeps with their two staging
+// arrays in `scratch` (ads_project_scratch_bytes of it).
+ads_status project_impl(ads_sim* s, const double* vals, double* coef, void* scratch) {
   const int q = s->q, P = s->P;
   const long long gz = (long long)s->E[2] * q, gy = (long long)s->E[1] * q, gx = (long long)s->E[0] * q;
   double* s1 = (double*)scratch;
@@ -935,6 +953,10 @@ ads_status ads_project(ads_sim* s, const double* vals, double* coef, void* scrat
   HIPCHECK(hipStreamSynchronize(s->stream));
   return ADS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 ads_status ads_set_load(ads_sim* s, const double* b, const double* amp, int32_t namp) {
   if (!s || !b || (namp > 0 && !amp)) return fail(ADS_EINVAL, "NULL argument");
@@ -1108,6 +1130,7 @@ ads_status ads_step(ads_sim* s, int32_t nsteps) {
 ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
   if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
+  if (s->pooled) return fail(ADS_ESTATE, "ads_tune on a pooled simulation (the pool fixes its launch classes)");
   if (s->elastic) {
     *chosen = 0;
     return ADS_OK;
@@ -1355,6 +1378,9 @@ void pool_build_seq(ads_pool* P, int ncu) {
 ads_status pool_rebuild(ads_pool* P) {
   std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
   P->nonempty.assign(P->seq.size(), 0);
+  // launches of each active simulation taken by some launch class: every
+  // one of them must be, or that simulation would be stepped incompletely
+  std::vector<int> taken(P->slots.size(), 0);
   for (size_t li = 0; li < P->seq.size(); ++li) {
     PoolLaunch& L = P->seq[li];
     std::vector<std::vector<char>> sel;
@@ -1369,6 +1395,7 @@ ads_status pool_rebuild(ads_pool* P) {
           (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && (l.var != L.var || l.coef != L.coef))))
         continue;
       sel.push_back(l.host_jobs);
+      taken[&sl - P->slots.data()]++;
       fixed_tz = fixed_tz || sl.sim->tz > 0;
     }
     // P-wave right-hand sides: z-chunks chosen for the whole batch on the
@@ -1449,6 +1476,14 @@ ads_status pool_rebuild(ads_pool* P) {
     P->nonempty[li] = n == 0 ? 0 : (L.kind == Launch::SWEEP ? L.w : L.kind == Launch::PLANE ? (int)L.lds : 1);
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
+  }
+  for (size_t i = 0; i < P->slots.size(); ++i) {
+    const ads_pool::Slot& sl = P->slots[i];
+    if (sl.active && taken[i] != (int)sl.sim->step_l.size()) {
+      P->dirty = true;
+      return fail(ADS_EINVAL, "pool slot " + std::to_string(i) + ": " + std::to_string(sl.sim->step_l.size() - taken[i]) +
+                                  " of its launches match no launch class of the pool");
+    }
   }
   HIPCHECK(hipMemcpyAsync(P->d_tab, P->h_tab.data(), P->tab_bytes, hipMemcpyHostToDevice, P->stream));
   HIPCHECK(hipStreamSynchronize(P->stream));
@@ -1556,6 +1591,8 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
   g_force_var = -1;
   if (st != ADS_OK) return st;
+  s->pooled = true;
+  s->pool_dirty = &P->dirty;
   P->used[found] = need;
   P->slots[free_slot] = ads_pool::Slot{s, found, need, false};
   *slot = free_slot;

@@ -31,8 +31,10 @@
 // accumulator is complete after each layer and is written.  Two barriers
 // per layer, no atomics, each output computed by one thread.  Tiles are
 // spread over the XCDs in contiguous ranges (halo re-reads hit the L2).
-// T is the type of the x- and y-passes (double, or float in mixed mode);
-// the predictor, the z-accumulation and the output are FP64.
+// T is the type of the x- and y-stiffness passes K_x w, K_y X2 and of
+// M_y X1 (double, or float in mixed mode, on differences formed in FP64);
+// the predictor, the mass channel X2 = M_x w and YK = M_y X2, the
+// z-accumulation and the output are FP64.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -48,7 +50,6 @@ struct BandGeom {
   static constexpr int SX = BTX + 2 * p, SY = BTY + 2 * p;
   static constexpr int NS = (SY * SX + BNT - 1) / BNT;    // predictor loads per thread and layer
   static constexpr int NXI = (SY * BTX + BNT - 1) / BNT;  // x-pass items per thread
-  static constexpr int LDS = SY * SX + 2 * SY * BTX;      // W [SY][SX], X1, X2 [SY][BTX]
 };
 
 __device__ __forceinline__ int find_job_band(const RhsJob* jobs, int njobs, int tile) {
@@ -87,10 +88,15 @@ template <typename T, int p>
 __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
   using Gm = BandGeom<T, p>;
   constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NXI = Gm::NXI;
-  __shared__ T smem[Gm::LDS];
-  T* Wl = smem;                 // [SY][SX]
-  T* X1 = Wl + SY * SX;         // [SY][BTX]
-  T* X2 = X1 + SY * BTX;        // [SY][BTX]
+  // The predictor and the mass channel stay FP64 in every mode: a stiffness
+  // band applied to differences of FP32-rounded values would turn their
+  // rounding (relative to the values) into an error of the stiffness action
+  // larger by about (wavelength / h)^2.  In mixed mode only the stiffness
+  // passes K_x w and K_y X2, and M_y X1, run in FP32, on differences formed
+  // in FP64.
+  __shared__ double Wl[SY * SX];   // predictor layer with halos
+  __shared__ T X1[SY * BTX];       // K_x w
+  __shared__ double X2[SY * BTX];  // M_x w
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
   const int tid = threadIdx.x, lx = tid % BTX, ly = tid / BTX;
@@ -124,7 +130,8 @@ __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rh
     const int wsplit = J.wsplit;
 
     // band rows of this thread's x-column (x-pass) and y-row (y-pass)
-    T kx[B], mx[B], ky[B], my[B];
+    T kx[B], ky[B], my[B];
+    double mx[B], myd[B];
     {
       const gmem<double>* bx = gview(band_table<p>(J.tab[0], J.E[0]));
       const gmem<double>* by = gview(band_table<p>(J.tab[1], J.E[1]));
@@ -133,9 +140,10 @@ __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rh
       const long long ix = (long long)(vx ? gx : 0) * B, iy = (long long)(vy ? gy : 0) * B;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        mx[k] = vx ? (T)bx[ix + k] : T(0);
+        mx[k] = vx ? bx[ix + k] : 0.0;
         kx[k] = vx ? (T)bx[(long long)nfx * B + ix + k] : T(0);
-        my[k] = vy ? (T)by[iy + k] : T(0);
+        myd[k] = vy ? by[iy + k] : 0.0;
+        my[k] = (T)myd[k];
         ky[k] = vy ? (T)by[(long long)nfy * B + iy + k] : T(0);
       }
     }
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rh
           const double hi = (double)bf16_round_band((float)w);
           w = wsplit == 1 ? hi : w - hi;
         }
-        if (k < SY * SX) Wl[k] = (T)w;
+        if (k < SY * SX) Wl[k] = w;
       }
     };
     auto store = [&](int o, double accv, double ldv, double rv) {
@@ -236,12 +244,13 @@ __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rh
       for (int i = 0; i < NXI; ++i) {
         const int r = ly + i * (BNT / BTX);
         if (r < SY) {
-          const T* w = Wl + r * SX + lx;
-          const T wc = w[p];
-          T a1 = kx[p] * wc, a2 = mx[0] * w[0];
+          const double* w = Wl + r * SX + lx;
+          const double wc = w[p];
+          T a1 = kx[p] * (T)wc;
+          double a2 = mx[0] * w[0];
 #pragma unroll
           for (int k = 0; k < B; ++k) {
-            if (k != p) a1 = fma(kx[k], w[k] - wc, a1);
+            if (k != p) a1 = fma(kx[k], (T)(w[k] - wc), a1);
             if (k > 0) a2 = fma(mx[k], w[k], a2);
           }
           X1[r * BTX + lx] = a1;
@@ -252,20 +261,22 @@ __global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rh
       // y-pass of the owned column, then the z-band into the accumulators
       {
         const T* c1 = X1 + ly * BTX + lx;
-        const T* c2 = X2 + ly * BTX + lx;
-        const T v2c = c2[p * BTX];
-        T ym = my[0] * c1[0], yk = my[0] * c2[0];
-        ym = fma(ky[p], v2c, ym);
+        const double* c2 = X2 + ly * BTX + lx;
+        const double v2c = c2[p * BTX];
+        T ym = my[0] * c1[0];
+        double yk = myd[0] * c2[0];
+        ym = fma(ky[p], (T)v2c, ym);
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-          const T v1 = c1[k * BTX], v2 = c2[k * BTX];
+          const T v1 = c1[k * BTX];
+          const double v2 = c2[k * BTX];
           if (k > 0) {
             ym = fma(my[k], v1, ym);
-            yk = fma(my[k], v2, yk);
+            yk = fma(myd[k], v2, yk);
           }
-          if (k != p) ym = fma(ky[k], v2 - v2c, ym);
+          if (k != p) ym = fma(ky[k], (T)(v2 - v2c), ym);
         }
-        const double dym = (double)ym, dyk = (double)yk;
+        const double dym = (double)ym, dyk = yk;
         // output o = s - p + k takes column s of its z-band rows: entry
         // (o, s) at o*(2p+1) + (s - o + p) = o*(2p+1) + 2p - k
         const long long zbb = __double_as_longlong(zbv);

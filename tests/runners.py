@@ -70,3 +70,44 @@ def gpu_sim(cfg: W.SimConfig, device="cuda", precision=None, u0_full=None):
     if cfg.load == "ricker_point":
         sim.set_point_load(W.source_point(cfg.seed), W.load_amplitudes(cfg))
     return sim, u0
+
+
+def oracle_pwave_at(cfg: W.SimConfig, steps):
+    """The oracle's P-wave run with the states (u, v, a) kept only after the
+    steps listed in ``steps`` (a 128^3 history of every step would not fit
+    comfortably in host memory).  Returns (pw, u0, {k: (u, v, a)})."""
+    from oracle import pwave
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
+    xs = [pw.quad_points(d) for d in range(3)]
+    u0 = pw.project(W.initial_values(cfg, *xs))
+    last = max(steps)
+    F = lambda k: None
+    if cfg.load == "ricker_point":
+        b = pw.point_load(W.source_point(cfg.seed))
+        amps = W.load_amplitudes(cfg, last)
+        F = lambda k: amps[k] * b
+    u, v = u0, np.zeros_like(u0)
+    a = pw.initial_accel(u0, F(0))
+    keep = {0: (u, v, a)} if 0 in steps else {}
+    for k in range(1, last + 1):
+        u, v, a = pw.step(u, v, a, F(k))
+        if k in steps:
+            keep[k] = (u, v, a)
+    return pw, u0, keep
+
+
+def oracle_elastic_at(cfg: W.SimConfig, steps):
+    """The oracle's elasticity run with (U^n, U^{n-1}) kept only after the
+    listed steps.  Returns (el, U0, {k: (U^k, U^{k-1})})."""
+    from oracle import elastic, pwave
+    el = elastic.Elastic(cfg.nelem, cfg.p, cfg.q, cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, bc=oracle_bc(cfg))
+    vals = W.initial_values(cfg, *[el.b1[d].x for d in range(3)])
+    pw = pwave.PWave(cfg.nelem, cfg.p, cfg.q, cfg.tau, bc=oracle_bc(cfg))
+    U0 = np.stack([pw.project(vals[c]) for c in range(3)])
+    keep = {}
+    Un, Unm1 = U0, el.start(U0, None)
+    for k in range(1, max(steps) + 1):
+        Un, Unm1 = el.step(Un, Unm1), Un
+        if k in steps:
+            keep[k] = (Un, Unm1)
+    return el, U0, keep

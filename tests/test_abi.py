@@ -108,3 +108,21 @@ def test_library_has_no_cpu_fallback_symbols(lib):
     from paper_1911_08158_amd import binding
     src = open(binding.__file__).read()
     assert "oracle" not in src.replace("no fallback", "")
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding refuses anything but an FP64 contiguous device tensor
+    (here: host tensors and wrong dtypes) with ValueError, and knows the
+    sizes the library will read (full layout and Gauss-point grid)."""
+    import torch
+    from paper_1911_08158_amd import binding
+    for t in (torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float32), np.zeros(8)):
+        with pytest.raises(ValueError):
+            binding._ptr(t, 8, "x")
+    assert binding._ptr(None, 8) is None
+    p = _params(nelem=(4, 5, 6), p=2)
+    assert p.full_numel == 6 * 7 * 8 and p.gauss_numel == 12 * 15 * 18
+    e = _params(problem="elastic", nelem=(4, 5, 6), p=3)
+    assert e.full_numel == 3 * 7 * 8 * 9
+    f = _params(nelem=(4, 5, 0), p=2)
+    assert f.full_numel == 6 * 7 and f.gauss_numel == 12 * 15 * 3

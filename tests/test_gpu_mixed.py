@@ -1,15 +1,16 @@
-"""Mixed-precision right-hand side (FP32 contractions or band passes, FP64
-predictor, z-accumulation, assembly, factors, sweeps and update), in both
-forms (Kronecker band passes and quadrature), against the FP64 oracle:
-relative L2 error of u reported per step; target <= 1e-6 after 100 steps on
-C3 (128^3 elements, p = 2).  The BF16-input mode (predictor rounded
-to BF16, then a correction pass on the FP64 remainder) is held to the same
-bar."""
+"""Mixed-precision right-hand side (FP32 stiffness passes on FP64
+differences or FP32 quadrature contractions; FP64 predictor, mass channel,
+z-accumulation, assembly, factors, sweeps and update), in both forms
+(Kronecker band passes and quadrature), against the FP64 oracle: relative
+L2 error of u, u' and u'' reported per step; target <= 1e-6 for u and u'
+after 100 steps on C3 (128^3 elements, p = 2).  The BF16-input mode
+(predictor rounded to BF16, then a correction pass on the FP64 remainder)
+is held to the same bars."""
 import numpy as np
 import pytest
 
 import workloads as W
-from runners import gpu_sim, oracle_pwave, rel_l2
+from runners import gpu_sim, oracle_pwave, oracle_pwave_at, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -67,22 +68,45 @@ def test_bf16_inputs_not_pooled():
     pool.close()
 
 
+def max_rel(x, ref):
+    """Largest pointwise error relative to the largest reference entry: an
+    error confined to a few lines or tiles, which a global L2 norm over 2.2 M
+    coefficients would dilute, shows here."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
 @pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
 def test_mixed_c3_error_per_step(precision):
-    """C3, 100 steps: the error against the FP64 oracle at every 10th step."""
+    """C3, 100 steps: the error of u, u' and u'' against the FP64 oracle at
+    steps 1, 10, 20, ..., 100 (relative L2 over all coefficients, and the
+    pointwise maximum relative to the largest entry).  Bars after 100 steps:
+    u and u' 1e-6 in L2 (1e-5 pointwise); u'' 1e-5 in L2 (1e-4 pointwise).
+    u'' = G^{-1}(F - K w) carries the high-frequency part of the accumulated
+    error of u amplified by the stiffness (its error grows about linearly
+    with the step count from 8e-7 at step 1), so an FP32 stiffness action
+    cannot hold it to 1e-6 over 100 steps; the measured values are printed
+    per step."""
     _cuda()
     cfg = W.C3
-    pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    marks = [1] + list(range(10, cfg.steps + 1, 10))
+    pw, u0, keep = oracle_pwave_at(cfg, set(marks))
     sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0))
     sim.factor()
     errs = []
-    for k in range(1, cfg.steps + 1):
-        sim.step(1)
-        if k % 10 == 0 or k == 1:
-            u, v, a = sim.get_state()
-            eu = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
-            ev = rel_l2(v.cpu().numpy(), pw.to_full(hist[k][1]))
-            errs.append((k, eu, ev))
-            print(f"C3 {precision} step {k}: rel L2 u {eu:.3e} v {ev:.3e}", flush=True)
+    done = 0
+    for k in marks:
+        sim.step(k - done)
+        done = k
+        st = [t.cpu().numpy() for t in sim.get_state()]
+        ref = [pw.to_full(r) for r in keep[k]]
+        e = [rel_l2(x, r) for x, r in zip(st, ref)]
+        m = [max_rel(x, r) for x, r in zip(st, ref)]
+        errs.append((k, e, m))
+        print(f"C3 {precision} step {k}: rel L2 u {e[0]:.3e} v {e[1]:.3e} a {e[2]:.3e}; "
+              f"max u {m[0]:.3e} v {m[1]:.3e} a {m[2]:.3e}", flush=True)
     sim.close()
-    assert errs[-1][1] <= 1e-6, errs
+    k, e, m = errs[-1]
+    assert max(e[0], e[1]) <= 1e-6 and e[2] <= 1e-5, errs
+    assert max(m[0], m[1]) <= 1e-5 and m[2] <= 1e-4, errs

@@ -168,3 +168,36 @@ def test_benchmark_batch_full_size():
         sim.close()
         for x, y in zip(out, ref):
             assert np.array_equal(x, y), c.init
+
+
+def test_tune_refused_for_pooled_sim_and_pool_matches_oracle():
+    """ads_tune on a pooled simulation is refused (ADS_ESTATE): the pool fixes
+    its launch classes, and a changed right-hand-side variant would match no
+    class and leave the simulation without a right-hand side.  The pooled
+    run that follows is checked against the oracle, as is a simulation whose
+    load is replaced while it is in the batch (the pool gathers its jobs
+    again)."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.binding import AdsError
+    cfg = W.C2.with_(nelem=(12, 10, 14), steps=8)
+    pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+    pool = Pool(256 << 20, max_slots=4)
+    s = pool.admit(cfg)
+    s.set_state(torch.from_numpy(np.ascontiguousarray(pw.to_full(u0_ref))).to("cuda"), None, None, 0)
+    s.set_point_load(W.source_point(cfg.seed), W.load_amplitudes(cfg))
+    s.factor()
+    with pytest.raises(AdsError) as e:
+        s.tune()
+    assert e.value.status == -4
+    pool.activate(s)
+    pool.step(4)
+    # the same load again, set while the simulation is in the batch
+    s.set_point_load(W.source_point(cfg.seed), W.load_amplitudes(cfg))
+    pool.step(cfg.steps - 4)
+    u, v, a = s.get_state()
+    for x, r in zip((u, v, a), hist[cfg.steps]):
+        assert rel_l2(x.cpu().numpy(), pw.to_full(r)) <= 1e-12
+    pool.retire(s)
+    pool.close()

@@ -294,3 +294,24 @@ def test_variable_coefficient_energy_conserved(bc):
     (_, hist) = pw.run(u0, nsteps=15, history=True)
     En = np.array([pw.energy(u, v) for (u, v, a) in hist[1:]])
     np.testing.assert_allclose(En / En[0], 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_point_load_evaluates_the_spline(p, bc):
+    """The point load b_ijk = B_i(x_s) B_j(y_s) B_k(z_s) is the functional
+    c -> u_h(x_s): for random coefficients c, b . c equals the spline
+    u_h = sum c_ijk B_i(x) B_j(y) B_k(z) evaluated at x_s by scipy's B-spline
+    evaluator.  Three different element counts and three distinct
+    coordinates, so an exchange of axes or a wrong basis fails."""
+    from scipy.interpolate import BSpline
+    pw = pwave.PWave((3, 4, 5), p, tau=0.1, bc=bc)
+    xs = [0.31, 0.52, 0.77]
+    c = np.random.default_rng(23).normal(size=pw.free_shape)
+    ref = c
+    for d in (2, 1, 0):          # contract z, then y, then x
+        B = BSpline.design_matrix(np.array([xs[d]]), pw.b1[d].knots, p).toarray()[0, pw.idx[d]]
+        ref = np.tensordot(B, ref, axes=([0], [0]))
+    b = pw.point_load(xs)
+    assert b.shape == pw.free_shape
+    np.testing.assert_allclose(np.sum(b * c), float(ref), rtol=1e-13, atol=1e-14)
