@@ -130,6 +130,19 @@ ads_status ads_project_scratch_bytes(const ads_params* prm, size_t* bytes);
 ads_status ads_project(ads_sim* sim, const double* dev_vals, double* dev_coef,
                        void* dev_scratch, size_t scratch_bytes);
 
+/* The projection above with the library's own staging memory instead of
+ * dev_scratch, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc);
+ * it allocates nothing.  The staging memory is a static device array of
+ * ADS_PROJECT_STATIC_BYTES per GPU, held until the process ends; ADS_ENOMEM
+ * (nothing enqueued) when ads_project_scratch_bytes exceeds it (e.g. meshes
+ * of 64^3 elements fit at p = 2 and 3, 128^3 does not).  Every call on one
+ * GPU uses the same array: calls that overlap on one GPU (different
+ * streams or threads) race and must be serialized by the caller.
+ * Synchronizes the simulation's stream, like ads_project. */
+#define ADS_PROJECT_STATIC_BYTES (64u << 20)
+ads_status ads_project_static(ads_sim* sim, const double* dev_vals, double* dev_coef);
+
 /* Load F(t_k) = amp[k] * b (Section 2 uses f_{n+1} in the step n -> n+1;
  * Section 5 uses f^n).  dev_b: load vector (full layout, per component);
  * host_amp[k], k = 0..namp-1, amplitude at t_k = k tau (0 beyond namp;

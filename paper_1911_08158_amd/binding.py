@@ -106,6 +106,7 @@ def load_library():
         "ads_project_scratch_bytes": [P, POINTER(c_size_t)],
         "ads_create": [P, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, POINTER(c_void_p)],
         "ads_project": [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t],
+        "ads_project_static": [c_void_p, c_void_p, c_void_p],
         "ads_set_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_set_point_load": [c_void_p, c_void_p, c_void_p, c_int32],
         "ads_factor": [c_void_p],
@@ -235,6 +236,18 @@ class Sim:
         self._pre()
         _check(L.ads_project(self._h, _ptr(vals, self.prm.gauss_numel * self.prm.comps, "vals"),
                              _ptr(out, self.prm.full_numel, "out"), scratch.data_ptr(), n.value))
+        self._post()
+        return out
+
+    def project_static(self, vals):
+        """The projection through ads_project_static (the library's static
+        staging memory; nothing allocated by the library)."""
+        import torch
+        out = self._empty_full()
+        vals = vals.to(self.device, torch.float64).contiguous()
+        self._pre()
+        _check(load_library().ads_project_static(self._h, _ptr(vals, self.prm.gauss_numel * self.prm.comps, "vals"),
+                                                 _ptr(out, self.prm.full_numel, "out")))
         self._post()
         return out
 

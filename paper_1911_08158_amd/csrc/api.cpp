@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,13 @@
 #include "launch.hpp"
 
 using namespace ads;
+
+// Staging memory of ads_project_static: a file-scope device array, so that
+// that entry point allocates nothing.  Each device holds its own copy; host
+// code uses the address hipGetSymbolAddress returns for the current device
+// (static_scratch_address below), never the array's name, which on the host
+// is not a device address.  Every call on a device shares its copy.
+static __device__ __align__(256) char scratch[(size_t)ADS_PROJECT_STATIC_BYTES];
 
 namespace {
 
@@ -41,6 +49,29 @@ ads_status fail(ads_status s, const std::string& msg) {
 hipError_t set_attributes_once() {
   static const hipError_t e = sweep_set_attributes();
   return e;
+}
+
+constexpr size_t kStaticScratchBytes = (size_t)ADS_PROJECT_STATIC_BYTES;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+ads_status static_scratch_address(void** out) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ADS_EDEVICE, "device index beyond the static-buffer table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ADS_EDEVICE, "hipGetSymbolAddress returned NULL for the static buffer");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return ADS_OK;
 }
 
 constexpr int kAmpCap = 4096;
@@ -921,6 +952,19 @@ ads_status ads_project(ads_sim* s, const double* vals, double* coef, void* scrat
   ads_project_scratch_bytes(&s->prm, &need);
   if (scratch_bytes < need) return fail(ADS_ENOMEM, "projection scratch too small");
   return project_impl(s, vals, coef, scratch);
+}
+
+ads_status ads_project_static(ads_sim* s, const double* vals, double* coef) {
+  if (!s || !vals || !coef) return fail(ADS_EINVAL, "NULL argument");
+  size_t need = 0;
+  ads_project_scratch_bytes(&s->prm, &need);
+  if (need > kStaticScratchBytes)
+    return fail(ADS_ENOMEM, "projection staging of " + std::to_string(need) + " bytes exceeds the " +
+                                std::to_string(kStaticScratchBytes) + "-byte static buffer (use ads_project)");
+  void* buf = nullptr;
+  ads_status st = static_scratch_address(&buf);
+  if (st != ADS_OK) return st;
+  return project_impl(s, vals, coef, buf);
 }
 
 }  // extern "C"
