@@ -57,15 +57,17 @@ typedef enum {
 typedef enum { ADS_PWAVE = 0, ADS_ELASTIC = 1 } ads_problem;
 
 /* Arithmetic of the right-hand side.  Without a wave-speed field it is the
- * Kronecker form of eq. pwave2 (assembled 1D band matrices, three band
- * passes, HBM-bound; the default); with one, the sum-factorized Gauss
- * quadrature.  The mixed modes run the x- and y-passes (the quadrature's
- * contractions) in FP32, the z-accumulation in FP64.  Sweeps, factors and
- * the time update are FP64 in every mode.  ADS_MIXED_BF16 contracts the
- * predictor rounded to BF16 (the inputs a BF16 matrix unit would take; the
- * basis tables stay FP32), then a second pass contracts the FP64 remainder
- * and adds it (one correction step), FP32 arithmetic in both: two
- * right-hand-side launches per step, P-wave only, not accepted by pools. */
+ * Kronecker form of the stiffness (P-wave: eq. pwave2; elasticity: the
+ * blocks of Upsilon, Section 5) over assembled 1D band matrices, three
+ * band passes, HBM-bound (the default); with a field (P-wave), or when
+ * ads_tune picks it, the sum-factorized Gauss quadrature.  In the Kronecker
+ * form the mixed modes run the passes with stiffness-type bands (K, G, G^T)
+ * in FP32 on differences formed in FP64; the mass passes, the
+ * z-accumulation and the assembly stay FP64.  Sweeps, factors and the time
+ * update are FP64 in every mode.  ADS_MIXED_BF16 (P-wave only, not
+ * accepted by pools) contracts the predictor rounded to BF16, then a second
+ * pass contracts the FP64 remainder and adds it (one correction step),
+ * FP32 arithmetic in both: two right-hand-side launches per step. */
 typedef enum {
   ADS_FP64 = 0,        /* FP64 band passes / sum-factorized quadrature       */
   ADS_MIXED_FP32 = 1,  /* FP32 contractions, FP64 combination and assembly   */
@@ -201,17 +203,18 @@ ads_status ads_energy(ads_sim* sim, double* host_energy);
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 
-/* Autotuner of the right-hand side (measurement-driven, P-wave): times
- * every variant on this mesh (HIP events, a few launches each;
- * synchronizes): 0-2 are tile shapes of the quadrature kernel, 3 is the
- * Kronecker form (the default; not offered with a wave-speed field), keeps
- * the fastest and caches the choice per (degree, precision, field or none,
- * mesh) for later simulations in the process.  *chosen receives the variant
- * index, host_ms (may be NULL, up to cap entries) the mean ms per variant.
- * Call after ads_factor.  The environment variable ADS_RHS_VAR (0-3) sets the variant
- * of a new simulation, ADS_POOL_RHS_VAR that of a new pool's launches.
- * Elasticity: no variants, returns ADS_OK with *chosen = 0.  ADS_ESTATE for
- * a simulation owned by a pool (the pool fixes the launch classes). */
+/* Autotuner of the right-hand side (measurement-driven): times every
+ * variant on this mesh (HIP events, a few launches each; synchronizes) and
+ * keeps the fastest.  P-wave: 0-2 are tile shapes of the quadrature kernel,
+ * 3 is the Kronecker form (the default; not offered with a wave-speed
+ * field).  Elasticity: 0 is the quadrature (FP64), 3 the Kronecker form
+ * (the default).  The choice is cached per (problem, degree, precision,
+ * field or none, mesh) for later simulations in the process.  *chosen
+ * receives the variant index, host_ms[v] (may be NULL; entries v < cap) the
+ * mean ms of variant v.  Call after ads_factor.  The environment variable
+ * ADS_RHS_VAR (0-3) sets the variant of a new simulation, ADS_POOL_RHS_VAR
+ * that of a new pool's P-wave launches.  ADS_ESTATE for a simulation owned
+ * by a pool (the pool fixes the launch classes). */
 ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);
 
 /* Copy the state out (full layout; asynchronous on the sim's stream).

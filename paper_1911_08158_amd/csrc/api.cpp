@@ -249,8 +249,8 @@ bool valid_params(const ads_params* prm, std::string& why) {
     why = "precision must be ADS_FP64, ADS_MIXED_FP32 or ADS_MIXED_BF16";
     return false;
   }
-  if (prm->precision != ADS_FP64 && prm->problem != ADS_PWAVE) {
-    why = "mixed precision is implemented for the P-wave only";
+  if (prm->precision == ADS_MIXED_BF16 && prm->problem != ADS_PWAVE) {
+    why = "the BF16-input mode is implemented for the P-wave only (elasticity: ADS_FP64 or ADS_MIXED_FP32)";
     return false;
   }
   if (prm->problem == ADS_ELASTIC) {
@@ -293,9 +293,10 @@ void carve(ads_sim* s, Carver& c) {
   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P], then the
   // element mass and stiffness matrices sum_g W N N^T, sum_g W D D^T [E][P][P],
   // then the assembled matrices M, K of the free coefficients [nf][2p+1]
+  // (elasticity: then G and G^T of the free coefficients [nf][2p+1])
   for (int d = 0; d < 3; ++d)
     s->d_tab[d] = c.dbl((size_t)4 * s->E[d] * q * P + (size_t)s->E[d] * q + (size_t)2 * s->E[d] * P * P +
-                        (size_t)2 * s->nf[d] * (2 * p + 1));
+                        (size_t)(s->elastic ? 4 : 2) * s->nf[d] * (2 * p + 1));
   auto fac = [&](DevFactor& f, int d) {
     f.m = s->nf[d];
     f.L = c.dbl((size_t)f.m * p);
@@ -521,7 +522,9 @@ RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_
   return J;
 }
 
-RhsJob rhs_elastic_job(const ads_sim* s) {
+// Elasticity right-hand side: variant 3 is the Kronecker form (band passes,
+// FP64 or mixed), variant 0 the sum-factorized quadrature (FP64).
+RhsJob rhs_elastic_job(const ads_sim* s, int var, int mixed) {
   RhsJob J{};
   J.u = s->u;
   J.cu = 1.0;
@@ -536,7 +539,11 @@ RhsJob rhs_elastic_job(const ads_sim* s) {
   J.lam = s->prm.lambda;
   J.mu = s->prm.mu;
   fill_tables(s, J);
-  rhs_tiles(s, J, rhs_el_tile_x(s->p), rhs_el_tile_y(s->p));
+  if (var == 3)
+    rhs_tiles(s, J, rhs_el_band_tile_x(), rhs_el_band_tile_y(s->p),
+              (long long)rhs_el_band_blocks_per_cu(s->p, mixed) * s->ncu, 2 * s->p);
+  else
+    rhs_tiles(s, J, rhs_el_tile_x(s->p), rhs_el_tile_y(s->p));
   return J;
 }
 
@@ -649,7 +656,8 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
         e = launch_rhs_pwave(l.p, l.mixed, l.var, l.coef, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::RHS_E:
-        e = launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
+        e = l.var == 3 ? launch_rhs_elastic_band(l.p, l.mixed, l.d_hdr, grid_of(l, grid_cap), s->stream)
+                       : launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::SWEEP:
         e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.w, l.max_m, s->stream);
@@ -763,12 +771,17 @@ ads_status build_launches(ads_sim* s) {
     if (!add_ads_solve(s, s->start_l, s->fS, s->R, s->R, s->a, 1.0, plain_epi(), err))
       return fail(ADS_ENOMEM, err);
   } else {
-    RhsJob rj = rhs_elastic_job(s);
+    // step: the chosen variant and precision; start and energy in FP64
+    const int mx = (s->mixed && s->rhs_var == 3) ? 1 : 0;
+    RhsJob rj = rhs_elastic_job(s, s->rhs_var, mx);
     const LaunchHdr* d = s->arena.add(std::vector<RhsJob>{rj}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    s->step_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, 0, 0, as_bytes(rj)});
+    s->step_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, s->rhs_var, mx, as_bytes(rj)});
     if (!add_at_solve(s, s->step_l, true, true, err)) return fail(ADS_ENOMEM, err);
-    s->start_l.push_back(Launch{Launch::RHS_E, d, 1, rj.ntiles, 0, s->p, -1, 0, 0, as_bytes(rj)});
+    RhsJob r0 = rhs_elastic_job(s, s->rhs_var, 0);
+    d = s->arena.add(std::vector<RhsJob>{r0}, err);
+    if (!d) return fail(ADS_ENOMEM, err);
+    s->start_l.push_back(Launch{Launch::RHS_E, d, 1, r0.ntiles, 0, s->p, -1, s->rhs_var, 0, as_bytes(r0)});
     if (!add_at_solve(s, s->start_l, false, false, err)) return fail(ADS_ENOMEM, err);
     // energy diagnostic (V = (U^{n+1} - U^n)/tau in Y, W = (U^{n+1} + U^n)/2 in Z):
     // R = Upsilon W, R = Upsilon V (quadrature), R = L^T V (split diagonal and
@@ -776,14 +789,14 @@ ads_status build_launches(ads_sim* s) {
     const long long nf = s->nfree;
     const double tau = s->prm.tau, rho = s->prm.rho, h = 0.5 * tau * tau;
     for (double* src : {s->Z, s->Y}) {
-      RhsJob ke = rhs_elastic_job(s);
+      RhsJob ke = rhs_elastic_job(s, s->rhs_var, 0);
       ke.u = src;
       ke.load = nullptr;
       ke.amp = nullptr;
       ke.rscale = -1.0;
       d = s->arena.add(std::vector<RhsJob>{ke}, err);
       if (!d) return fail(ADS_ENOMEM, err);
-      s->energy_l.push_back(Launch{Launch::RHS_E, d, 1, ke.ntiles, 0, s->p, -1, 0, 0, as_bytes(ke)});
+      s->energy_l.push_back(Launch{Launch::RHS_E, d, 1, ke.ntiles, 0, s->p, -1, s->rhs_var, 0, as_bytes(ke)});
     }
     for (int i = 0; i < 3; ++i) {
       KronJob K = kron_base(s, s->R + i * nf, nullptr, 0.0);
@@ -874,6 +887,7 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
   if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(3, std::atoi(e)));
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
+  if (s->elastic && s->rhs_var != 3) s->rhs_var = 0;  // elasticity: quadrature (0) or Kronecker form (3)
   Carver c{(char*)ws};
   carve(s, c);
   // host tables and matrices
@@ -904,19 +918,27 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
             }
             buf.push_back(m);
           }
-    // band matrices of the Kronecker form: M, then K; in x and y the
-    // diagonal slot of K holds the row sum (the x- and y-passes apply K to
-    // differences to the diagonal, so that FP32-rounded entries still
-    // annihilate constants); z keeps K itself (its pass is FP64)
+    // band matrices of the Kronecker form: M, then K (elasticity: then G
+    // and G^T); in x and y the diagonal slot of K, G and G^T holds the row
+    // sum (the x- and y-passes apply them to differences to the diagonal,
+    // so that FP32-rounded entries still annihilate constants); z keeps the
+    // matrices themselves (its pass is FP64)
     buf.insert(buf.end(), s->Mf[d].a.begin(), s->Mf[d].a.end());
-    {
-      const Band& K = s->Kf[d];
+    auto push_diff_band = [&](const Band& K) {
       const int B = 2 * K.p + 1;
       for (int i = 0; i < K.n; ++i) {
         double rs = 0.0;
         for (int k = 0; k < B; ++k) rs += K.a[(size_t)i * B + k];
         for (int k = 0; k < B; ++k) buf.push_back(k == K.p && d < 2 ? rs : K.a[(size_t)i * B + k]);
       }
+    };
+    push_diff_band(s->Kf[d]);
+    if (s->elastic) {
+      Band GT = s->Gf[d];
+      for (int i = 0; i < GT.n; ++i)
+        for (int j = std::max(0, i - GT.p); j <= std::min(GT.n - 1, i + GT.p); ++j) GT.at(i, j) = s->Gf[d].at(j, i);
+      push_diff_band(s->Gf[d]);
+      push_diff_band(GT);
     }
     if ((st = upload(s, s->d_tab[d], buf.data(), buf.size() * 8)) != ADS_OK) return st;
     if ((st = upload_factor(s, s->fM[d], s->Mf[d])) != ADS_OK) return st;
@@ -1175,17 +1197,18 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
   if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
   if (s->pooled) return fail(ADS_ESTATE, "ads_tune on a pooled simulation (the pool fixes its launch classes)");
-  if (s->elastic) {
-    *chosen = 0;
-    return ADS_OK;
-  }
   static std::map<std::string, int> cache;
   // the wave-speed field is part of the key: without one the Kronecker form
   // is a candidate, with one it is not
-  const std::string key = std::to_string(s->p) + "/" + std::to_string(s->mixed) + "/" +
-                          std::to_string(s->coef != nullptr) + "/" + std::to_string(s->nf[0]) +
-                          "x" + std::to_string(s->nf[1]) + "x" + std::to_string(s->nf[2]);
-  const int nv = rhs_num_variants(s->p, s->coef != nullptr);
+  const std::string key = std::string(s->elastic ? "E" : "P") + std::to_string(s->p) + "/" +
+                          std::to_string(s->mixed) + "/" + std::to_string(s->coef != nullptr) + "/" +
+                          std::to_string(s->nf[0]) + "x" + std::to_string(s->nf[1]) + "x" + std::to_string(s->nf[2]);
+  // candidates: P-wave tile variants 0-2 of the quadrature and the Kronecker
+  // form 3 (without a wave-speed field); elasticity quadrature 0 and 3
+  std::vector<int> cands;
+  if (s->elastic) cands = {0, 3};
+  else
+    for (int v = 0; v < rhs_num_variants(s->p, s->coef != nullptr); ++v) cands.push_back(v);
   int best = -1;
   auto it = cache.find(key);
   if (it != cache.end()) {
@@ -1195,7 +1218,7 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     double best_ms = 1e30;
-    for (int v = 0; v < nv; ++v) {
+    for (int v : cands) {
       s->rhs_var = v;
       ads_status st = build_launches(s);
       if (st != ADS_OK) return st;
@@ -1409,7 +1432,9 @@ void pool_build_seq(ads_pool* P, int ncu) {
         int var = rhs_form_var(P->var[p - 2][mixed], coef != 0);
         add(Launch::RHS_P, p, mixed, var, coef, 0, rhs_blocks_per_cu(p, mixed, var, coef) * ncu, sizeof(RhsJob));
       }
-  for (int p = 2; p <= 3; ++p) add(Launch::RHS_E, p, 0, 0, 0, 0, 2 * ncu, sizeof(RhsJob));
+  for (int p = 2; p <= 3; ++p)
+    for (int mixed = 0; mixed <= 1; ++mixed)
+      add(Launch::RHS_E, p, mixed, 3, 0, 0, rhs_el_band_blocks_per_cu(p, mixed) * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
     if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
     else if (is_plane_stage(k)) add(Launch::PLANE, 0, 0, 0, 0, k, ncu, sizeof(PlaneJob));
@@ -1435,8 +1460,8 @@ ads_status pool_rebuild(ads_pool* P) {
       if ((int)st.size() <= L.stage) continue;
       const Launch& l = st[L.stage];
       if (l.kind != L.kind) continue;
-      if (L.stage == 0 &&
-          (l.p != L.p || l.mixed != L.mixed || (l.kind == Launch::RHS_P && (l.var != L.var || l.coef != L.coef))))
+      if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || l.var != L.var ||
+                           (l.kind == Launch::RHS_P && l.coef != L.coef)))
         continue;
       sel.push_back(l.host_jobs);
       taken[&sl - P->slots.data()]++;
@@ -1444,7 +1469,7 @@ ads_status pool_rebuild(ads_pool* P) {
     }
     // P-wave right-hand sides: z-chunks chosen for the whole batch on the
     // persistent grid of this launch
-    if (L.kind == Launch::RHS_P && !sel.empty() && !fixed_tz) {
+    if ((L.kind == Launch::RHS_P || L.kind == Launch::RHS_E) && !sel.empty() && !fixed_tz) {
       std::vector<std::pair<long long, int>> xy_nfz;
       for (const auto& j : sel) {
         const RhsJob* r = (const RhsJob*)j.data();
@@ -1547,7 +1572,7 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
     hipError_t e = hipSuccess;
     switch (L.kind) {
       case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); break;
-      case Launch::RHS_E: e = launch_rhs_elastic(L.p, h, L.grid, P->stream); break;
+      case Launch::RHS_E: e = launch_rhs_elastic_band(L.p, L.mixed, h, L.grid, P->stream); break;
       case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, P->stream); break;
       case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;
       case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, P->stream); break;
@@ -1631,7 +1656,8 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   if (found == (size_t)-1 && cur + need <= P->bytes) found = cur;
   if (found == (size_t)-1) return fail(ADS_ENOMEM, "not enough free pool memory");
   ads_sim* s = nullptr;
-  g_force_var = P->var[prm->p - 2][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
+  // elasticity takes the Kronecker form in every pool
+  g_force_var = prm->problem == ADS_ELASTIC ? 3 : P->var[prm->p - 2][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
   ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
   g_force_var = -1;
   if (st != ADS_OK) return st;

@@ -37,6 +37,12 @@ hipError_t launch_rhs_band(int p, int mixed, const LaunchHdr* d_hdr, int grid, h
 int rhs_el_tile_x(int p);
 int rhs_el_tile_y(int p);
 hipError_t launch_rhs_elastic(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s);
+// Elasticity right-hand side in the Kronecker form (band passes; FP64, or
+// FP32 stiffness-type passes with mixed = 1)
+int rhs_el_band_tile_x();
+int rhs_el_band_tile_y(int p);
+int rhs_el_band_blocks_per_cu(int p, int mixed);
+hipError_t launch_rhs_elastic_band(int p, int mixed, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 
 hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s);
 int kron_tile_x();

@@ -23,6 +23,7 @@ MIX = [
     W.C1.with_(nelem=(24, 16, 20), tau=0.005, precision="mixed_fp32"),
     W.C4.with_(nelem=(9, 8, 10), tau=0.01),
     W.C4.with_(nelem=(6, 7, 5), p=3, q=4, tau=0.02, lam=2.0, mu=0.5),
+    W.C4.with_(nelem=(11, 7, 9), tau=0.01, precision="mixed_fp32"),
     W.C2.with_(nelem=(16, 18, 14), steps=100),           # P-wave p=3 with a point source
 ]
 
