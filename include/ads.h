@@ -95,7 +95,8 @@ typedef enum { ADS_BC_DIRICHLET0 = 0, ADS_BC_NATURAL = 1 } ads_bc;
 typedef struct {
   int32_t problem;     /* ads_problem   */
   int32_t nelem[3];    /* >= 1 each; nelem[2] = 0: two-dimensional P-wave */
-  int32_t p;           /* 2 or 3        */
+  int32_t p;           /* 1 to 5 (the quadrature right-hand side, and with
+                          it a wave-speed field, needs 2 or 3)          */
   int32_t nquad;       /* 0 or p+1      */
   int32_t bc;          /* ads_bc        */
   int32_t precision;   /* ads_precision */
@@ -171,7 +172,8 @@ ads_status ads_factor(ads_sim* sim);
  * preconditioned Newmark step; with c2ref >= max c^2 the discrete energy of
  * ads_energy stays conserved.  The library keeps the pointer: the caller
  * keeps the array alive and unchanged until ads_destroy.  ADS_EINVAL for
- * elasticity or c2ref <= 0, ADS_ESTATE after ads_factor. */
+ * elasticity, a degree other than 2 or 3 (the quadrature kernels are
+ * instantiated for those) or c2ref <= 0, ADS_ESTATE after ads_factor. */
 ads_status ads_set_coefficient(ads_sim* sim, const double* dev_c2, double c2ref);
 
 /* Time-stepping coefficient set of the P-wave (before ads_factor; default
@@ -261,7 +263,7 @@ const char* ads_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Batched pool (serving form; not a construct of the paper).  Many
- * simulations of different meshes, degrees (2, 3), problems and precisions
+ * simulations of different meshes, degrees (1 to 5), problems and precisions
  * live in one caller workspace and advance together: every pool step runs
  * ONE launch per kernel class and stage for all active simulations
  * (persistent kernels over device job tables), replayed from a hipGraph

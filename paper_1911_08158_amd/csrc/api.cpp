@@ -47,7 +47,10 @@ ads_status fail(ads_status s, const std::string& msg) {
 // Kernel attributes (dynamic LDS above the default) are set once per
 // process; the static's initialization is thread-safe.
 hipError_t set_attributes_once() {
-  static const hipError_t e = sweep_set_attributes();
+  static const hipError_t e = [] {
+    const hipError_t a = sweep_set_attributes();
+    return a != hipSuccess ? a : kron_set_attributes();
+  }();
   return e;
 }
 
@@ -229,8 +232,8 @@ bool valid_params(const ads_params* prm, std::string& why) {
       return false;
     }
   }
-  if (prm->p != 2 && prm->p != 3) {
-    why = "spline degree p must be 2 or 3";
+  if (prm->p < 1 || prm->p > 5) {
+    why = "spline degree p must be in [1, 5]";
     return false;
   }
   if (prm->nquad != 0 && prm->nquad != prm->p + 1) {
@@ -356,7 +359,7 @@ SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* 
   J.ny = s->nf[1];
   J.nz = s->nf[2];
   J.nlines = (int)(s->nfree / s->nf[dir]);
-  J.ntiles = sweep_groups(J.nlines, sweep_width_for(J.nlines, max_m(s), s->ncu));
+  J.ntiles = sweep_groups(J.nlines, sweep_width_for(J.nlines, max_m(s), s->ncu, s->p));
   J.tile0 = 0;
   J.epi = EPI_STORE;
   J.scale = scale;
@@ -409,7 +412,7 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
     const LaunchHdr* d = s->arena.add(std::vector<SweepJob>{*j}, err);
     if (!d) return false;
     L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir, 0, 0, as_bytes(*j)});
-    L.back().w = sweep_width_for(j->nlines, max_m(s), s->ncu);
+    L.back().w = sweep_width_for(j->nlines, max_m(s), s->ncu, s->p);
   }
   return true;
 }
@@ -498,6 +501,14 @@ void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident =
 // jobs with one take the quadrature kernel's variant 0 instead.
 int rhs_form_var(int var, bool coef) { return (coef && var == 3) ? 0 : var; }
 
+// The quadrature kernels (P-wave tile variants 0-2, elasticity variant 0)
+// are instantiated for p = 2 and 3; every degree has the Kronecker form.
+bool quadrature_ok(int p) { return p == 2 || p == 3; }
+// Variant of an FP64 right-hand side used by the start and the energy
+// diagnostic: the quadrature's variant 0 where it exists, else the
+// Kronecker form.
+int fp64_aux_var(const ads_sim* s) { return quadrature_ok(s->p) ? 0 : 3; }
+
 RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift, int mixed, int var) {
   RhsJob J{};
   J.u = s->u;
@@ -562,7 +573,7 @@ KronJob kron_base(const ads_sim* s, double* out, const double* base, double alph
   K.tiles[1] = (K.ny + kron_tile_y() - 1) / kron_tile_y();
   // a tile walks TZ + 2p source layers
   set_kron_zchunks(K, best_zchunks({{(long long)K.tiles[0] * K.tiles[1], K.nz}}, 2 * K.p,
-                                   (long long)kron_blocks_per_cu() * s->ncu));
+                                   (long long)kron_blocks_per_cu(s->p) * s->ncu));
   return K;
 }
 
@@ -660,13 +671,13 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
                        : launch_rhs_elastic(l.p, l.d_hdr, grid_of(l, grid_cap), s->stream);
         break;
       case Launch::SWEEP:
-        e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.w, l.max_m, s->stream);
+        e = launch_sweeps(l.d_hdr, grid_of(l, grid_cap), l.w, l.max_m, l.p, s->stream);
         break;
       case Launch::KRON:
-        e = launch_kron(l.d_hdr, grid_of(l, grid_cap), s->stream);
+        e = launch_kron(l.d_hdr, grid_of(l, grid_cap), l.p, s->stream);
         break;
       case Launch::PLANE:
-        e = launch_planes(l.d_hdr, grid_of(l, grid_cap), l.lds, s->stream);
+        e = launch_planes(l.d_hdr, grid_of(l, grid_cap), l.lds, l.p, s->stream);
         break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -741,22 +752,23 @@ ads_status build_launches(ads_sim* s) {
     z.counter = s->counter;
     if (!add_ads_solve(s, s->step_l, s->fS, s->R, s->R, nullptr, 1.0, z, err)) return fail(ADS_ENOMEM, err);
     // start: u''_0 = G^{-1}(F_0 - K u_0)
-    // the start is computed in FP64 (tile variant 0) in every precision mode
-    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, 0);
+    // the start is computed in FP64 in every precision mode
+    const int av = rhs_form_var(fp64_aux_var(s), s->coef != nullptr);
+    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, av);
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
-    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, 0, 0, as_bytes(r0)});
+    s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, av, 0, as_bytes(r0)});
     s->start_l.back().coef = s->coef != nullptr;
     // energy diagnostic: R = K u, R = K v (FP64 quadrature), R = G v (split operator)
     for (double* src : {s->u, s->v}) {
-      RhsJob ke = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, 0);
+      RhsJob ke = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, av);
       ke.u = src;
       ke.load = nullptr;
       ke.amp = nullptr;
       ke.rscale = -1.0;
       d = s->arena.add(std::vector<RhsJob>{ke}, err);
       if (!d) return fail(ADS_ENOMEM, err);
-      s->energy_l.push_back(Launch{Launch::RHS_P, d, 1, ke.ntiles, 0, s->p, -1, 0, 0, as_bytes(ke)});
+      s->energy_l.push_back(Launch{Launch::RHS_P, d, 1, ke.ntiles, 0, s->p, -1, av, 0, as_bytes(ke)});
       s->energy_l.back().coef = s->coef != nullptr;
     }
     {
@@ -888,6 +900,7 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(3, std::atoi(e)));
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
   if (s->elastic && s->rhs_var != 3) s->rhs_var = 0;  // elasticity: quadrature (0) or Kronecker form (3)
+  if (!quadrature_ok(s->p)) s->rhs_var = 3;            // degrees without a quadrature kernel
   Carver c{(char*)ws};
   carve(s, c);
   // host tables and matrices
@@ -1120,6 +1133,8 @@ ads_status ads_energy(ads_sim* s, double* host_energy) {
 ads_status ads_set_coefficient(ads_sim* s, const double* dev_c2, double c2ref) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   if (s->elastic) return fail(ADS_EINVAL, "the wave-speed field is a P-wave parameter");
+  if (!quadrature_ok(s->p))
+    return fail(ADS_EINVAL, "a wave-speed field needs the quadrature right-hand side (p = 2 or 3)");
   if (!(c2ref > 0.0) || !std::isfinite(c2ref)) return fail(ADS_EINVAL, "c2ref must be positive and finite");
   if (s->factored) return fail(ADS_ESTATE, "ads_set_coefficient after ads_factor");
   s->coef = dev_c2;
@@ -1206,7 +1221,8 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   // candidates: P-wave tile variants 0-2 of the quadrature and the Kronecker
   // form 3 (without a wave-speed field); elasticity quadrature 0 and 3
   std::vector<int> cands;
-  if (s->elastic) cands = {0, 3};
+  if (!quadrature_ok(s->p)) cands = {3};
+  else if (s->elastic) cands = {0, 3};
   else
     for (int v = 0; v < rhs_num_variants(s->p, s->coef != nullptr); ++v) cands.push_back(v);
   int best = -1;
@@ -1399,7 +1415,7 @@ struct ads_pool {
   // right-hand-side variant per [p-2][mixed]: the Kronecker form, bound by
   // HBM (launches of simulations with a wave-speed field take the
   // quadrature kernel's 14/13-row tiles, variant 0)
-  int var[2][2] = {{3, 3}, {3, 3}};
+  int var[kMaxP][2] = {{3, 3}, {3, 3}, {3, 3}, {3, 3}, {3, 3}};
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;
@@ -1426,19 +1442,22 @@ void pool_build_seq(ads_pool* P, int ncu) {
     off += (L.cap + kAlign - 1) / kAlign * kAlign;
     P->seq.push_back(L);
   };
-  for (int p = 2; p <= 3; ++p)
+  // right-hand-side classes: P-wave per degree, precision and wave-speed
+  // field (fields only where the quadrature exists), elasticity per degree
+  // and precision (Kronecker form)
+  for (int p = 1; p <= kMaxP; ++p)
     for (int mixed = 0; mixed <= 1; ++mixed)
-      for (int coef = 0; coef <= 1; ++coef) {
-        int var = rhs_form_var(P->var[p - 2][mixed], coef != 0);
+      for (int coef = 0; coef <= (quadrature_ok(p) ? 1 : 0); ++coef) {
+        int var = rhs_form_var(quadrature_ok(p) ? P->var[p - 1][mixed] : 3, coef != 0);
         add(Launch::RHS_P, p, mixed, var, coef, 0, rhs_blocks_per_cu(p, mixed, var, coef) * ncu, sizeof(RhsJob));
       }
-  for (int p = 2; p <= 3; ++p)
+  for (int p = 1; p <= kMaxP; ++p)
     for (int mixed = 0; mixed <= 1; ++mixed)
       add(Launch::RHS_E, p, mixed, 3, 0, 0, rhs_el_band_blocks_per_cu(p, mixed) * ncu, sizeof(RhsJob));
   for (int k = 1; k <= kPoolStages; ++k) {
-    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, 0, k, kron_blocks_per_cu() * ncu, sizeof(KronJob));
+    if (is_kron_stage(k)) add(Launch::KRON, 0, 0, 0, 0, k, kron_blocks_per_cu(kMaxP) * ncu, sizeof(KronJob));
     else if (is_plane_stage(k)) add(Launch::PLANE, 0, 0, 0, 0, k, ncu, sizeof(PlaneJob));
-    else add(Launch::SWEEP, 0, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM) * ncu, sizeof(SweepJob));
+    else add(Launch::SWEEP, 0, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM, kMaxP) * ncu, sizeof(SweepJob));
   }
   P->tab_bytes = off;
 }
@@ -1482,32 +1501,41 @@ ads_status pool_rebuild(ads_pool* P) {
       }
     }
     // couplings: z-chunks chosen for the whole batch on the persistent grid
+    // (the launch's LDS and instantiation follow the largest degree)
     if (L.kind == Launch::KRON && !sel.empty()) {
       std::vector<std::pair<long long, int>> xy_nfz;
-      int pmax = 2;
+      int pmax = 1;
       for (const auto& j : sel) {
         const KronJob* r = (const KronJob*)j.data();
         xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nz});
         pmax = std::max(pmax, r->p);
       }
+      L.p = pmax;
+      L.grid = kron_blocks_per_cu(pmax) * P->ncu;
       const int k = best_zchunks(xy_nfz, 2 * pmax, L.grid);
       for (auto& j : sel) set_kron_zchunks(*(KronJob*)j.data(), k);
     }
     // in-plane sweeps: LDS of the largest plane, persistent grid for it
     if (L.kind == Launch::PLANE && !sel.empty()) {
       L.lds = 0;
+      L.p = 1;
       for (const auto& j : sel) {
         const PlaneJob* r = (const PlaneJob*)j.data();
         L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p));
+        L.p = std::max(L.p, r->p);
       }
-      L.grid = plane_blocks_per_cu(L.lds) * P->ncu;
+      L.grid = plane_blocks_per_cu(L.lds, L.p) * P->ncu;
     }
     // sweeps: tile width and persistent grid for the batch's line count
     if (L.kind == Launch::SWEEP && !sel.empty()) {
       long long lines = 0;
-      for (const auto& j : sel) lines += ((const SweepJob*)j.data())->nlines;
-      L.w = sweep_width_for(lines, kPoolMaxM, P->ncu);
-      L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM) * P->ncu;
+      L.p = 1;
+      for (const auto& j : sel) {
+        lines += ((const SweepJob*)j.data())->nlines;
+        L.p = std::max(L.p, ((const SweepJob*)j.data())->p);
+      }
+      L.w = sweep_width_for(lines, kPoolMaxM, P->ncu, L.p);
+      L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM, L.p) * P->ncu;
       for (auto& j : sel) {
         SweepJob* r = (SweepJob*)j.data();
         r->ntiles = sweep_groups(r->nlines, L.w);
@@ -1540,9 +1568,12 @@ ads_status pool_rebuild(ads_pool* P) {
     LaunchHdr h{};
     h.njobs = n;
     h.total_tiles = total;
-    // launch shape (a captured graph holds it): sweep tile width, or the
-    // in-plane LDS size
-    P->nonempty[li] = n == 0 ? 0 : (L.kind == Launch::SWEEP ? L.w : L.kind == Launch::PLANE ? (int)L.lds : 1);
+    // launch shape (a captured graph holds it): sweep tile width, in-plane
+    // LDS size, and the largest degree (instantiation and factor rows)
+    P->nonempty[li] = n == 0 ? 0
+                             : (L.kind == Launch::SWEEP ? L.w * 8 + L.p
+                                : L.kind == Launch::PLANE ? (int)L.lds * 8 + L.p
+                                : L.kind == Launch::KRON ? L.p : 1);
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
@@ -1573,9 +1604,9 @@ ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
     switch (L.kind) {
       case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); break;
       case Launch::RHS_E: e = launch_rhs_elastic_band(L.p, L.mixed, h, L.grid, P->stream); break;
-      case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, P->stream); break;
-      case Launch::KRON: e = launch_kron(h, L.grid, P->stream); break;
-      case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, P->stream); break;
+      case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, L.p, P->stream); break;
+      case Launch::KRON: e = launch_kron(h, L.grid, L.p, P->stream); break;
+      case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, L.p, P->stream); break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
     if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
@@ -1657,7 +1688,8 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   if (found == (size_t)-1) return fail(ADS_ENOMEM, "not enough free pool memory");
   ads_sim* s = nullptr;
   // elasticity takes the Kronecker form in every pool
-  g_force_var = prm->problem == ADS_ELASTIC ? 3 : P->var[prm->p - 2][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
+  g_force_var = (prm->problem == ADS_ELASTIC || !quadrature_ok(prm->p))
+                    ? 3 : P->var[prm->p - 1][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
   ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
   g_force_var = -1;
   if (st != ADS_OK) return st;

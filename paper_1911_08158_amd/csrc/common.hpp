@@ -11,7 +11,7 @@
 
 namespace ads {
 
-constexpr int kMaxP = 3;          // spline degrees 2 and 3 are instantiated
+constexpr int kMaxP = 5;          // spline degrees 1 to 5 are instantiated
 
 // Every launch reads its job count and tile count from a device-side header
 // that precedes its job table, so that a captured graph can be replayed

@@ -175,34 +175,75 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
   __syncthreads();   // LDS is reused by the next tile
 }
 
-// Jobs of both degrees may share a launch: the degree is taken per tile.
+// Jobs of different degrees may share a launch: the degree is taken per
+// tile (HI instantiation: every degree 1 to 5, for launches that hold
+// p = 4 or 5; else 1 to 3; the LDS is sized for the largest degree of the
+// launch).
+template <bool HI>
 __global__ __launch_bounds__(KNT) void kron_kernel(const LaunchHdr* __restrict__ hdr) {
   extern __shared__ double lds[];
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
   const KronJob* __restrict__ jobs = hdr_jobs<KronJob>(hdr);
   for (int tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const KronJob& J = jobs[find_job_kron(jobs, njobs, tile)];
-    if (J.p == 2) kron_tile<2>(J, tile - J.tile0, lds);
-    else kron_tile<3>(J, tile - J.tile0, lds);
+    if constexpr (HI) {
+      if (J.p == 5) {
+        kron_tile<5>(J, tile - J.tile0, lds);
+        continue;
+      }
+      if (J.p == 4) {
+        kron_tile<4>(J, tile - J.tile0, lds);
+        continue;
+      }
+    }
+    {
+      if (J.p == 1) kron_tile<1>(J, tile - J.tile0, lds);
+      else if (J.p == 2) kron_tile<2>(J, tile - J.tile0, lds);
+      else kron_tile<3>(J, tile - J.tile0, lds);
+    }
   }
 }
 
 int kron_tile_x() { return KTX; }
 int kron_tile_y() { return KTY; }
 
-// LDS of the larger degree (a launch may mix degrees)
-static size_t kron_lds_bytes() { return std::max(KronGeom<2>::lds_elems, KronGeom<3>::lds_elems) * sizeof(double); }
-
-int kron_blocks_per_cu() {
-  int n = 0;
-  const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kron_kernel, KNT, kron_lds_bytes());
-  return (e == hipSuccess && n > 0) ? n : 2;
+static size_t kron_lds_elems(int p) {
+  switch (p) {
+    case 1: return KronGeom<1>::lds_elems;
+    case 2: return KronGeom<2>::lds_elems;
+    case 3: return KronGeom<3>::lds_elems;
+    case 4: return KronGeom<4>::lds_elems;
+    default: return KronGeom<5>::lds_elems;
+  }
+}
+// LDS of a launch whose largest degree is pmax (the layout of every degree
+// up to pmax fits)
+static size_t kron_lds_bytes(int pmax) {
+  size_t e = 0;
+  for (int p = 1; p <= pmax; ++p) e = std::max(e, kron_lds_elems(p));
+  return e * sizeof(double);
 }
 
-hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s) {
+int kron_blocks_per_cu(int pmax) {
+  int n = 0;
+  const void* k = pmax >= 4 ? (const void*)kron_kernel<true> : (const void*)kron_kernel<false>;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, KNT, kron_lds_bytes(pmax));
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t kron_set_attributes() {
+  for (const void* k : {(const void*)kron_kernel<false>, (const void*)kron_kernel<true>}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, int pmax, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kron_kernel, dim3(grid), dim3(KNT), kron_lds_bytes(), s, d_hdr);
+  if (pmax < 1 || pmax > kMaxP) return hipErrorInvalidValue;
+  if (pmax >= 4) hipLaunchKernelGGL(kron_kernel<true>, dim3(grid), dim3(KNT), kron_lds_bytes(pmax), s, d_hdr);
+  else hipLaunchKernelGGL(kron_kernel<false>, dim3(grid), dim3(KNT), kron_lds_bytes(pmax), s, d_hdr);
   return hipGetLastError();
 }
 

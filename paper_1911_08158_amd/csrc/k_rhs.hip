@@ -779,7 +779,7 @@ int rhs_tile_x(int p, int var) { return var == 3 ? rhs_band_tile_x() : 16 - p; }
 int rhs_tile_y(int p, int mixed, int var) {
   if (var == 3) return rhs_band_tile_y();
   if (var < 0 || var > 2) var = 0;
-  if (p == 2) return mixed ? kVarP2F[var].TY : kVarP2D[var].TY;
+  if (p <= 2) return mixed ? kVarP2F[var].TY : kVarP2D[var].TY;
   return mixed ? kVarP3F[var].TY : kVarP3D[var].TY;
 }
 
@@ -841,14 +841,15 @@ static hipError_t dispatch(int p, int mixed, int var, int coef, const LaunchHdr*
 
 hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr* d_hdr, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (p != 2 && p != 3) return hipErrorInvalidValue;
   if (var == 3) return coef ? hipErrorInvalidValue : launch_rhs_band(p, mixed, d_hdr, grid, s);
+  if (p != 2 && p != 3) return hipErrorInvalidValue;   // the quadrature is instantiated for p = 2, 3
   if (var < 0 || var > 2) var = 0;
   return dispatch(p, mixed, var, coef, d_hdr, grid, s, 0, nullptr);
 }
 
 int rhs_blocks_per_cu(int p, int mixed, int var, int coef) {
   if (var == 3 && !coef) return rhs_band_blocks_per_cu(p, mixed);
+  if (p != 2 && p != 3) return 1;
   if (var < 0 || var > 2) var = 0;
   int n = 1;
   (void)dispatch(p, mixed, var, coef, nullptr, 0, nullptr, 1, &n);

@@ -82,10 +82,10 @@ __device__ __forceinline__ const double* band_table(const double* tab, int E) {
   return tab + (4ll * E * Q * P + (long long)E * Q + 2ll * E * P * P);
 }
 
-// waves per SIMD: four at p = 2 (FP32 at five spills registers and runs
-// slower), four (FP32) or three (FP64) at p = 3
+// waves per SIMD: four at p <= 2 (FP32 at five spills registers and runs
+// slower), four (FP32) or three (FP64) at p = 3, two above
 template <typename T, int p>
-__global__ __launch_bounds__(BNT, p == 2 ? 4 : (sizeof(T) == 4 ? 4 : 3)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(BNT, p <= 2 ? 4 : (p == 3 ? (sizeof(T) == 4 ? 4 : 3) : 2)) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
   using Gm = BandGeom<T, p>;
   constexpr int B = Gm::B, SX = Gm::SX, SY = Gm::SY, NS = Gm::NS, NXI = Gm::NXI;
   // The predictor and the mass channel stay FP64 in every mode: a stiffness
@@ -331,10 +331,20 @@ static hipError_t band_one(const LaunchHdr* d_hdr, int grid, hipStream_t s, int 
   return hipGetLastError();
 }
 
+template <int p>
+static hipError_t band_p(int mixed, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
+  return mixed ? band_one<float, p>(d_hdr, grid, s, op, out) : band_one<double, p>(d_hdr, grid, s, op, out);
+}
+
 static hipError_t band_dispatch(int p, int mixed, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
-  if (p == 2) return mixed ? band_one<float, 2>(d_hdr, grid, s, op, out) : band_one<double, 2>(d_hdr, grid, s, op, out);
-  if (p == 3) return mixed ? band_one<float, 3>(d_hdr, grid, s, op, out) : band_one<double, 3>(d_hdr, grid, s, op, out);
-  return hipErrorInvalidValue;
+  switch (p) {
+    case 1: return band_p<1>(mixed, d_hdr, grid, s, op, out);
+    case 2: return band_p<2>(mixed, d_hdr, grid, s, op, out);
+    case 3: return band_p<3>(mixed, d_hdr, grid, s, op, out);
+    case 4: return band_p<4>(mixed, d_hdr, grid, s, op, out);
+    case 5: return band_p<5>(mixed, d_hdr, grid, s, op, out);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int rhs_band_tile_x() { return BTX; }

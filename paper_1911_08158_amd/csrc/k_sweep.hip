@@ -221,8 +221,25 @@ __device__ __forceinline__ void substitute(double* tl, int lane, int m, const do
 
 // Job tiling: SweepJob.tile0 / ntiles count groups of 4W lines; the header's
 // total_tiles is the number of groups of the launch.
-template <int W>
-__global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restrict__ hdr, int max_m) {
+// Substitution of degree p: HI instantiations take every degree 1 to 5
+// (launches whose jobs include p = 4 or 5), the others p = 1, 2, 3 (two
+// kernels, so that the registers of the high degrees do not weigh on the
+// common ones).
+template <int W, bool HI>
+__device__ __forceinline__ void substitute_p(int p, double* tl, int lane, int m, const double* fl) {
+  if constexpr (HI) {
+    if (p == 5) return substitute<W, 5>(tl, lane, m, fl);
+    if (p == 4) return substitute<W, 4>(tl, lane, m, fl);
+  }
+  if (p == 1) substitute<W, 1>(tl, lane, m, fl);
+  else if (p == 2) substitute<W, 2>(tl, lane, m, fl);
+  else substitute<W, 3>(tl, lane, m, fl);
+}
+
+// frows: factor rows per line position in LDS, 2 pmax + 1 for the largest
+// degree pmax of the launch's jobs.
+template <int W, bool HI>
+__global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restrict__ hdr, int max_m, int frows) {
   static_assert(64 % W == 0, "W must divide the wave size");
   constexpr int RL = 64 / W;   // lanes per line in the cooperative y/z access
   extern __shared__ double lds[];
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
   const int lane = tid & 63, wv = tid >> 6;
   const int ll = lane % W, lq = lane / W;   // cooperative y/z access: line ll, row phase lq
   double* fl = lds;                                             // factor rows
-  double* tl = lds + (2 * kMaxP + 1) * max_m + wv * (W + 1) * max_m;  // this wave's tile
+  double* tl = lds + frows * max_m + wv * (W + 1) * max_m;      // this wave's tile
   int staged = -1;                                              // job whose factor is in LDS
   for (int grp = blockIdx.x; grp < total_groups; grp += gridDim.x) {
     const int jb = find_job_sweep(jobs, njobs, grp);
@@ -297,10 +314,7 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
       }
     }
     wave_sync_sw();
-    if (lane < nl) {
-      if (J.p == 2) substitute<W, 2>(tl, lane, m, fl);
-      else substitute<W, 3>(tl, lane, m, fl);
-    }
+    if (lane < nl) substitute_p<W, HI>(J.p, tl, lane, m, fl);
     wave_sync_sw();
     if (dir == 0) {
       const long long gb = (long long)line0 * m;
@@ -533,6 +547,46 @@ size_t plane_lds_bytes(int nx, int ny, int p) {
 }
 bool plane_fits(int nx, int ny, int p) { return plane_lds_bytes(nx, ny, p) <= (size_t)160 * 1024; }
 
+// x-lines of a plane: forward pass from global memory, backward in LDS
+template <int P>
+__device__ __forceinline__ void plane_x(const gmem<double>* __restrict__ src, double scale, double* col, int nx,
+                                        const double* fxl) {
+  fwd_from_global<P>(src, scale, col, nx, fxl);
+  bwd_st<P, false>(col, 1, nullptr, 0, nx, fxl);
+}
+// y-lines of a plane: forward pass in LDS, backward pass storing the results
+template <int P>
+__device__ __forceinline__ void plane_y(double* col, int PX, gmem<double>* __restrict__ dst, int nx, int ny,
+                                        const double* fyl) {
+  fwd_st<P>(col, PX, ny, fyl);
+  bwd_st<P, true>(col, PX, dst, nx, ny, fyl);
+}
+
+// Degree dispatch as in substitute_p (HI: every degree, else 1 to 3).
+template <bool HI>
+__device__ __forceinline__ void plane_x_p(int p, const gmem<double>* __restrict__ src, double scale, double* col,
+                                          int nx, const double* fxl) {
+  if constexpr (HI) {
+    if (p == 5) return plane_x<5>(src, scale, col, nx, fxl);
+    if (p == 4) return plane_x<4>(src, scale, col, nx, fxl);
+  }
+  if (p == 1) plane_x<1>(src, scale, col, nx, fxl);
+  else if (p == 2) plane_x<2>(src, scale, col, nx, fxl);
+  else plane_x<3>(src, scale, col, nx, fxl);
+}
+template <bool HI>
+__device__ __forceinline__ void plane_y_p(int p, double* col, int PX, gmem<double>* __restrict__ dst, int nx,
+                                          int ny, const double* fyl) {
+  if constexpr (HI) {
+    if (p == 5) return plane_y<5>(col, PX, dst, nx, ny, fyl);
+    if (p == 4) return plane_y<4>(col, PX, dst, nx, ny, fyl);
+  }
+  if (p == 1) plane_y<1>(col, PX, dst, nx, ny, fyl);
+  else if (p == 2) plane_y<2>(col, PX, dst, nx, ny, fyl);
+  else plane_y<3>(col, PX, dst, nx, ny, fyl);
+}
+
+template <bool HI>
 __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __restrict__ hdr) {
   extern __shared__ double lds[];
   const int njobs = hdr->njobs, total = hdr->total_tiles;
@@ -576,59 +630,57 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
     // LDS; a thread per line, lanes a padded row apart
     for (int y = tid; y < ny; y += kPT) {
       double* col = pl + y * PX;
-      if (p == 2) {
-        fwd_from_global<2>(gin + (long long)y * nx, scale, col, nx, fxl);
-        bwd_st<2, false>(col, 1, nullptr, 0, nx, fxl);
-      } else {
-        fwd_from_global<3>(gin + (long long)y * nx, scale, col, nx, fxl);
-        bwd_st<3, false>(col, 1, nullptr, 0, nx, fxl);
-      }
+      const gmem<double>* src = gin + (long long)y * nx;
+      plane_x_p<HI>(p, src, scale, col, nx, fxl);
     }
     __syncthreads();
     // y-lines: forward pass in LDS, the backward pass stores each final
     // value (a row of adjacent lanes: coalesced) instead of writing it back
     for (int x = tid; x < nx; x += kPT) {
-      if (p == 2) {
-        fwd_st<2>(pl + x, PX, ny, fyl);
-        bwd_st<2, true>(pl + x, PX, gout + x, nx, ny, fyl);
-      } else {
-        fwd_st<3>(pl + x, PX, ny, fyl);
-        bwd_st<3, true>(pl + x, PX, gout + x, nx, ny, fyl);
-      }
+      plane_y_p<HI>(p, pl + x, PX, gout + x, nx, ny, fyl);
     }
   }
 }
 
-int plane_blocks_per_cu(size_t lds_bytes) {
+// Launches whose jobs have a degree above 3 take the HI instantiations.
+static bool hi_degree(int pmax) { return pmax >= 4; }
+
+int plane_blocks_per_cu(size_t lds_bytes, int pmax) {
   int n = 0;
-  const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_plane_kernel, kPT, lds_bytes);
+  const void* k = hi_degree(pmax) ? (const void*)sweep_plane_kernel<true> : (const void*)sweep_plane_kernel<false>;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kPT, lds_bytes);
   const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds_bytes, 1));
   if (e != hipSuccess || n <= 0) n = by_lds;
   return std::max(1, std::min(n, by_lds));
 }
 
-hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (lds_bytes > (size_t)160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sweep_plane_kernel, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  if (hi_degree(pmax)) hipLaunchKernelGGL(sweep_plane_kernel<true>, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  else hipLaunchKernelGGL(sweep_plane_kernel<false>, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
   return hipGetLastError();
 }
 
-// Dynamic LDS of a workgroup: the factor rows (2p+1 <= 7 per line position)
-// and kWaves tiles of max_m rows of pitch W + 1.
-static size_t sweep_lds_bytes(int W, int max_m) {
-  return (size_t)(2 * kMaxP + 1 + kWaves * (W + 1)) * max_m * sizeof(double);
+// Dynamic LDS of a workgroup: the factor rows (2 pmax + 1 per line
+// position) and kWaves tiles of max_m rows of pitch W + 1.
+static size_t sweep_lds_bytes(int W, int max_m, int pmax) {
+  return (size_t)(2 * pmax + 1 + kWaves * (W + 1)) * max_m * sizeof(double);
+}
+
+template <bool HI>
+static const void* sweep_fn(int W) {
+  if (W == 16) return (const void*)sweep_kernel<16, HI>;
+  if (W == 8) return (const void*)sweep_kernel<8, HI>;
+  return (const void*)sweep_kernel<4, HI>;
 }
 
 // Resident workgroups per CU for lines of at most max_m unknowns.
-static int sweep_resident(int W, int max_m) {
-  const size_t lds = sweep_lds_bytes(W, max_m);
+static int sweep_resident(int W, int max_m, int pmax) {
+  const size_t lds = sweep_lds_bytes(W, max_m, pmax);
   int n = 0;
-  hipError_t e;
-  if (W == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<16>, kNT, lds);
-  else if (W == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<8>, kNT, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)sweep_kernel<4>, kNT, lds);
+  const void* k = hi_degree(pmax) ? sweep_fn<true>(W) : sweep_fn<false>(W);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kNT, lds);
   const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds, 1));
   if (e != hipSuccess || n <= 0) n = by_lds;
   return std::max(1, std::min(n, by_lds));
@@ -641,49 +693,54 @@ static int sweep_resident(int W, int max_m) {
 // launches with too few lines to give every CU a group, and for lines too
 // long for four 16-line tiles in LDS (ADS_SWEEP_W = 4, 8 or 16 overrides
 // where it fits).
-int sweep_width_for(long long lines, int max_m, int ncu) {
+int sweep_width_for(long long lines, int max_m, int ncu, int pmax) {
   static const int forced = [] {
     const char* e = std::getenv("ADS_SWEEP_W");
     const int v = e ? std::atoi(e) : 0;
     return (v == 4 || v == 8 || v == 16) ? v : 0;
   }();
-  auto fits = [&](int W) { return sweep_lds_bytes(W, max_m) <= (size_t)160 * 1024; };
+  auto fits = [&](int W) { return sweep_lds_bytes(W, max_m, pmax) <= (size_t)160 * 1024; };
   if (forced && fits(forced)) return forced;
   for (int W : {16, 8}) {
     if (fits(W) && lines >= (long long)ncu * kWaves * W) return W;
   }
-  return 4;   // fits for lines up to 758 long (the library accepts up to 512)
+  return 4;   // fits for lines up to 728 long at p = 5 (the library accepts up to 512)
 }
 
 // Groups of 4W lines in a job of `lines` lines.
 int sweep_groups(long long lines, int W) { return (int)((lines + (long long)kWaves * W - 1) / (kWaves * W)); }
 
-int sweep_blocks_per_cu(int W, int max_m) { return sweep_resident(W, max_m); }
+int sweep_blocks_per_cu(int W, int max_m, int pmax) { return sweep_resident(W, max_m, pmax); }
 
-hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hipStream_t s) {
-  const size_t lds = sweep_lds_bytes(W, max_m);
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, int pmax, hipStream_t s) {
+  const size_t lds = sweep_lds_bytes(W, max_m, pmax);
   if (grid <= 0) return hipSuccess;
+  if (W != 16 && W != 8 && W != 4) return hipErrorInvalidValue;
+  if (pmax < 1 || pmax > kMaxP) return hipErrorInvalidValue;
+  const int frows = 2 * pmax + 1;
+  const bool hi = hi_degree(pmax);
   if (W == 16) {
-    hipLaunchKernelGGL(sweep_kernel<16>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
+    if (hi) hipLaunchKernelGGL((sweep_kernel<16, true>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
+    else hipLaunchKernelGGL((sweep_kernel<16, false>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
   } else if (W == 8) {
-    hipLaunchKernelGGL(sweep_kernel<8>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
-  } else if (W == 4) {
-    hipLaunchKernelGGL(sweep_kernel<4>, dim3(grid), dim3(kNT), lds, s, d_hdr, max_m);
+    if (hi) hipLaunchKernelGGL((sweep_kernel<8, true>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
+    else hipLaunchKernelGGL((sweep_kernel<8, false>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
   } else {
-    return hipErrorInvalidValue;
+    if (hi) hipLaunchKernelGGL((sweep_kernel<4, true>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
+    else hipLaunchKernelGGL((sweep_kernel<4, false>), dim3(grid), dim3(kNT), lds, s, d_hdr, max_m, frows);
   }
   return hipGetLastError();
 }
 
 hipError_t sweep_set_attributes() {
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)sweep_plane_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)sweep_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)sweep_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)sweep_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  const void* ks[] = {(const void*)sweep_plane_kernel<false>, (const void*)sweep_plane_kernel<true>,
+                      sweep_fn<false>(16), sweep_fn<false>(8), sweep_fn<false>(4),
+                      sweep_fn<true>(16), sweep_fn<true>(8), sweep_fn<true>(4)};
+  for (const void* k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ads

@@ -9,17 +9,18 @@ namespace ads {
 // the jobs) and a grid size (all tiles, or a persistent grid that loops).
 // Sweeps: a workgroup takes groups of 4W lines (one W-line tile per wave);
 // job tile counts are in groups.
-int sweep_width_for(long long lines, int max_m, int ncu);
+// pmax: the largest spline degree among the launch's jobs (1..5).
+int sweep_width_for(long long lines, int max_m, int ncu, int pmax);
 int sweep_groups(long long lines, int W);
-int sweep_blocks_per_cu(int W, int max_m);
-hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, hipStream_t s);
+int sweep_blocks_per_cu(int W, int max_m, int pmax);
+hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, int pmax, hipStream_t s);
 hipError_t sweep_set_attributes();
 // In-plane sweeps: one workgroup per z-plane (PlaneJob tiles are planes);
 // a plane of nx x ny unknowns fits when plane_lds_bytes <= 160 KiB.
 size_t plane_lds_bytes(int nx, int ny, int p);
 bool plane_fits(int nx, int ny, int p);
-int plane_blocks_per_cu(size_t lds_bytes);
-hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, hipStream_t s);
+int plane_blocks_per_cu(size_t lds_bytes, int pmax);
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, hipStream_t s);
 
 // P-wave right-hand side: variants 0-2 are tile shapes of the quadrature
 // kernel; variant 3 is the Kronecker (assembled band) form, for jobs
@@ -44,10 +45,11 @@ int rhs_el_band_tile_y(int p);
 int rhs_el_band_blocks_per_cu(int p, int mixed);
 hipError_t launch_rhs_elastic_band(int p, int mixed, const LaunchHdr* d_hdr, int grid, hipStream_t s);
 
-hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, hipStream_t s);
+hipError_t launch_kron(const LaunchHdr* d_hdr, int grid, int pmax, hipStream_t s);
+hipError_t kron_set_attributes();
 int kron_tile_x();
 int kron_tile_y();
-int kron_blocks_per_cu();
+int kron_blocks_per_cu(int pmax);
 
 hipError_t launch_full_to_free(const double* full, double* fr, const int n[3], const int nf[3],
                                const int off[3], int ncomp, hipStream_t s);

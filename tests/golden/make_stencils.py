@@ -34,7 +34,7 @@ def stencils(p):
 
 if __name__ == "__main__":
     out = {"citation": "cardinal B-spline autocorrelation identity (see README.md)"}
-    for p in (1, 2, 3, 4):
+    for p in (1, 2, 3, 4, 5):
         mass, stiff = stencils(p)
         out[f"p{p}"] = {"mass_over_h": [[f.numerator, f.denominator] for f in mass],
                         "stiffness_times_h": [[f.numerator, f.denominator] for f in stiff]}

@@ -36,7 +36,7 @@ def _params(**kw):
     return Params.of(**d)
 
 
-@pytest.mark.parametrize("bad", [dict(p=1), dict(p=4), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
+@pytest.mark.parametrize("bad", [dict(p=0), dict(p=6), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
                                  dict(problem="elastic", mu=0.0), dict(problem="elastic", rho=-1.0),
                                  dict(problem="elastic", precision="mixed_bf16"),
                                  dict(nelem=(600, 4, 4)), dict(bc=2), dict(bc=-1),

@@ -13,7 +13,7 @@ from oracle import bspline, matrices as mx
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "stencils.json")
 
 
-@pytest.mark.parametrize("E,p", [(1, 1), (3, 2), (7, 2), (5, 3), (9, 3), (6, 4)])
+@pytest.mark.parametrize("E,p", [(1, 1), (3, 2), (7, 2), (5, 3), (9, 3), (6, 4), (7, 5)])
 def test_partition_of_unity_and_support(E, p):
     """P1: sum_i B_i = 1, sum_i B_i' = 0, B_i >= 0, supp B_i = [t_i, t_{i+p+1}]."""
     t = bspline.open_uniform_knots(E, p)
@@ -29,7 +29,7 @@ def test_partition_of_unity_and_support(E, p):
         assert np.all(B[outside, i] == 0.0)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_derivative_matches_finite_difference(p):
     t = bspline.open_uniform_knots(6, p)
     x = np.random.default_rng(2).uniform(0.01, 0.99, 50)
@@ -39,14 +39,14 @@ def test_derivative_matches_finite_difference(p):
     np.testing.assert_allclose(bspline.basis_deriv(t, p, x), fd, atol=1e-7)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_greville_reproduces_linear(p):
     t = bspline.open_uniform_knots(5, p)
     x = np.linspace(0, 1, 37)
     np.testing.assert_allclose(bspline.basis(t, p, x) @ bspline.greville(t, p), x, atol=1e-14)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_interior_stencils_closed_form(p):
     """P2: interior rows equal the cardinal-spline autocorrelation values
     (tests/golden/stencils.json, exact rationals)."""

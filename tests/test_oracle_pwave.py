@@ -8,7 +8,7 @@ import scipy.linalg
 from oracle import kron, matrices as mx, pwave, quadref
 
 
-@pytest.mark.parametrize("E,p", [((3, 4, 2), 2), ((3, 2, 3), 3)])
+@pytest.mark.parametrize("E,p", [((3, 4, 2), 2), ((3, 2, 3), 3), ((4, 3, 2), 1), ((2, 3, 2), 4), ((2, 2, 3), 5)])
 def test_stiffness_quadrature_route(E, p):
     """P7: element-loop quadrature of (grad B_i, grad u_h) equals the
     Kronecker route sum_d K_d (x) M (x) M, also on the full index set."""
@@ -33,7 +33,7 @@ def _mode(pw, k):
 
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
 @pytest.mark.parametrize("tau", [1e-2, 0.3, 10.0])
-@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_eigenmode_recursion(tau, p, bc):
     """P8: on a separable eigenmode the 3D scheme reduces to the scalar
     recursion with s = sum lam_d and g = prod(1 + eta lam_d) (with natural
@@ -156,7 +156,7 @@ def test_point_load_partition_of_unity():
     assert abs(b.sum() - 1.0) < 1e-14 and b.min() >= 0
 
 
-@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_brute_force_dense_run(p):
     """P16: everything assembled densely (np.kron) and solved with dense
     solves matches the oracle's line-solve path."""
@@ -178,8 +178,11 @@ def test_brute_force_dense_run(p):
         V = V + 0.5 * tau * (A + A1)
         U = W + pw.eta * A1
         A = A1
-    np.testing.assert_allclose(u.ravel(), U, rtol=1e-12, atol=1e-12 * np.abs(U).max())
-    np.testing.assert_allclose(a.ravel(), A, rtol=1e-12, atol=1e-12 * np.abs(A).max())
+    # two FP64 routes differ by rounding amplified by the condition number of
+    # G (7e6 for p = 5 on this mesh: boundary splines of high degree)
+    tol = max(1e-12, 1e-15 * np.linalg.cond(Gf))
+    np.testing.assert_allclose(u.ravel(), U, rtol=tol, atol=tol * np.abs(U).max())
+    np.testing.assert_allclose(a.ravel(), A, rtol=tol, atol=tol * np.abs(A).max())
 
 
 def test_splitting_error_order():

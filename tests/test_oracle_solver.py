@@ -14,7 +14,7 @@ def _spd_band(m, p, seed):
     return A
 
 
-@pytest.mark.parametrize("m,p", [(1, 2), (2, 2), (5, 2), (16, 2), (4, 3), (13, 3), (40, 3)])
+@pytest.mark.parametrize("m,p", [(1, 2), (2, 2), (5, 2), (16, 2), (4, 3), (13, 3), (40, 3), (9, 1), (30, 4), (25, 5)])
 def test_band_lu_against_lapack(m, p):
     A = _spd_band(m, p, 0)
     assert A.shape == (m, m)
@@ -45,7 +45,7 @@ def test_band_lu_reconstructs_matrix():
     np.testing.assert_allclose(L @ U, A, atol=1e-15)
 
 
-@pytest.mark.parametrize("shape,p", [((3, 4, 5), 2), ((4, 4, 4), 3), ((2, 6, 3), 3), ((5, 3, 4), 2)])
+@pytest.mark.parametrize("shape,p", [((3, 4, 5), 2), ((4, 4, 4), 3), ((2, 6, 3), 3), ((5, 3, 4), 2), ((4, 3, 5), 1), ((2, 3, 2), 4), ((2, 2, 3), 5)])
 def test_kronecker_identity_dense(shape, p):
     """P6: three line-solve passes equal a dense solve of the assembled
     Kronecker product, (A_x(x)A_y(x)A_z)^{-1} = A_x^{-1}(x)A_y^{-1}(x)A_z^{-1}."""
