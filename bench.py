@@ -319,32 +319,71 @@ def measure_accuracy(cfg, steps):
             "v": "u'", "a": "u''", "oracle_seconds": round(t_oracle, 1), "errors": out}
 
 
-def measure_elastic(cfg, steps, warmup):
-    """Elasticity (alternating-triangular step), one FP64 simulation."""
+def measure_elastic(cfg, steps, warmup, precision="fp64"):
+    """Elasticity (alternating-triangular step), one simulation, per-kernel
+    launches.  The timed steps carry no events; kernel times per kind come
+    from a separate profiled pass."""
     import torch
     from paper_1911_08158_amd import Sim
-    sim = Sim(cfg, device="cuda:0", precision="fp64")
+    sim = Sim(cfg, device="cuda:0", precision=precision)
     setup_sim(sim, cfg)
     sim.step(warmup)
     torch.cuda.synchronize()
-    sim.profile(True)
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms, kinds, step_ms = sim.profile_read(steps)
+    nprof = max(5, min(steps, 50))
+    sim.profile(True)
+    sim.step(nprof)
+    ms, kinds, step_ms = sim.profile_read(nprof)
+    sim.profile(False)
     sim.check_finite()
     sim.close()
     per = {}
     for k, m in zip(kinds, ms):
         per[k] = round(per.get(k, 0.0) + float(m), 5)
     return {
-        "workload": f"elasticity {cfg.nelem[0]}^3 elements p={cfg.p} (3 x {cfg.n[0]}^3 DOFs) tau={cfg.tau}, FP64",
+        "workload": f"elasticity {cfg.nelem[0]}^3 elements p={cfg.p} (3 x {cfg.n[0]}^3 DOFs) tau={cfg.tau}, "
+                    f"{precision}",
         "dof_steps_per_s": cfg.dofs() * steps / wall,
         "ms_per_step": wall / steps * 1e3,
         "ms_per_step_by_kind": per,
+        "step_ms_p50": float(np.percentile(step_ms, 50)),
         "step_ms_p99": float(np.percentile(step_ms, 99)),
+        "timing": f"wall clock over {steps} steps without events; kernels from HIP events in {nprof} profiled steps",
     }
+
+
+def measure_serving_plain(reqs):
+    """The same request stream served plainly: one simulation at a time in
+    arrival order (FIFO), FP64 right-hand side, per-kernel launches (no pool,
+    no batching), every request's steps back to back.  The closed-loop
+    throughput (all requests queued at t = 0) is the comparison for the
+    pool's closed loop."""
+    import torch
+
+    import workloads as W
+    from paper_1911_08158_amd import Sim
+    t0 = time.perf_counter()
+    dof_steps = 0
+    gpu_s = 0.0
+    for r in reqs:
+        cfg = r.cfg.with_(precision="fp64")
+        sim = Sim(cfg, device="cuda:0", precision="fp64")
+        sim.set_state(torch.from_numpy(W.initial_coefficients(cfg)).to("cuda:0"), None, None, 0)
+        sim.factor()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        sim.step(cfg.steps)
+        torch.cuda.synchronize()
+        gpu_s += time.perf_counter() - ts
+        sim.close()
+        dof_steps += cfg.dofs() * cfg.steps
+    wall = time.perf_counter() - t0
+    return {"requests": len(reqs), "wall_s": wall, "stepping_s": gpu_s, "dof_steps": int(dof_steps),
+            "dof_steps_per_s": dof_steps / wall, "dof_steps_per_stepping_s": dof_steps / gpu_s,
+            "note": "wall includes per-request creation and factorization; stepping_s only the step loops"}
 
 
 def measure_serving(nreq, pool_gib, max_slots):
@@ -371,19 +410,22 @@ def measure_serving(nreq, pool_gib, max_slots):
     pool = Pool(int(pool_gib * (1 << 30)), max_slots=max_slots, device="cuda:0")
     base = W.serving_mix(nreq)
     closed = [W.Request(r.rid, 0.0, r.cfg) for r in base]
-    _, st_closed = serve(pool, closed, setup, steps_of, dofs_of)
+    _, st_closed = serve(pool, closed, setup, steps_of, dofs_of, check_every=10)
     sat = nreq / st_closed["wall_s"]
     arrivals = W.serving_mix(nreq, rate=0.8 * sat)
-    _, st = serve(pool, arrivals, setup, steps_of, dofs_of)
+    _, st = serve(pool, arrivals, setup, steps_of, dofs_of, check_every=10)
     pool.close()
+    plain = measure_serving_plain(closed)
     npw = sum(1 for r in base if r.cfg.problem == "pwave")
     return {
-        "workload": f"{nreq} requests: P-wave (mixed) / elasticity (FP64) {npw}/{nreq - npw}, "
+        "workload": f"{nreq} requests: P-wave / elasticity {npw}/{nreq - npw}, mixed-precision right-hand sides, "
                     "E_d in {32,48,64,96} per direction, p in {2,3}, tau in {1e-3,5e-3}, 50 steps",
         "pool_gib": pool_gib, "max_slots": max_slots,
         "saturation_requests_per_s": sat,
         "closed_loop": st_closed,
         "poisson_0p8": st,
+        "plain_fifo_fp64": plain,
+        "served_vs_plain": st_closed["dof_steps_per_s"] / plain["dof_steps_per_s"],
     }
 
 
@@ -488,7 +530,9 @@ def main():
         print(json.dumps({"form": "serving", **measure_serving(args.requests, 16, 64)}), flush=True)
         return
     if args.only == "elastic":
-        print(json.dumps({"form": "elastic", **measure_elastic(W.C4, args.steps, args.warmup)}), flush=True)
+        for prec in ("fp64", "mixed_fp32"):
+            print(json.dumps({"form": f"elastic_{prec}", **measure_elastic(W.C4, args.steps, args.warmup, prec)}),
+                  flush=True)
         return
     if args.only == "quadrature":
         for prec in ("fp64", "mixed_fp32"):
@@ -546,7 +590,8 @@ def main():
     out["quadrature_rhs"] = {"workload": "P-wave 128^3 elements p=2 tau=2e-3 with the wave-speed field "
                                          "c^2 = 1 + 0.5 sin(2 pi x) cos(2 pi y) sin(2 pi z + 0.3) at the Gauss points "
                                          "(c2ref = 1.5), one simulation", **quad}
-    out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup)
+    out["elastic_fp64"] = measure_elastic(W.C4, args.steps, args.warmup, "fp64")
+    out["elastic_mixed"] = measure_elastic(W.C4, args.steps, args.warmup, "mixed_fp32")
     c2 = W.C2.with_(precision="fp64")
     out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
                                         "FP64, one simulation", **measure_plain(c2, args.steps, args.warmup)}

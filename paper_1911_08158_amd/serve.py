@@ -7,6 +7,15 @@ iteration advances all active simulations by one pool step (one graph
 replay); simulations that have taken their steps are read out and retired,
 which frees their memory for the queue.  Per-step latency of a simulation is
 the duration of the pool step that advanced it (HIP events).
+
+Failure handling (every request ends with a status):
+  done       all steps taken;
+  rejected   the pool refuses the parameters (ADS_EINVAL), or the request
+             does not fit even in an empty pool (it could never be admitted);
+  cancelled  the request's ``cancel_at`` time (seconds after the start)
+             passed while it was queued or running;
+  failed     the periodic health check (every ``check_every`` steps) found a
+             non-finite state: the slot is retired, the others continue.
 """
 from __future__ import annotations
 
@@ -17,6 +26,10 @@ from typing import Callable, List, Optional
 
 import numpy as np
 
+from .binding import AdsError
+
+ADS_ENUMERIC = -5
+
 
 @dataclasses.dataclass
 class RequestRecord:
@@ -26,18 +39,23 @@ class RequestRecord:
     finished: float = float("nan")
     steps: int = 0
     dofs: int = 0
+    status: str = "queued"
+    error: str = ""
     step_ms: List[float] = dataclasses.field(default_factory=list)
     result: Optional[object] = None
 
 
 def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable,
-          keep_results: bool = False, clock=time.perf_counter, max_wall: float = 600.0):
+          keep_results: bool = False, clock=time.perf_counter, max_wall: float = 600.0,
+          check_every: int = 0, sleep=time.sleep):
     """Run the request stream to completion.
 
-    requests: objects with ``rid``, ``arrival`` (seconds after start) and
-    ``cfg``; setup(sim, cfg) configures a freshly admitted slot (initial
-    state, load, factor); steps_of(req) / dofs_of(req) give the step count
-    and the DOFs counted by the throughput metric.  Returns (records, stats).
+    requests: objects with ``rid``, ``arrival`` (seconds after start), ``cfg``
+    and optionally ``cancel_at``; setup(sim, cfg) configures a freshly
+    admitted slot (initial state, load, factor); steps_of(req) / dofs_of(req)
+    give the step count and the DOFs counted by the throughput metric.
+    check_every > 0: every that many steps of a simulation its state is
+    checked for non-finite values.  Returns (records, stats).
     """
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     recs = {r.rid: RequestRecord(r.rid, r.arrival) for r in requests}
@@ -45,23 +63,59 @@ def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable
     t0 = clock()
     busy = 0.0
     dof_steps = 0
+
+    def cancelled(req, now):
+        c = getattr(req, "cancel_at", None)
+        return c is not None and now >= c
+
+    def finish(slot, status, error=""):
+        req, sim, n = active.pop(slot)
+        rec = recs[req.rid]
+        if keep_results and status == "done":
+            rec.result = [t.cpu().numpy() if t is not None else None for t in sim.get_state()]
+        rec.steps = n
+        rec.dofs = dofs_of(req)
+        rec.status = status
+        rec.error = error
+        pool.retire(sim)
+        rec.finished = clock() - t0
+
     while pending or active:
         now = clock() - t0
         if now > max_wall:
             raise TimeoutError("serving loop exceeded its wall-clock budget")
+        # running requests whose cancellation time has passed
+        for slot in [s for s, ent in active.items() if cancelled(ent[0], now)]:
+            finish(slot, "cancelled")
+        # admission, first come first served
         while pending and pending[0].arrival <= now:
             req = pending[0]
-            sim = pool.admit(req.cfg)
+            rec = recs[req.rid]
+            if cancelled(req, now):
+                pending.popleft()
+                rec.status, rec.finished = "cancelled", now
+                continue
+            try:
+                sim = pool.admit(req.cfg)
+            except AdsError as e:            # parameters this pool cannot take
+                pending.popleft()
+                rec.status, rec.error, rec.finished = "rejected", str(e), now
+                continue
             if sim is None:
+                if not active:               # nothing left to free: it never fits
+                    pending.popleft()
+                    rec.status, rec.error, rec.finished = "rejected", "larger than the empty pool", now
+                    continue
                 break
             pending.popleft()
             setup(sim, req.cfg)
             pool.activate(sim)
             active[sim.slot] = [req, sim, 0]
-            recs[req.rid].admitted = clock() - t0
+            rec.admitted = clock() - t0
+            rec.status = "running"
         if not active:
             if pending:
-                time.sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
+                sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
             continue
         pool.step(1)
         dt = float(pool.step_times()[-1])          # synchronizes
@@ -70,22 +124,26 @@ def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable
             ent = active[slot]
             req, sim = ent[0], ent[1]
             ent[2] += 1
-            rec = recs[req.rid]
-            rec.step_ms.append(dt)
+            recs[req.rid].step_ms.append(dt)
             dof_steps += dofs_of(req)
+            if check_every > 0 and ent[2] % check_every == 0:
+                try:
+                    sim.check_finite()
+                except AdsError as e:
+                    if e.status != ADS_ENUMERIC:
+                        raise
+                    finish(slot, "failed", "non-finite state")
+                    continue
             if ent[2] >= steps_of(req):
-                if keep_results:
-                    rec.result = [t.cpu().numpy() if t is not None else None for t in sim.get_state()]
-                rec.steps = ent[2]
-                rec.dofs = dofs_of(req)
-                pool.retire(sim)
-                del active[slot]
-                rec.finished = clock() - t0
+                finish(slot, "done")
     wall = clock() - t0
-    lat = np.concatenate([np.asarray(r.step_ms) for r in recs.values()]) if recs else np.zeros(0)
-    req_lat = np.array([r.finished - r.arrival for r in recs.values()])
+    done = [r for r in recs.values() if r.status == "done"]
+    lat = np.concatenate([np.asarray(r.step_ms) for r in recs.values()] or [np.zeros(0)])
+    req_lat = np.array([r.finished - r.arrival for r in done])
+    counts = collections.Counter(r.status for r in recs.values())
     stats = {
         "requests": len(recs),
+        "status": dict(counts),
         "wall_s": wall,
         "gpu_busy_s": busy,
         "dof_steps": int(dof_steps),

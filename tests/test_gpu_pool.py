@@ -202,3 +202,56 @@ def test_tune_refused_for_pooled_sim_and_pool_matches_oracle():
         assert rel_l2(x.cpu().numpy(), pw.to_full(r)) <= 1e-12
     pool.retire(s)
     pool.close()
+
+
+def test_serve_evicts_nonfinite_and_rejects_what_never_fits():
+    """The serving loop on the real pool: a simulation whose initial state is
+    NaN is evicted at its first health check while the others run on; a
+    request larger than the empty pool and one the pool refuses (more than
+    128 free coefficients per direction) are rejected instead of stalling
+    the queue; every completed result is bitwise the simulation run alone."""
+    _cuda()
+    import dataclasses
+
+    import torch
+    from paper_1911_08158_amd import Pool
+    from paper_1911_08158_amd.serve import serve
+
+    cfgs = [W.C1.with_(name="ok0", nelem=(20, 17, 23), tau=0.01, steps=6, precision="mixed_fp32"),
+            W.C1.with_(name="nan", nelem=(12, 11, 9), tau=0.01, steps=6),
+            W.C4.with_(name="big", nelem=(96, 96, 96), tau=0.01, steps=6),
+            W.C1.with_(name="ok1", nelem=(9, 8, 10), p=3, q=4, tau=0.01, steps=6),
+            W.C1.with_(name="wide", nelem=(200, 4, 4), tau=0.01, steps=6),
+            W.C4.with_(name="ok2", nelem=(7, 6, 8), tau=0.02, steps=6, precision="mixed_fp32")]
+
+    @dataclasses.dataclass
+    class Req:
+        rid: int
+        arrival: float
+        cfg: object
+
+    def setup(sim, cfg):
+        xs = [sim.quad_points(d) for d in range(3)]
+        u0 = sim.project(torch.from_numpy(np.ascontiguousarray(W.initial_values(cfg, *xs))).to("cuda"))
+        if cfg.name == "nan":
+            u0 = u0 * float("nan")
+        sim.set_state(u0, None, None, 0)
+        sim.factor()
+
+    pool = Pool(64 << 20, max_slots=8)
+    recs, stats = serve(pool, [Req(i, 0.0, c) for i, c in enumerate(cfgs)], setup,
+                        steps_of=lambda r: r.cfg.steps, dofs_of=lambda r: r.cfg.dofs(),
+                        keep_results=True, check_every=2)
+    pool.close()
+    st = {cfgs[r.rid].name: r for r in recs}
+    print({k: (v.status, v.steps, v.error) for k, v in st.items()}, flush=True)
+    assert st["nan"].status == "failed" and st["nan"].steps == 2
+    assert st["big"].status == "rejected" and st["wide"].status == "rejected"
+    for name in ("ok0", "ok1", "ok2"):
+        r = st[name]
+        assert r.status == "done" and r.steps == 6
+        cfg = cfgs[r.rid]
+        ref = _alone(cfg, 6)
+        got = [x for x in r.result if x is not None]
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), name

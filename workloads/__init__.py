@@ -265,8 +265,7 @@ def serving_mix(nreq: int = 200, rate: float = 1.0, seed: int = MASTER_SEED,
         ne = tuple(int(rng.choice(sizes)) for _ in range(3))
         p = int(rng.choice(degrees))
         tau = float(rng.choice(taus))
-        cfg = SimConfig(f"req{i}", prob, ne, p, p + 1, tau, steps,
-                        precision=precision if prob == "pwave" else "fp64",
+        cfg = SimConfig(f"req{i}", prob, ne, p, p + 1, tau, steps, precision=precision,
                         init=f"gauss1:{seed + 1000 + i}")
         out.append(Request(i, t, cfg))
     return out
