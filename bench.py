@@ -210,9 +210,10 @@ def measure_plain(cfg, steps, warmup, precision="fp64", coef=False, tune=True):
     }
 
 
-def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
-    """Batched form: `batch` simulations in one pool, one graph replay per
-    step; then a profiled pass (direct launches, events per kernel)."""
+def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32", tune=True):
+    """Batched form: `batch` simulations in one pool, launch shapes chosen by
+    the pool's autotuner, one graph replay per step; then a profiled pass
+    (direct launches, events per kernel)."""
     import torch
     from paper_1911_08158_amd import Pool
     from paper_1911_08158_amd.binding import Params, workspace_bytes
@@ -225,6 +226,7 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
         setup_sim(s, cfg)
         pool.activate(s)
         sims.append(s)
+    shapes = pool.tune()[1] if tune else None
     pool.step(warmup)
     pool.step_times()
     pool.stream.synchronize()
@@ -244,6 +246,9 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
         s.check_finite()
     pool.close()
     ent = [(k, ms) for (k, p, mixed, ms) in prof if ms > 0]     # launched classes only
+    launched = [i for i, (k, p, mixed, ms) in enumerate(prof) if ms > 0]
+    tuned = None if shapes is None else {f"{prof[i][0]}@{i}": int(shapes[i]) for i in launched}
+    rhs_var = 3 if shapes is None else int(shapes[next(i for i in launched if prof[i][0] == "rhs")])
     return {
         "dof_steps_per_s": cfg.dofs() * batch * steps / wall,
         "ms_per_step": wall / steps * 1e3,
@@ -252,6 +257,8 @@ def measure_batched(cfg, batch, steps, warmup, precision="mixed_fp32"):
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "timing": f"wall clock over {steps} graph replays; kernels from HIP events in {nprof} "
                   "direct-launch steps of the same batch",
+        "rhs_variant": rhs_var,
+        "tuned_shapes": tuned,
     }
 
 
@@ -544,8 +551,7 @@ def main():
         return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
-    # the Kronecker form (variant 3) runs in the pool unless ADS_POOL_RHS_VAR asks otherwise
-    band_b = os.environ.get("ADS_POOL_RHS_VAR", "3") == "3"
+    band_b = batched["rhs_variant"] == 3
     dom = max(batched["kernels"], key=lambda k: k["ms"])
     roof = roofline_entry(dom, cfg, args.batch, band_b, True)
     roof["dominant"] = f"{dom['kernel']}: the longest launch of the batched step"

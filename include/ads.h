@@ -213,11 +213,21 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * (the default).  The choice is cached per (problem, degree, precision,
  * field or none, mesh) for later simulations in the process.  *chosen
  * receives the variant index, host_ms[v] (may be NULL; entries v < cap) the
- * mean ms of variant v.  Call after ads_factor.  The environment variable
- * ADS_RHS_VAR (0-3) sets the variant of a new simulation, ADS_POOL_RHS_VAR
- * that of a new pool's P-wave launches.  ADS_ESTATE for a simulation owned
- * by a pool (the pool fixes the launch classes). */
+ * mean ms of variant v.  Call after ads_factor.  ADS_ESTATE for a
+ * simulation owned by a pool (the pool chooses its launch shapes, see
+ * ads_pool_tune). */
 ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap);
+
+/* Launch shapes of a simulation, set explicitly (measurement and tests; the
+ * defaults and ads_tune choose them otherwise).  rhs_var: right-hand-side
+ * variant as in ads_tune (-1 keeps the current one); rhs_tz: owned z-layers
+ * per right-hand-side tile (0 = chosen from the occupancy, -1 keeps);
+ * sweep_w (NULL keeps all): lines per wave tile of the x-, y- and z-sweeps
+ * (4, 8 or 16; 0 = default, -1 keeps).  Results do not depend on the
+ * shapes, except through the variant (the two right-hand-side forms round
+ * differently).  ADS_EINVAL for a variant the problem or degree lacks or a
+ * width that does not fit the LDS, ADS_ESTATE for a pooled simulation. */
+ads_status ads_set_launch_shape(ads_sim* sim, int32_t rhs_var, int32_t rhs_tz, const int32_t* sweep_w);
 
 /* Copy the state out (full layout; asynchronous on the sim's stream).
  * P-wave: u, u', u'' (any pointer may be NULL).  Elasticity: U^n into dev_u,
@@ -297,6 +307,19 @@ ads_status ads_pool_retire(ads_pool* pool, int32_t slot);
 /* Durations (ms) of the pool steps since the last call (synchronizes); at
  * most 65536 steps are timed between two calls, later ones are not. */
 ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int32_t* n);
+/* Autotuner of the pool's launch shapes for the current batch (measurement-
+ * driven; synchronizes): every P-wave right-hand-side class (degrees 2, 3)
+ * times the quadrature tile variants and, without a wave-speed field, the
+ * Kronecker form on the batch's own jobs; every sweep class times tile
+ * widths of 4, 8 and 16 lines per wave (on a copy of its jobs that solves
+ * in place with a plain store, so that no state changes).  Each class keeps
+ * its fastest shape; the choices are cached per class and batch shape and
+ * the graph is captured again at the next step.  *nchanged receives the
+ * number of classes whose shape changed; host_shape (may be NULL; cap
+ * entries, launch positions as in ads_pool_profile_read) the shape of each
+ * launch: right-hand sides their variant, sweeps their tile width, other
+ * launches 0, launches with no simulation in the batch -1. */
+ads_status ads_pool_tune(ads_pool* pool, int32_t* nchanged, int32_t* host_shape, int32_t cap);
 /* Kernel timing of pool steps (measurement support): with enable = 1 the
  * following ads_pool_step calls enqueue the launches directly (no graph)
  * with HIP events around each; ads_pool_profile_read synchronizes and

@@ -119,6 +119,8 @@ def load_library():
         "ads_get_step": [c_void_p, POINTER(c_int64)],
         "ads_check_finite": [c_void_p],
         "ads_tune": [c_void_p, POINTER(c_int32), c_void_p, c_int32],
+        "ads_set_launch_shape": [c_void_p, c_int32, c_int32, c_void_p],
+        "ads_pool_tune": [c_void_p, POINTER(c_int32), c_void_p, c_int32],
         "ads_profile": [c_void_p, c_int32],
         "ads_profile_read": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_int32,
                              POINTER(c_int32)],
@@ -317,6 +319,14 @@ class Sim:
     def check_finite(self):
         _check(load_library().ads_check_finite(self._h))
 
+    def set_launch_shape(self, rhs_var=-1, rhs_tz=-1, sweep_w=None):
+        """Launch shapes set explicitly (-1 keeps, 0 = default; sweep_w: one
+        tile width per direction x, y, z)."""
+        w = None
+        if sweep_w is not None:
+            w = (c_int32 * 3)(*[int(x) for x in sweep_w])
+        _check(load_library().ads_set_launch_shape(self._h, int(rhs_var), int(rhs_tz), w))
+
     def tune(self):
         """Autotune the right-hand-side tiling on this mesh; returns the
         chosen variant and the measured ms per variant (NaN if cached)."""
@@ -406,6 +416,15 @@ class Pool:
 
     def step(self, n=1):
         _check(load_library().ads_pool_step(self._h, int(n)))
+
+    def tune(self):
+        """Autotune the launch shapes of the current batch; returns the
+        number of launch classes whose shape changed and the shape of every
+        launch position (variant, tile width, 0, or -1 when not launched)."""
+        n = c_int32()
+        shape = np.full(256, -1, dtype=np.int32)
+        _check(load_library().ads_pool_tune(self._h, byref(n), shape.ctypes.data, shape.size))
+        return n.value, shape
 
     def retire(self, sim):
         _check(load_library().ads_pool_retire(self._h, sim.slot))

@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ads.h"
@@ -180,7 +181,8 @@ struct ads_sim {
   std::vector<Launch> step_l, start_l, projM_l, energy_l;
   bool factored = false, need_start = true, have_load = false;
   int namp = 0;
-  int tz = 0;
+  int tz = 0;           // right-hand side: owned z-layers per tile (0: chosen from the occupancy)
+  int sweep_w[3] = {0, 0, 0};   // sweeps per direction: lines per wave tile (0: default)
   int ncu = 0;          // compute units of the device (tiling of the right-hand side)
   // P-wave right-hand side: 3 = the Kronecker form (jobs with a wave-speed
   // field take the quadrature kernel's variant 0); ads_tune may choose another
@@ -348,6 +350,14 @@ void carve(ads_sim* s, Carver& c) {
 
 int max_m(const ads_sim* s) { return std::max(s->nf[0], std::max(s->nf[1], s->nf[2])); }
 
+// Tile width of a sweep launch of direction dir: the one set by
+// ads_set_launch_shape where it fits, else the default.
+int sim_sweep_width(const ads_sim* s, int dir, long long lines) {
+  const int w = s->sweep_w[dir];
+  if (w > 0 && sweep_width_fits(w, max_m(s), s->p)) return w;
+  return sweep_width_for(lines, max_m(s), s->ncu, s->p);
+}
+
 SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* in, double* out, double scale) {
   SweepJob J{};
   J.in = in;
@@ -359,7 +369,7 @@ SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* 
   J.ny = s->nf[1];
   J.nz = s->nf[2];
   J.nlines = (int)(s->nfree / s->nf[dir]);
-  J.ntiles = sweep_groups(J.nlines, sweep_width_for(J.nlines, max_m(s), s->ncu, s->p));
+  J.ntiles = sweep_groups(J.nlines, sim_sweep_width(s, dir, J.nlines));
   J.tile0 = 0;
   J.epi = EPI_STORE;
   J.scale = scale;
@@ -412,7 +422,7 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
     const LaunchHdr* d = s->arena.add(std::vector<SweepJob>{*j}, err);
     if (!d) return false;
     L.push_back(Launch{Launch::SWEEP, d, 1, j->ntiles, max_m(s), s->p, j->dir, 0, 0, as_bytes(*j)});
-    L.back().w = sweep_width_for(j->nlines, max_m(s), s->ncu, s->p);
+    L.back().w = sim_sweep_width(s, j->dir, j->nlines);
   }
   return true;
 }
@@ -896,8 +906,6 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   s->stream = (hipStream_t)stream;
   geometry(s);
   s->ncu = ncu;
-  if (const char* e = std::getenv("ADS_RHS_TZ")) s->tz = std::atoi(e);
-  if (const char* e = std::getenv("ADS_RHS_VAR")) s->rhs_var = std::max(0, std::min(3, std::atoi(e)));
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
   if (s->elastic && s->rhs_var != 3) s->rhs_var = 0;  // elasticity: quadrature (0) or Kronecker form (3)
   if (!quadrature_ok(s->p)) s->rhs_var = 3;            // degrees without a quadrature kernel
@@ -1208,6 +1216,31 @@ ads_status ads_step(ads_sim* s, int32_t nsteps) {
   return ADS_OK;
 }
 
+ads_status ads_set_launch_shape(ads_sim* s, int32_t rhs_var, int32_t rhs_tz, const int32_t* sweep_w) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (s->pooled) return fail(ADS_ESTATE, "launch shapes of a pooled simulation are the pool's");
+  int var = s->rhs_var;
+  if (rhs_var >= 0) {
+    const bool ok = rhs_var == 3 || (quadrature_ok(s->p) && (s->elastic ? rhs_var == 0 : rhs_var <= 2));
+    if (!ok) return fail(ADS_EINVAL, "right-hand-side variant not available for this problem and degree");
+    var = rhs_var;
+  }
+  if (rhs_tz < -1 || rhs_tz > 4096) return fail(ADS_EINVAL, "rhs_tz must be -1 (keep), 0 (automatic) or a depth");
+  int w[3] = {s->sweep_w[0], s->sweep_w[1], s->sweep_w[2]};
+  if (sweep_w) {
+    for (int d = 0; d < 3; ++d) {
+      if (sweep_w[d] < 0) continue;
+      if (sweep_w[d] != 0 && !sweep_width_fits(sweep_w[d], max_m(s), s->p))
+        return fail(ADS_EINVAL, "sweep tile width must be 0 (default), 4, 8 or 16 lines and fit the LDS");
+      w[d] = sweep_w[d];
+    }
+  }
+  s->rhs_var = var;
+  if (rhs_tz >= 0) s->tz = rhs_tz;
+  for (int d = 0; d < 3; ++d) s->sweep_w[d] = w[d];
+  return build_launches(s);
+}
+
 ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
   if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
@@ -1412,10 +1445,13 @@ struct ads_pool {
   hipGraphExec_t exec = nullptr;
   std::vector<hipEvent_t> ev;
   int nev = 0;
-  // right-hand-side variant per [p-2][mixed]: the Kronecker form, bound by
-  // HBM (launches of simulations with a wave-speed field take the
-  // quadrature kernel's 14/13-row tiles, variant 0)
-  int var[kMaxP][2] = {{3, 3}, {3, 3}, {3, 3}, {3, 3}, {3, 3}};
+  // P-wave right-hand-side variant per [p-1][mixed][wave-speed field]: by
+  // default the Kronecker form (HBM-bound), and the quadrature's 14/13-row
+  // tiles (variant 0) with a field; ads_pool_tune measures the others
+  int var[kMaxP][2][2];
+  std::vector<int> w_force;        // per launch class: sweep tile width chosen by the tuner (0: default)
+  size_t tune_off = 0;             // table region for the tuner's timing launches
+  std::map<std::string, int> tune_cache;   // launch class + batch shape -> choice
   bool prof = false;
   std::vector<hipEvent_t> pev;     // (launches + 1) per profiled step
   int prof_steps = 0;
@@ -1448,7 +1484,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   for (int p = 1; p <= kMaxP; ++p)
     for (int mixed = 0; mixed <= 1; ++mixed)
       for (int coef = 0; coef <= (quadrature_ok(p) ? 1 : 0); ++coef) {
-        int var = rhs_form_var(quadrature_ok(p) ? P->var[p - 1][mixed] : 3, coef != 0);
+        int var = quadrature_ok(p) ? P->var[p - 1][mixed][coef] : 3;
         add(Launch::RHS_P, p, mixed, var, coef, 0, rhs_blocks_per_cu(p, mixed, var, coef) * ncu, sizeof(RhsJob));
       }
   for (int p = 1; p <= kMaxP; ++p)
@@ -1459,11 +1495,34 @@ void pool_build_seq(ads_pool* P, int ncu) {
     else if (is_plane_stage(k)) add(Launch::PLANE, 0, 0, 0, 0, k, ncu, sizeof(PlaneJob));
     else add(Launch::SWEEP, 0, 0, 0, 0, k, sweep_blocks_per_cu(4, kPoolMaxM, kMaxP) * ncu, sizeof(SweepJob));
   }
+  P->w_force.assign(P->seq.size(), 0);
+  P->tune_off = off;
+  off += (sizeof(LaunchHdr) + (size_t)P->max_slots * sizeof(SweepJob) + kAlign - 1) / kAlign * kAlign;
   P->tab_bytes = off;
+}
+
+// The pool chooses the P-wave right-hand-side variant per class: an active
+// simulation whose step was built with another (a wave-speed field set
+// after admission, or a class retuned) is rebuilt with the class's.
+ads_status pool_align(ads_pool* P) {
+  for (ads_pool::Slot& sl : P->slots) {
+    if (!sl.active || sl.sim->elastic || !quadrature_ok(sl.sim->p)) continue;
+    ads_sim* s = sl.sim;
+    const int want = P->var[s->p - 1][s->mixed ? 1 : 0][s->coef != nullptr ? 1 : 0];
+    if (rhs_form_var(s->rhs_var, s->coef != nullptr) == want) continue;
+    s->rhs_var = want;
+    ads_status st = build_launches(s);
+    if (st != ADS_OK) return st;
+  }
+  return ADS_OK;
 }
 
 // Gathers the jobs of every active simulation into the merged tables.
 ads_status pool_rebuild(ads_pool* P) {
+  {
+    ads_status st = pool_align(P);
+    if (st != ADS_OK) return st;
+  }
   std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
   P->nonempty.assign(P->seq.size(), 0);
   // launches of each active simulation taken by some launch class: every
@@ -1534,7 +1593,8 @@ ads_status pool_rebuild(ads_pool* P) {
         lines += ((const SweepJob*)j.data())->nlines;
         L.p = std::max(L.p, ((const SweepJob*)j.data())->p);
       }
-      L.w = sweep_width_for(lines, kPoolMaxM, P->ncu, L.p);
+      const int wf = P->w_force[li];
+      L.w = (wf > 0 && sweep_width_fits(wf, kPoolMaxM, L.p)) ? wf : sweep_width_for(lines, kPoolMaxM, P->ncu, L.p);
       L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM, L.p) * P->ncu;
       for (auto& j : sel) {
         SweepJob* r = (SweepJob*)j.data();
@@ -1573,7 +1633,7 @@ ads_status pool_rebuild(ads_pool* P) {
     P->nonempty[li] = n == 0 ? 0
                              : (L.kind == Launch::SWEEP ? L.w * 8 + L.p
                                 : L.kind == Launch::PLANE ? (int)L.lds * 8 + L.p
-                                : L.kind == Launch::KRON ? L.p : 1);
+                                : L.kind == Launch::KRON ? L.p : 1 + L.var);
     std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
     if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
@@ -1635,10 +1695,11 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
   P->max_slots = max_slots;
   P->use_graph = use_graph != 0;
   P->slots.resize(max_slots);
-  if (const char* e = std::getenv("ADS_POOL_RHS_VAR")) {
-    int v = std::max(0, std::min(3, std::atoi(e)));
-    for (auto& r : P->var) r[0] = r[1] = v;
-  }
+  for (auto& a : P->var)
+    for (auto& b : a) {
+      b[0] = 3;   // no wave-speed field: the Kronecker form
+      b[1] = 0;   // with one: the quadrature's first tile variant
+    }
   P->ncu = ncu;
   pool_build_seq(P, ncu);
   P->arena_off = (P->tab_bytes + kAlign - 1) / kAlign * kAlign;
@@ -1689,7 +1750,7 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   ads_sim* s = nullptr;
   // elasticity takes the Kronecker form in every pool
   g_force_var = (prm->problem == ADS_ELASTIC || !quadrature_ok(prm->p))
-                    ? 3 : P->var[prm->p - 1][prm->precision == ADS_MIXED_FP32 ? 1 : 0];
+                    ? 3 : P->var[prm->p - 1][prm->precision == ADS_MIXED_FP32 ? 1 : 0][0];
   ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
   g_force_var = -1;
   if (st != ADS_OK) return st;
@@ -1774,6 +1835,144 @@ ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
     HIPCHECK(hipEventRecord(P->ev[P->nev], P->stream));
     P->nev++;
   }
+  return ADS_OK;
+}
+
+ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, int32_t cap) {
+  if (!P || !nchanged) return fail(ADS_EINVAL, "NULL argument");
+  ads_status st;
+  if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
+  *nchanged = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  // mean ms of `reps` back-to-back launches after one warm-up launch
+  auto timed = [&](auto&& launch, double* ms) -> ads_status {
+    if (launch() != hipSuccess) return fail(ADS_EDEVICE, "tuner launch failed");
+    HIPCHECK(hipEventRecord(e0, P->stream));
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r)
+      if (launch() != hipSuccess) return fail(ADS_EDEVICE, "tuner launch failed");
+    HIPCHECK(hipEventRecord(e1, P->stream));
+    HIPCHECK(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHECK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f / reps;
+    return ADS_OK;
+  };
+  // the class's gathered jobs (header + table in the host copy)
+  auto jobs_of = [&](const PoolLaunch& L, auto* tag) {
+    using J = std::remove_pointer_t<decltype(tag)>;
+    LaunchHdr h;
+    std::memcpy(&h, P->h_tab.data() + L.off, sizeof(h));
+    std::vector<J> v(h.njobs);
+    if (h.njobs) std::memcpy(v.data(), P->h_tab.data() + L.off + sizeof(LaunchHdr), h.njobs * sizeof(J));
+    return v;
+  };
+  for (size_t li = 0; li < P->seq.size(); ++li) {
+    if (!P->nonempty[li]) continue;
+    PoolLaunch& L = P->seq[li];
+    if (L.kind == Launch::RHS_P && quadrature_ok(L.p)) {
+      // right-hand side: quadrature tile variants (and the Kronecker form
+      // without a wave-speed field), timed on the batch's own jobs (they
+      // write only the right-hand-side buffers)
+      std::vector<std::string> shp;
+      for (const RhsJob& j : jobs_of(L, (RhsJob*)nullptr))
+        shp.push_back(std::to_string(j.nf[0]) + "x" + std::to_string(j.nf[1]) + "x" + std::to_string(j.nf[2]));
+      std::sort(shp.begin(), shp.end());
+      std::string key = "R" + std::to_string(li);
+      for (const std::string& x : shp) key += "/" + x;
+      int& cur = P->var[L.p - 1][L.mixed][L.coef];
+      const int before = cur;
+      auto it = P->tune_cache.find(key);
+      int best = before;
+      if (it != P->tune_cache.end()) {
+        best = it->second;
+      } else {
+        double best_ms = 1e30;
+        for (int v = 0; v < (L.coef ? 3 : 4); ++v) {
+          cur = v;
+          L.var = v;
+          L.grid = rhs_blocks_per_cu(L.p, L.mixed, v, L.coef) * P->ncu;
+          if ((st = pool_rebuild(P)) != ADS_OK) return st;
+          const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
+          double ms = 0.0;
+          if ((st = timed([&] { return launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); },
+                          &ms)) != ADS_OK)
+            return st;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+          }
+        }
+        P->tune_cache[key] = best;
+      }
+      cur = best;
+      L.var = best;
+      L.grid = rhs_blocks_per_cu(L.p, L.mixed, best, L.coef) * P->ncu;
+      if (best != before) ++*nchanged;
+      if ((st = pool_rebuild(P)) != ADS_OK) return st;
+    } else if (L.kind == Launch::SWEEP) {
+      // sweeps: tile widths, timed on a copy of the batch's table whose jobs
+      // solve in place with the plain store epilogue (no time update, no
+      // step counter): only the step's temporaries are touched
+      long long lines = 0;
+      for (const SweepJob& j : jobs_of(L, (SweepJob*)nullptr)) lines += j.nlines;
+      const std::string key = "S" + std::to_string(li) + "/" + std::to_string(lines) + "/" + std::to_string(L.p);
+      const int before = L.w;
+      auto it = P->tune_cache.find(key);
+      int best = before;
+      if (it != P->tune_cache.end()) {
+        best = it->second;
+      } else {
+        double best_ms = 1e30;
+        for (int W : {4, 8, 16}) {
+          if (!sweep_width_fits(W, kPoolMaxM, L.p)) continue;
+          P->w_force[li] = W;
+          if ((st = pool_rebuild(P)) != ADS_OK) return st;
+          std::vector<SweepJob> js = jobs_of(L, (SweepJob*)nullptr);
+          for (SweepJob& j : js) {
+            j.epi = EPI_STORE;
+            j.out = const_cast<double*>(j.in);
+            j.counter = nullptr;
+          }
+          LaunchHdr th{};
+          std::memcpy(&th, P->h_tab.data() + L.off, sizeof(th));
+          std::vector<char> buf(sizeof(LaunchHdr) + js.size() * sizeof(SweepJob));
+          std::memcpy(buf.data(), &th, sizeof(th));
+          std::memcpy(buf.data() + sizeof(LaunchHdr), js.data(), js.size() * sizeof(SweepJob));
+          HIPCHECK(hipMemcpyAsync(P->d_tab + P->tune_off, buf.data(), buf.size(), hipMemcpyHostToDevice, P->stream));
+          const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + P->tune_off);
+          double ms = 0.0;
+          if ((st = timed([&] { return launch_sweeps(h, L.grid, L.w, kPoolMaxM, L.p, P->stream); }, &ms)) != ADS_OK)
+            return st;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = W;
+          }
+        }
+        P->tune_cache[key] = best;
+      }
+      P->w_force[li] = best;
+      if (best != before) ++*nchanged;
+      if ((st = pool_rebuild(P)) != ADS_OK) return st;
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  if (host_shape)
+    for (size_t li = 0; li < P->seq.size() && (int)li < cap; ++li) {
+      const PoolLaunch& L = P->seq[li];
+      host_shape[li] = !P->nonempty[li] ? -1
+                       : (L.kind == Launch::RHS_P || L.kind == Launch::RHS_E) ? L.var
+                       : L.kind == Launch::SWEEP ? L.w : 0;
+    }
   return ADS_OK;
 }
 

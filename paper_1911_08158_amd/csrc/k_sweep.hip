@@ -686,23 +686,20 @@ static int sweep_resident(int W, int max_m, int pmax) {
   return std::max(1, std::min(n, by_lds));
 }
 
-// Tile width for a launch over `lines` lines of at most max_m unknowns on
-// ncu CUs.  Measured on 128-long lines: W = 16 (rows of 128 contiguous
-// bytes in the y/z access) beats 8 and 4 both for one 128^3 simulation and
-// for a batch of four, so it is the default; narrower tiles remain for
-// launches with too few lines to give every CU a group, and for lines too
-// long for four 16-line tiles in LDS (ADS_SWEEP_W = 4, 8 or 16 overrides
-// where it fits).
+bool sweep_width_fits(int W, int max_m, int pmax) {
+  return (W == 4 || W == 8 || W == 16) && sweep_lds_bytes(W, max_m, pmax) <= (size_t)160 * 1024;
+}
+
+// Default tile width for a launch over `lines` lines of at most max_m
+// unknowns on ncu CUs (the pool's autotuner and ads_set_launch_shape may
+// choose another).  Measured on 128-long lines: W = 16 (rows of 128
+// contiguous bytes in the y/z access) beats 8 and 4 both for one 128^3
+// simulation and for a batch of four; narrower tiles remain for launches
+// with too few lines to give every CU a group, and for lines too long for
+// four 16-line tiles in LDS.
 int sweep_width_for(long long lines, int max_m, int ncu, int pmax) {
-  static const int forced = [] {
-    const char* e = std::getenv("ADS_SWEEP_W");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 4 || v == 8 || v == 16) ? v : 0;
-  }();
-  auto fits = [&](int W) { return sweep_lds_bytes(W, max_m, pmax) <= (size_t)160 * 1024; };
-  if (forced && fits(forced)) return forced;
   for (int W : {16, 8}) {
-    if (fits(W) && lines >= (long long)ncu * kWaves * W) return W;
+    if (sweep_width_fits(W, max_m, pmax) && lines >= (long long)ncu * kWaves * W) return W;
   }
   return 4;   // fits for lines up to 728 long at p = 5 (the library accepts up to 512)
 }

@@ -11,6 +11,7 @@ namespace ads {
 // job tile counts are in groups.
 // pmax: the largest spline degree among the launch's jobs (1..5).
 int sweep_width_for(long long lines, int max_m, int ncu, int pmax);
+bool sweep_width_fits(int W, int max_m, int pmax);
 int sweep_groups(long long lines, int W);
 int sweep_blocks_per_cu(int W, int max_m, int pmax);
 hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, int pmax, hipStream_t s);

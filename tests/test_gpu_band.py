@@ -20,13 +20,6 @@ def _cuda():
         pytest.skip("no GPU")
 
 
-@pytest.fixture
-def band(monkeypatch):
-    monkeypatch.setenv("ADS_RHS_VAR", "3")
-    yield
-    monkeypatch.delenv("ADS_RHS_VAR")
-
-
 @pytest.mark.parametrize("cfg", [
     W.C1.with_(steps=5),
     W.C1.with_(nelem=(37, 41, 35), steps=4, init="noise"),      # 32 x 8 tiles with ragged tails
@@ -39,7 +32,7 @@ def band(monkeypatch):
     W.C1.with_(nelem=(2, 3, 2), steps=3, init="noise", bc="natural"),
     W.C1.with_(tau=50.0, steps=4),                               # stiff: tau^2 lambda >> 1
 ], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
-def test_band_form_matches_oracle(cfg, band):
+def test_band_form_matches_oracle(cfg):
     _cuda()
     pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
     sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0_ref))
@@ -55,7 +48,7 @@ def test_band_form_matches_oracle(cfg, band):
     sim.close()
 
 
-def test_band_form_point_source(band):
+def test_band_form_point_source():
     """p = 3 with the Ricker point source (load vector and amplitude table),
     z-chunks of a ragged mesh."""
     _cuda()
@@ -76,7 +69,7 @@ def test_band_form_point_source(band):
 @pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(20, 17, 23), tau=0.01, steps=20),
                                  W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
                          ids=["p2", "p3"])
-def test_band_form_mixed(cfg, precision, band):
+def test_band_form_mixed(cfg, precision):
     _cuda()
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
     sim, _ = gpu_sim(cfg, precision=precision, u0_full=pw.to_full(u0))
@@ -89,7 +82,7 @@ def test_band_form_mixed(cfg, precision, band):
     sim.close()
 
 
-def test_band_form_c3_fp64_and_mixed(band):
+def test_band_form_c3_fp64_and_mixed():
     """C3 size (128^3, p = 2): 10 FP64 steps compared in full; the FP32 band
     passes within 1e-6 after the same steps."""
     _cuda()
@@ -108,7 +101,7 @@ def test_band_form_c3_fp64_and_mixed(band):
         sim.close()
 
 
-def test_band_form_z_chunks_bitwise(band, monkeypatch):
+def test_band_form_z_chunks_bitwise():
     """Every output is computed by one thread with the same operation order
     whatever the z-chunking, so results are bitwise identical."""
     _cuda()
@@ -116,23 +109,20 @@ def test_band_form_z_chunks_bitwise(band, monkeypatch):
     pw, u0, _ = oracle_pwave(cfg, 0)
     outs = []
     for tz in (0, 1, 5, 40):
-        monkeypatch.setenv("ADS_RHS_TZ", str(tz))
-        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0), rhs_tz=tz)
         sim.factor()
         sim.step(cfg.steps)
         outs.append([t.cpu().numpy() for t in sim.get_state()])
         sim.close()
-    monkeypatch.delenv("ADS_RHS_TZ")
     for o in outs[1:]:
         for x, y in zip(o, outs[0]):
             assert np.array_equal(x, y)
 
 
-def test_band_form_with_field_takes_quadrature(band):
+def test_band_form_with_field_takes_quadrature():
     """A wave-speed field has no Kronecker form: with variant 3 asked for,
     such a simulation runs the quadrature kernel (variant 0), bitwise."""
     _cuda()
-    import os
     import torch
     from runners import oracle_bc
     from oracle import pwave
@@ -142,26 +132,23 @@ def test_band_form_with_field_takes_quadrature(band):
     c2 = W.wave_speed_field(*xs)
     u0 = base.project(W.initial_values(cfg, *xs))
     outs = []
-    for var in ("3", "0"):
-        os.environ["ADS_RHS_VAR"] = var
-        sim, _ = gpu_sim(cfg, u0_full=base.to_full(u0))
+    for var in (3, 0):
+        sim, _ = gpu_sim(cfg, u0_full=base.to_full(u0), rhs_var=var)
         sim.set_coefficient(torch.from_numpy(c2).cuda(), 1.5)
         sim.factor()
         sim.step(cfg.steps)
         outs.append([t.cpu().numpy() for t in sim.get_state()])
         sim.close()
-    os.environ["ADS_RHS_VAR"] = "3"
     for x, y in zip(*outs):
         assert np.array_equal(x, y)
 
 
-def test_band_form_pooled(monkeypatch):
+def test_band_form_pooled():
     """Pooled simulations on the Kronecker form (FP64 and mixed, two
     degrees, one batch) against the oracle."""
     _cuda()
     import torch
     from paper_1911_08158_amd import Pool
-    monkeypatch.setenv("ADS_POOL_RHS_VAR", "3")
     cfgs = [W.C1.with_(nelem=(18, 20, 16), tau=0.01, steps=10),
             W.C1.with_(nelem=(11, 9, 13), p=3, q=4, tau=0.01, steps=10)]
     refs = [oracle_pwave(c, c.steps) for c in cfgs]

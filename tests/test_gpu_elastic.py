@@ -26,16 +26,16 @@ def _cuda():
     W.C4.with_(nelem=(4, 6, 5), p=3, q=4, steps=3, tau=0.02, lam=2.0, mu=0.5, bc="natural"),
 ], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
 @pytest.mark.parametrize("form", ["band", "quadrature"])
-def test_elastic_matches_oracle(cfg, form, monkeypatch):
+def test_elastic_matches_oracle(cfg, form):
     """Both right-hand-side forms (Kronecker band passes, sum-factorized
     quadrature) against the oracle, step by step."""
     _cuda()
-    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
+    var = 3 if form == "band" else 0
     el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
-    sim, U0 = gpu_sim(cfg)
+    sim, U0 = gpu_sim(cfg, rhs_var=var)
     assert rel_l2(U0.cpu().numpy(), el.to_full(U0_ref)) <= TOL
     sim.close()
-    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref))
+    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref), rhs_var=var)
     sim.factor()
     u, v, _ = sim.get_state()
     assert rel_l2(v.cpu().numpy(), el.to_full(hist[0][1])) <= TOL   # U^{-1}

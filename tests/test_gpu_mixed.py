@@ -25,11 +25,10 @@ def _cuda():
                                  W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
                          ids=["p2", "p3"])
 @pytest.mark.parametrize("form", ["band", "quadrature"])
-def test_mixed_small_meshes(cfg, form, monkeypatch):
+def test_mixed_small_meshes(cfg, form):
     _cuda()
-    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
-    sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0))
+    sim, _ = gpu_sim(cfg, precision="mixed_fp32", u0_full=pw.to_full(u0), rhs_var=3 if form == "band" else 0)
     sim.factor()
     for k in range(1, cfg.steps + 1):
         sim.step(1)
@@ -43,11 +42,10 @@ def test_mixed_small_meshes(cfg, form, monkeypatch):
                                  W.C1.with_(nelem=(13, 11, 9), p=3, q=4, tau=0.01, steps=20)],
                          ids=["p2", "p3"])
 @pytest.mark.parametrize("form", ["band", "quadrature"])
-def test_bf16_inputs_small_meshes(cfg, form, monkeypatch):
+def test_bf16_inputs_small_meshes(cfg, form):
     _cuda()
-    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
     pw, u0, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
-    sim, _ = gpu_sim(cfg, precision="mixed_bf16", u0_full=pw.to_full(u0))
+    sim, _ = gpu_sim(cfg, precision="mixed_bf16", u0_full=pw.to_full(u0), rhs_var=3 if form == "band" else 0)
     sim.factor()
     for k in range(1, cfg.steps + 1):
         sim.step(1)

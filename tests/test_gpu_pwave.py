@@ -38,18 +38,18 @@ def _cuda():
     W.C1.with_(nelem=(1, 2, 1), steps=3, init="noise", bc="natural"),
 ], ids=lambda c: f"{c.nelem}-p{c.p}-tau{c.tau}-{c.bc}")
 @pytest.mark.parametrize("form", ["band", "quadrature"])
-def test_pwave_run_matches_oracle(cfg, form, monkeypatch):
+def test_pwave_run_matches_oracle(cfg, form):
     """Both right-hand-side forms: the Kronecker band passes (variant 3, the
     default) and the sum-factorized quadrature (variant 0)."""
     _cuda()
-    monkeypatch.setenv("ADS_RHS_VAR", "3" if form == "band" else "0")
+    var = 3 if form == "band" else 0
     pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
-    sim, u0 = gpu_sim(cfg)
+    sim, u0 = gpu_sim(cfg, rhs_var=var)
     # projection (projection contractions + mass sweeps)
     assert rel_l2(u0.cpu().numpy(), pw.to_full(u0_ref)) <= TOL
     sim.close()
     # time integration from identical coefficients
-    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0_ref))
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0_ref), rhs_var=var)
     sim.factor()
     # start: RHS quadrature with w = u0 and the split solve
     u, v, a = sim.get_state()
@@ -158,7 +158,7 @@ def test_checkpoint_resume_bitwise():
 
 
 @pytest.mark.parametrize("p", [2, 3])
-def test_rhs_tile_variants_bitwise_and_tuner(p, monkeypatch):
+def test_rhs_tile_variants_bitwise_and_tuner(p):
     """Every tile variant of the quadrature kernel (and z-chunking) computes
     each output with the same arithmetic, so results are bitwise identical;
     the autotuner picks one of the four variants (the Kronecker form, 3, is
@@ -169,9 +169,7 @@ def test_rhs_tile_variants_bitwise_and_tuner(p, monkeypatch):
     pw, u0, _ = oracle_pwave(cfg, 0)
     outs = []
     for var, tz in ((0, 0), (1, 0), (2, 0), (0, 5)):
-        monkeypatch.setenv("ADS_RHS_VAR", str(var))
-        monkeypatch.setenv("ADS_RHS_TZ", str(tz))
-        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0), rhs_var=var, rhs_tz=tz)
         sim.factor()
         sim.step(cfg.steps)
         outs.append([t.cpu().numpy() for t in sim.get_state()])
@@ -179,15 +177,11 @@ def test_rhs_tile_variants_bitwise_and_tuner(p, monkeypatch):
     for o in outs[1:]:
         for x, y in zip(o, outs[0]):
             assert np.array_equal(x, y)
-    monkeypatch.setenv("ADS_RHS_VAR", "3")
-    monkeypatch.setenv("ADS_RHS_TZ", "0")
-    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+    sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0), rhs_var=3, rhs_tz=0)
     sim.factor()
     sim.step(cfg.steps)
     band = [t.cpu().numpy() for t in sim.get_state()]
     sim.close()
-    monkeypatch.delenv("ADS_RHS_VAR")
-    monkeypatch.delenv("ADS_RHS_TZ")
     sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
     sim.factor()
     chosen, ms = sim.tune()
@@ -394,3 +388,29 @@ def test_wave_speed_field_in_pool_bitwise():
         for x, y in zip(s.get_state(), r):
             assert np.array_equal(x.cpu().numpy(), y)
     pool.close()
+
+
+def test_launch_shapes_explicit():
+    """ads_set_launch_shape: sweep tile widths do not change any result
+    (bitwise); unavailable variants and widths are refused."""
+    _cuda()
+    from paper_1911_08158_amd.binding import AdsError
+    cfg = W.C1.with_(nelem=(37, 20, 33), steps=3, init="noise")
+    pw, u0, _ = oracle_pwave(cfg, 0)
+    outs = []
+    for w in ((4, 4, 4), (8, 8, 8), (16, 16, 16), (0, 0, 0)):
+        sim, _ = gpu_sim(cfg, u0_full=pw.to_full(u0))
+        sim.set_launch_shape(sweep_w=w)
+        sim.factor()
+        sim.step(cfg.steps)
+        outs.append([t.cpu().numpy() for t in sim.get_state()])
+        sim.close()
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+    sim, _ = gpu_sim(cfg)
+    for bad in (dict(rhs_var=7), dict(sweep_w=(5, 0, 0)), dict(rhs_tz=-2)):
+        with pytest.raises(AdsError) as ei:
+            sim.set_launch_shape(**bad)
+        assert ei.value.status == -1
+    sim.close()
