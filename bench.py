@@ -60,9 +60,9 @@ RHS_BYTES = 32   # per free DOF: reads u, u', u'', writes R
 # launch's traffic is reported as null once its sources hash differently.
 TRAFFIC = {
     "rhs": {"sources": ["paper_1911_08158_amd/csrc/k_rhs_band.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-            "sha256": "5dd82e7d6b49be5742543004bf6a2f13a839b796f779ac0a929021f05cc652a3", "fetch_kib": 107692.8, "write_kib": 65536.0},
+            "sha256": "57502d423aae62a74a2e658c72580b90064ceaf65299ff6e92a2c91fdc23c4d5", "fetch_kib": 107695.9, "write_kib": 65536.0},
     "sweep_z": {"sources": ["paper_1911_08158_amd/csrc/k_sweep.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-                "sha256": "1c197557bef897b9898deaff4f3ce13189e606979e825b679a555dde12d4ddb7", "fetch_kib": 131253.4, "write_kib": 196608.1},
+                "sha256": "20e20094457929893f7a9af7fc7fec541d7e936348a414c6ff6b1e2b747f47bd", "fetch_kib": 131245.3, "write_kib": 196608.0},
     "fetch_scale": 2.0, "write_scale": 1.0,
     "batch": 4,
 }
