@@ -584,6 +584,11 @@ def main():
         "roofline_batched_rhs": roofline_entry(rhs_b, cfg, args.batch, band_b, True),
         "roofline_plain_fp64_rhs": roofline_entry(rhs64, cfg, 1, band_p, False),
         "gpu": gpu_info(),
+        "precision_note": "right-hand-side contractions on the VALU, not on MFMA: every contraction of the "
+                          "path is a band of width 2p+1 (dense MFMA tiles 15-38 % useful; FP32 MFMA issues at 2x "
+                          "the non-packed FP32 VALU, FP64 MFMA at 1x) and the kernels are bound by memory and "
+                          "latency; BF16 operands cannot meet 1e-6 on this stiffness action (cancellation ~40) "
+                          "without three-way splits. Mixed mode = FP32 stiffness passes on FP64 differences.",
     }
     out["accuracy"] = measure_accuracy(cfg, 100)
     # the quadrature right-hand side (a wave-speed field), FP64 and mixed
