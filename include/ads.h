@@ -210,8 +210,12 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * keeps the fastest.  P-wave: 0-2 are tile shapes of the quadrature kernel,
  * 3 is the Kronecker form (the default; not offered with a wave-speed
  * field).  Elasticity: 0 is the quadrature (FP64), 3 the Kronecker form
- * (the default).  The choice is cached per (problem, degree, precision,
- * field or none, mesh) for later simulations in the process.  *chosen
+ * (the default).  Then, per direction, it times the tile widths 4, 8 and 16
+ * lines per wave of the step's sweeps (on copies of their jobs that solve in
+ * place with a plain store: only the step's temporaries change, the state
+ * does not) and keeps the fastest.  The choices are cached per (problem,
+ * degree, precision, field or none, mesh) for later simulations in the
+ * process.  *chosen
  * receives the variant index, host_ms[v] (may be NULL; entries v < cap) the
  * mean ms of variant v.  Call after ads_factor.  ADS_ESTATE for a
  * simulation owned by a pool (the pool chooses its launch shapes, see

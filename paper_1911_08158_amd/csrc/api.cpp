@@ -1245,7 +1245,21 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
   if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
   if (s->pooled) return fail(ADS_ESTATE, "ads_tune on a pooled simulation (the pool fixes its launch classes)");
+  // choices cached per process (keyed by problem, degree, precision, field
+  // or none, mesh); the lock makes concurrent tuning from several threads safe
+  static std::mutex cache_mu;
   static std::map<std::string, int> cache;
+  auto cached = [&](const std::string& k, int* v) {
+    std::lock_guard<std::mutex> lock(cache_mu);
+    auto it = cache.find(k);
+    if (it == cache.end()) return false;
+    *v = it->second;
+    return true;
+  };
+  auto remember = [&](const std::string& k, int v) {
+    std::lock_guard<std::mutex> lock(cache_mu);
+    cache[k] = v;
+  };
   // the wave-speed field is part of the key: without one the Kronecker form
   // is a candidate, with one it is not
   const std::string key = std::string(s->elastic ? "E" : "P") + std::to_string(s->p) + "/" +
@@ -1258,43 +1272,104 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   else if (s->elastic) cands = {0, 3};
   else
     for (int v = 0; v < rhs_num_variants(s->p, s->coef != nullptr); ++v) cands.push_back(v);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  // mean ms of 5 back-to-back launches after a warm-up launch
+  auto timed = [&](auto&& launch, double* ms) -> ads_status {
+    ads_status st = launch();
+    if (st != ADS_OK) return st;
+    HIPCHECK(hipEventRecord(e0, s->stream));
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r)
+      if ((st = launch()) != ADS_OK) return st;
+    HIPCHECK(hipEventRecord(e1, s->stream));
+    HIPCHECK(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHECK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f / reps;
+    return ADS_OK;
+  };
+  ads_status st;
   int best = -1;
-  auto it = cache.find(key);
-  if (it != cache.end()) {
-    best = it->second;
-  } else {
-    hipEvent_t e0, e1;
-    HIPCHECK(hipEventCreate(&e0));
-    HIPCHECK(hipEventCreate(&e1));
+  if (!cached(key, &best)) {
     double best_ms = 1e30;
     for (int v : cands) {
       s->rhs_var = v;
-      ads_status st = build_launches(s);
-      if (st != ADS_OK) return st;
+      if ((st = build_launches(s)) != ADS_OK) return st;
       std::vector<Launch> one(1, s->step_l[0]);
-      if ((st = enqueue(s, one)) != ADS_OK) return st;
-      HIPCHECK(hipEventRecord(e0, s->stream));
-      const int reps = 5;
-      for (int r = 0; r < reps; ++r)
-        if ((st = enqueue(s, one)) != ADS_OK) return st;
-      HIPCHECK(hipEventRecord(e1, s->stream));
-      HIPCHECK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-      double per = ms / reps;
+      double per = 0.0;
+      if ((st = timed([&] { return enqueue(s, one); }, &per)) != ADS_OK) return st;
       if (host_ms && v < cap) host_ms[v] = per;
       if (per < best_ms) {
         best_ms = per;
         best = v;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    cache[key] = best;
+    remember(key, best);
   }
   s->rhs_var = best;
-  ads_status st = build_launches(s);
-  if (st != ADS_OK) return st;
+  // sweep tile widths, per direction: the step's sweeps of that direction,
+  // timed on copies of their jobs that solve in place with a plain store (no
+  // time update, no step counter), placed after the job arena's tables, so
+  // that only the step's temporaries change
+  for (int d = 0; d < 3; ++d) {
+    if ((st = build_launches(s)) != ADS_OK) return st;
+    bool has = false;
+    for (const Launch& l : s->step_l) has = has || (l.kind == Launch::SWEEP && l.dir == d);
+    if (!has) continue;
+    const std::string wkey = key + "/v" + std::to_string(best) + "/W" + std::to_string(d);
+    int bw = 0;
+    if (!cached(wkey, &bw)) {
+      double best_ms = 1e30;
+      for (int W : {4, 8, 16}) {
+        if (!sweep_width_fits(W, max_m(s), s->p)) continue;
+        s->sweep_w[d] = W;
+        if ((st = build_launches(s)) != ADS_OK) return st;
+        const size_t tail = (s->arena.host.size() + kAlign - 1) / kAlign * kAlign;
+        if (tail + sizeof(LaunchHdr) + sizeof(SweepJob) > s->arena.cap) break;
+        double tot = 0.0;
+        for (const Launch& l : s->step_l) {
+          if (l.kind != Launch::SWEEP || l.dir != d) continue;
+          SweepJob j;
+          std::memcpy(&j, l.host_jobs.data(), sizeof(j));
+          j.epi = EPI_STORE;
+          j.out = const_cast<double*>(j.in);
+          j.counter = nullptr;
+          j.tile0 = 0;
+          LaunchHdr h{};
+          h.njobs = 1;
+          h.total_tiles = j.ntiles;
+          std::vector<char> buf(sizeof(LaunchHdr) + sizeof(SweepJob));
+          std::memcpy(buf.data(), &h, sizeof(h));
+          std::memcpy(buf.data() + sizeof(LaunchHdr), &j, sizeof(j));
+          HIPCHECK(hipMemcpyAsync(s->arena.d_base + tail, buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream));
+          const LaunchHdr* dh = (const LaunchHdr*)(s->arena.d_base + tail);
+          double ms = 0.0;
+          auto go = [&]() -> ads_status {
+            const hipError_t e = launch_sweeps(dh, l.total_tiles, l.w, l.max_m, l.p, s->stream);
+            return e == hipSuccess ? ADS_OK : fail(ADS_EDEVICE, std::string("tuner launch: ") + hipGetErrorString(e));
+          };
+          if ((st = timed(go, &ms)) != ADS_OK) return st;
+          tot += ms;
+        }
+        if (tot < best_ms) {
+          best_ms = tot;
+          bw = W;
+        }
+      }
+      remember(wkey, bw);
+    }
+    s->sweep_w[d] = bw;
+  }
+  if ((st = build_launches(s)) != ADS_OK) return st;
   HIPCHECK(hipStreamSynchronize(s->stream));
   *chosen = best;
   return ADS_OK;

@@ -33,8 +33,13 @@ def test_mixed_small_meshes(cfg, form):
     for k in range(1, cfg.steps + 1):
         sim.step(1)
         u, _, _ = sim.get_state()
-        e = rel_l2(u.cpu().numpy(), pw.to_full(hist[k][0]))
-        assert e <= 1e-6, (k, e)
+        ref = pw.to_full(hist[k][0])
+        e = rel_l2(u.cpu().numpy(), ref)
+        # pointwise as well: these meshes end in ragged tiles (20 x 17 x 23
+        # against 32 x 8 and 14 x 14 columns), where a localized error would
+        # hide in the global norm
+        m = max_rel(u.cpu().numpy(), ref)
+        assert e <= 1e-6 and m <= 1e-5, (k, e, m)
     sim.close()
 
 
