@@ -362,6 +362,22 @@ def measure_elastic(cfg, steps, warmup, precision="fp64"):
     }
 
 
+def measure_grid_sweep(sizes, steps, warmup):
+    """The paper's cost claim (Appendix: three sets of 1D banded solves, O(N)
+    per step): DOF-steps/s of one FP64 P-wave simulation at p = 2 across
+    mesh sizes; flat throughput at large N is the O(N) behaviour (small
+    meshes are bound by launch latency instead)."""
+    import workloads as W
+    out = []
+    for e in sizes:
+        cfg = W.C3.with_(nelem=(e, e, e), precision="fp64")
+        r = measure_plain(cfg, steps, warmup, tune=True)
+        out.append({"elements": e, "dofs": cfg.dofs(), "dof_steps_per_s": r["dof_steps_per_s"],
+                    "ms_per_step": r["ms_per_step"], "rhs_variant": r["rhs_variant"]})
+    return {"workload": "P-wave p=2 tau=2e-3, one FP64 simulation per mesh (E^3 elements, (E+2)^3 DOFs)",
+            "points": out}
+
+
 def measure_serving_plain(reqs):
     """The same request stream served plainly: one simulation at a time in
     arrival order (FIFO), FP64 right-hand side, per-kernel launches (no pool,
@@ -513,7 +529,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature"], default=None,
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature", "grid"],
+                    default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -545,6 +562,10 @@ def main():
         for prec in ("fp64", "mixed_fp32"):
             q = measure_plain(cfg.with_(precision=prec), args.steps, args.warmup, precision=prec, coef=True)
             print(json.dumps({"form": f"quadrature_{prec}", **q}), flush=True)
+        return
+    if args.only == "grid":
+        print(json.dumps({"form": "grid_sweep", **measure_grid_sweep((32, 48, 64, 96, 128, 192, 256), 50, 5)}),
+              flush=True)
         return
     if args.only == "accuracy":
         print(json.dumps({"form": "accuracy", **measure_accuracy(cfg, args.steps)}), flush=True)
@@ -607,6 +628,7 @@ def main():
     out["c2_plain_fp64"] = {"workload": f"P-wave 64^3 elements p=3 ({c2.n[0]}^3 DOFs) tau={c2.tau}, point source, "
                                         "FP64, one simulation", **measure_plain(c2, args.steps, args.warmup)}
     out["c1_latency"] = measure_small_latency(W.C1, 200, 20)
+    out["grid_sweep"] = measure_grid_sweep((32, 48, 64, 96, 128, 192, 256), 50, 5)
     out["bf16_inputs"] = {"workload": "P-wave 128^3 elements p=2, one simulation, right-hand side on the predictor "
                                       "rounded to BF16 plus a correction pass on the FP64 remainder (FP32 "
                                       "stiffness passes; two right-hand-side launches per step)",
