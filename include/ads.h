@@ -84,8 +84,10 @@ typedef enum { ADS_BC_DIRICHLET0 = 0, ADS_BC_NATURAL = 1 } ads_bc;
 /* Problem statement (Section 2 for the P-wave, Section 5 for elasticity):
  * unit cube, nelem[d] uniform elements per direction (x, y, z), spline
  * degree p with open uniform knots and maximal continuity C^{p-1}, nquad
- * Gauss points per element and direction (0 means p+1; only p+1 is
- * supported), time step tau, density rho and Lame constants lambda, mu
+ * Gauss points per element and direction (0 means p+1, exact for these
+ * integrands; p+2 and p+3 give the same matrices up to rounding and are
+ * taken by the Kronecker-form right-hand sides only: no wave-speed field,
+ * no quadrature variant, not in pools), time step tau, density rho and Lame constants lambda, mu
  * (elasticity only; the P-wave has unit wave speed).  nelem[2] = 0 selects
  * the two-dimensional P-wave on the unit square, the setting of the paper's
  * exposition (Section 2: K = K_x (x) M_y + M_x (x) K_y, split left-hand side
@@ -97,7 +99,8 @@ typedef struct {
   int32_t nelem[3];    /* >= 1 each; nelem[2] = 0: two-dimensional P-wave */
   int32_t p;           /* 1 to 5 (the quadrature right-hand side, and with
                           it a wave-speed field, needs 2 or 3)          */
-  int32_t nquad;       /* 0 or p+1      */
+  int32_t nquad;       /* 0 (= p+1) or p+1 .. p+3 (above p+1: Kronecker
+                          forms only, not in pools)                      */
   int32_t bc;          /* ads_bc        */
   int32_t precision;   /* ads_precision */
   double tau;          /* > 0           */

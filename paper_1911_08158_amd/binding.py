@@ -82,7 +82,7 @@ class Params(ctypes.Structure):
     def gauss_numel(self):
         """Gauss points of one component ([(E_z q)][(E_y q)][(E_x q)]; the
         flat z-direction of a two-dimensional problem has one element)."""
-        q = int(self.p) + 1
+        q = int(self.nquad) or int(self.p) + 1
         return int(np.prod([max(int(self.nelem[d]), 1) * q for d in range(3)]))
 
 
@@ -162,7 +162,8 @@ def quad_points(prm: Params, d: int) -> np.ndarray:
     ne = int(prm.nelem[d])
     if d == 2 and ne == 0:   # two-dimensional: the flat direction has one element
         ne = 1
-    out = np.zeros(ne * (prm.p + 1))
+    q = int(prm.nquad) or int(prm.p) + 1   # the library writes ne * q points
+    out = np.zeros(ne * q)
     _check(load_library().ads_quad_points(byref(prm), d, out.ctypes.data))
     return out
 

@@ -215,7 +215,8 @@ int free_count(const ads_params& P, int d) {
   return P.nelem[d] + P.p - (P.bc == ADS_BC_NATURAL ? 0 : 2);
 }
 Tables1D tables_of(const ads_params& P, int d) {
-  return (d == 2 && flat_z(P)) ? make_tables_flat(P.p, P.p + 1) : make_tables(P.nelem[d], P.p, P.p + 1);
+  const int q = P.nquad > 0 ? P.nquad : P.p + 1;
+  return (d == 2 && flat_z(P)) ? make_tables_flat(P.p, q) : make_tables(P.nelem[d], P.p, q);
 }
 
 bool valid_params(const ads_params* prm, std::string& why) {
@@ -238,8 +239,8 @@ bool valid_params(const ads_params* prm, std::string& why) {
     why = "spline degree p must be in [1, 5]";
     return false;
   }
-  if (prm->nquad != 0 && prm->nquad != prm->p + 1) {
-    why = "nquad must be 0 or p+1";
+  if (prm->nquad != 0 && (prm->nquad < prm->p + 1 || prm->nquad > prm->p + 3)) {
+    why = "nquad must be 0 (p+1) or in [p+1, p+3]";
     return false;
   }
   if (prm->bc != ADS_BC_DIRICHLET0 && prm->bc != ADS_BC_NATURAL) {
@@ -275,7 +276,7 @@ bool valid_params(const ads_params* prm, std::string& why) {
 void geometry(ads_sim* s) {
   const ads_params& P = s->prm;
   s->p = P.p;
-  s->q = P.p + 1;
+  s->q = P.nquad > 0 ? P.nquad : P.p + 1;
   s->P = P.p + 1;
   s->elastic = P.problem == ADS_ELASTIC;
   s->ncomp = s->elastic ? 3 : 1;
@@ -436,6 +437,7 @@ SweepJob plain_epi() {
 void fill_tables(const ads_sim* s, RhsJob& J) {
   for (int d = 0; d < 3; ++d) {
     J.tab[d] = s->d_tab[d];
+    J.band[d] = s->d_tab[d] + (4ll * s->E[d] * s->q * s->P + (long long)s->E[d] * s->q + 2ll * s->E[d] * s->P * s->P);
     J.E[d] = s->E[d];
     J.nf[d] = s->nf[d];
     J.off[d] = s->off[d];
@@ -512,12 +514,15 @@ void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident =
 int rhs_form_var(int var, bool coef) { return (coef && var == 3) ? 0 : var; }
 
 // The quadrature kernels (P-wave tile variants 0-2, elasticity variant 0)
-// are instantiated for p = 2 and 3; every degree has the Kronecker form.
+// are instantiated for p = 2 and 3 with q = p+1 Gauss points; every degree
+// and Gauss rule has the Kronecker form (its band matrices are assembled on
+// the host with the simulation's rule).
 bool quadrature_ok(int p) { return p == 2 || p == 3; }
+bool quadrature_ok(const ads_sim* s) { return quadrature_ok(s->p) && s->q == s->p + 1; }
 // Variant of an FP64 right-hand side used by the start and the energy
 // diagnostic: the quadrature's variant 0 where it exists, else the
 // Kronecker form.
-int fp64_aux_var(const ads_sim* s) { return quadrature_ok(s->p) ? 0 : 3; }
+int fp64_aux_var(const ads_sim* s) { return quadrature_ok(s) ? 0 : 3; }
 
 RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift, int mixed, int var) {
   RhsJob J{};
@@ -879,7 +884,7 @@ ads_status ads_project_scratch_bytes(const ads_params* prm, size_t* bytes) {
   std::string why;
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
   if (!bytes) return fail(ADS_EINVAL, "bytes is NULL");
-  const long long q = prm->p + 1;
+  const long long q = prm->nquad > 0 ? prm->nquad : prm->p + 1;
   const long long gz = (flat_z(*prm) ? 1 : prm->nelem[2]) * q, gy = prm->nelem[1] * q;
   const long long fx = free_count(*prm, 0), fy = free_count(*prm, 1);
   *bytes = (size_t)(gz * gy * fx + gz * fy * fx) * sizeof(double) + 2 * kAlign;
@@ -908,7 +913,7 @@ ads_status ads_create(const ads_params* prm, void* ws, size_t bytes, void* strea
   s->ncu = ncu;
   if (g_force_var >= 0) s->rhs_var = g_force_var;   // simulations created by a pool
   if (s->elastic && s->rhs_var != 3) s->rhs_var = 0;  // elasticity: quadrature (0) or Kronecker form (3)
-  if (!quadrature_ok(s->p)) s->rhs_var = 3;            // degrees without a quadrature kernel
+  if (!quadrature_ok(s)) s->rhs_var = 3;               // degrees and rules without a quadrature kernel
   Carver c{(char*)ws};
   carve(s, c);
   // host tables and matrices
@@ -1141,8 +1146,8 @@ ads_status ads_energy(ads_sim* s, double* host_energy) {
 ads_status ads_set_coefficient(ads_sim* s, const double* dev_c2, double c2ref) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   if (s->elastic) return fail(ADS_EINVAL, "the wave-speed field is a P-wave parameter");
-  if (!quadrature_ok(s->p))
-    return fail(ADS_EINVAL, "a wave-speed field needs the quadrature right-hand side (p = 2 or 3)");
+  if (!quadrature_ok(s))
+    return fail(ADS_EINVAL, "a wave-speed field needs the quadrature right-hand side (p = 2 or 3, q = p+1)");
   if (!(c2ref > 0.0) || !std::isfinite(c2ref)) return fail(ADS_EINVAL, "c2ref must be positive and finite");
   if (s->factored) return fail(ADS_ESTATE, "ads_set_coefficient after ads_factor");
   s->coef = dev_c2;
@@ -1221,7 +1226,7 @@ ads_status ads_set_launch_shape(ads_sim* s, int32_t rhs_var, int32_t rhs_tz, con
   if (s->pooled) return fail(ADS_ESTATE, "launch shapes of a pooled simulation are the pool's");
   int var = s->rhs_var;
   if (rhs_var >= 0) {
-    const bool ok = rhs_var == 3 || (quadrature_ok(s->p) && (s->elastic ? rhs_var == 0 : rhs_var <= 2));
+    const bool ok = rhs_var == 3 || (quadrature_ok(s) && (s->elastic ? rhs_var == 0 : rhs_var <= 2));
     if (!ok) return fail(ADS_EINVAL, "right-hand-side variant not available for this problem and degree");
     var = rhs_var;
   }
@@ -1268,7 +1273,7 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   // candidates: P-wave tile variants 0-2 of the quadrature and the Kronecker
   // form 3 (without a wave-speed field); elasticity quadrature 0 and 3
   std::vector<int> cands;
-  if (!quadrature_ok(s->p)) cands = {3};
+  if (!quadrature_ok(s)) cands = {3};
   else if (s->elastic) cands = {0, 3};
   else
     for (int v = 0; v < rhs_num_variants(s->p, s->coef != nullptr); ++v) cands.push_back(v);
@@ -1801,6 +1806,8 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
     if (free_count(*prm, d) > kPoolMaxM) return fail(ADS_EINVAL, "pooled meshes: <= 128 free coefficients");
   if (prm->precision == ADS_MIXED_BF16)
     return fail(ADS_EINVAL, "ADS_MIXED_BF16 (two right-hand-side passes) is not pooled");
+  if (prm->nquad != 0 && prm->nquad != prm->p + 1)
+    return fail(ADS_EINVAL, "pooled simulations use q = p+1 Gauss points");
   int free_slot = -1;
   for (int i = 0; i < P->max_slots; ++i)
     if (!P->slots[i].sim) {

@@ -124,6 +124,7 @@ struct RhsJob {
   const double* coef;     // P-wave: c^2 at every Gauss point [Ez q][Ey q][Ex q], or null (c^2 = 1)
   double lam, mu;         // elasticity Lame constants
   const double* tab[3];   // per direction: N, D [E][q][P], W [E][q], W*N, W*D [E][q][P], M_e, K_e [E][P][P]
+  const double* band[3];  // per direction: the assembled bands M, K (elasticity: G, G^T) [nf][2p+1] after them
   int E[3], nf[3], off[3];
   int tiles[3];           // tiles along x, y, and z-chunks
   int TZ;                 // owned z-coefficients per chunk

@@ -68,19 +68,14 @@ __device__ __forceinline__ float bf16_round_band(float x) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
-// Assembled 1D matrices of direction d after the element tables of that
-// direction: M [nf][2p+1], then K [nf][2p+1]; entry (i, j) at
-// i*(2p+1) + (j - i + p), zero where j leaves the free range.  In x and y
-// the diagonal slot of K holds the row sum s_i instead, for the difference
-// form
+// Assembled 1D matrices of direction d (RhsJob::band[d], after the element
+// tables of that direction): M [nf][2p+1], then K [nf][2p+1]; entry (i, j)
+// at i*(2p+1) + (j - i + p), zero where j leaves the free range.  In x and
+// y the diagonal slot of K holds the row sum s_i instead, for the
+// difference form
 //   (K v)_i = s_i v_i + sum_{j != i} K_ij (v_j - v_i),
 // in which FP32-rounded entries still annihilate constants (s_i is zero
 // away from eliminated boundary coefficients); z keeps K (FP64 pass).
-template <int p>
-__device__ __forceinline__ const double* band_table(const double* tab, int E) {
-  constexpr int P = p + 1, Q = p + 1;
-  return tab + (4ll * E * Q * P + (long long)E * Q + 2ll * E * P * P);
-}
 
 // waves per SIMD: four at p <= 2 (FP32 at five spills registers and runs
 // slower), four (FP32) or three (FP64) at p = 3, two above
@@ -133,8 +128,8 @@ __global__ __launch_bounds__(BNT, p <= 2 ? 4 : (p == 3 ? (sizeof(T) == 4 ? 4 : 3
     T kx[B], ky[B], my[B];
     double mx[B], myd[B];
     {
-      const gmem<double>* bx = gview(band_table<p>(J.tab[0], J.E[0]));
-      const gmem<double>* by = gview(band_table<p>(J.tab[1], J.E[1]));
+      const gmem<double>* bx = gview(J.band[0]);
+      const gmem<double>* by = gview(J.band[1]);
       const int gx = x0 + lx, gy = y0 + ly;
       const bool vx = gx < nfx, vy = gy < nfy;
       const long long ix = (long long)(vx ? gx : 0) * B, iy = (long long)(vy ? gy : 0) * B;
@@ -151,7 +146,7 @@ __global__ __launch_bounds__(BNT, p <= 2 ? 4 : (p == 3 ? (sizeof(T) == 4 ? 4 : 3
     // k < 2p+1 holds M_z(s-p+k, s), lane 2p+1+k holds K_z(s-p+k, s) (zero
     // outside the free range); loaded with the layer's predictor and read
     // back with readlane
-    const gmem<double>* bzg = gview(band_table<p>(J.tab[2], J.E[2]));
+    const gmem<double>* bzg = gview(J.band[2]);
     const int zlane = threadIdx.x & 63;
     const int zk = zlane < B ? zlane : zlane - B;
     const long long zoff = zlane < B ? 0ll : (long long)nfz * B;

@@ -63,13 +63,12 @@ __device__ __forceinline__ int find_job_elb(const RhsJob* jobs, int njobs, int t
   return lo;
 }
 
-// Band matrices of direction d after its element tables: M, K, G, G^T,
-// each [nf][2p+1] with entry (i, j) at i*(2p+1) + (j - i + p); in x and y
-// the diagonal slots of K, G and G^T hold their row sums.
+// Band matrices of direction d (RhsJob::band[d]): M, K, G, G^T, each
+// [nf][2p+1] with entry (i, j) at i*(2p+1) + (j - i + p); in x and y the
+// diagonal slots of K, G and G^T hold their row sums.
 template <int p>
-__device__ __forceinline__ const double* el_band_table(const double* tab, int E, int nf, int op) {
-  constexpr int P = p + 1, Q = p + 1;
-  return tab + (4ll * E * Q * P + (long long)E * Q + 2ll * E * P * P) + (long long)op * nf * (2 * p + 1);
+__device__ __forceinline__ const double* el_band_table(const double* band, int nf, int op) {
+  return band + (long long)op * nf * (2 * p + 1);
 }
 
 // Band row b applied in difference form to the column c (stride ETX):
@@ -138,19 +137,19 @@ __global__ __launch_bounds__(ElBandGeom<p>::ENT, 2) void rhs_elastic_band_kernel
       const int op = k / (B * ETX), r = k - op * (B * ETX);
       const int c = r / ETX, col = r - c * ETX;
       const int gx = x0 + col;
-      (&Xb[0][0][0])[k] = gx < nfx ? gview(el_band_table<p>(J.tab[0], J.E[0], nfx, op))[(long long)gx * B + c] : 0.0;
+      (&Xb[0][0][0])[k] = gx < nfx ? gview(el_band_table<p>(J.band[0], nfx, op))[(long long)gx * B + c] : 0.0;
     }
     for (int k = tid; k < 4 * ETY * B; k += ENT) {
       const int op = k / (ETY * B), r = k - op * (ETY * B);
       const int row = r / B, c = r - row * B;
       const int gy = y0 + row;
-      (&Yb[0][0][0])[k] = gy < nfy ? gview(el_band_table<p>(J.tab[1], J.E[1], nfy, op))[(long long)gy * B + c] : 0.0;
+      (&Yb[0][0][0])[k] = gy < nfy ? gview(el_band_table<p>(J.band[1], nfy, op))[(long long)gy * B + c] : 0.0;
     }
     // z-band entries of a source layer s: lane op*B + k holds factor op's
     // entry (s-p+k, s), op = M, K, G, G^T (zero outside the free range)
     const int zlane = threadIdx.x & 63;
     const int zop = zlane / B, zk = zlane - zop * B;
-    const gmem<double>* bzg = gview(el_band_table<p>(J.tab[2], J.E[2], nfz, zop < 4 ? zop : 0));
+    const gmem<double>* bzg = gview(el_band_table<p>(J.band[2], nfz, zop < 4 ? zop : 0));
     double ampv = 0.0;
     if (J.load != nullptr && J.amp != nullptr) {
       long long ai = (long long)(*gview(J.counter)) + J.amp_shift;

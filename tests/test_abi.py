@@ -36,7 +36,7 @@ def _params(**kw):
     return Params.of(**d)
 
 
-@pytest.mark.parametrize("bad", [dict(p=0), dict(p=6), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
+@pytest.mark.parametrize("bad", [dict(p=0), dict(p=6), dict(q=2), dict(q=6), dict(tau=0.0), dict(tau=-1.0), dict(nelem=(0, 4, 4)),
                                  dict(problem="elastic", mu=0.0), dict(problem="elastic", rho=-1.0),
                                  dict(problem="elastic", precision="mixed_bf16"),
                                  dict(nelem=(600, 4, 4)), dict(bc=2), dict(bc=-1),
@@ -125,3 +125,15 @@ def test_binding_rejects_bad_tensors():
     assert e.full_numel == 3 * 7 * 8 * 9
     f = _params(nelem=(4, 5, 0), p=2)
     assert f.full_numel == 6 * 7 and f.gauss_numel == 12 * 15 * 3
+
+
+def test_gauss_rules_above_p_plus_one_accepted(lib):
+    """nquad in [p+1, p+3] is accepted; the projection data grid and the
+    workspace follow the rule."""
+    from paper_1911_08158_amd import binding
+    a = _params(q=3)
+    b = _params(q=5)
+    assert b.gauss_numel * 27 == a.gauss_numel * 125
+    assert binding.workspace_bytes(b) > binding.workspace_bytes(a)
+    xs = binding.quad_points(b, 0)
+    assert xs.size == 4 * 5 and np.all(np.diff(xs) > 0)

@@ -128,3 +128,32 @@ def test_pool_mixes_all_degrees_bitwise():
         for x, y in zip(got, r):
             assert np.array_equal(x, y), (c.p, c.problem, float(np.abs(x - y).max()))
     pool.close()
+
+
+@pytest.mark.parametrize("cfg", [
+    W.C1.with_(nelem=(9, 7, 8), p=2, q=4, tau=0.02, steps=4),
+    W.C1.with_(nelem=(7, 6, 9), p=3, q=6, tau=0.02, steps=3, bc="natural"),
+    W.C4.with_(nelem=(5, 6, 4), p=2, q=5, steps=3, tau=0.02, lam=0.8, mu=0.6),
+], ids=lambda c: f"{c.problem}-p{c.p}-q{c.q}")
+def test_gauss_rules_above_p_plus_one(cfg):
+    """More Gauss points than p+1 (exact either way): the Kronecker form with
+    bands assembled on the host from that rule, against the oracle with the
+    same rule; the projection samples the finer grid."""
+    if cfg.problem == "elastic":
+        el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
+        ref_full, pick = el.to_full, (lambda h: h[0])
+        u0_ref = U0_ref
+    else:
+        pw, u0_ref, (_, hist) = oracle_pwave(cfg, cfg.steps, history=True)
+        ref_full, pick = pw.to_full, (lambda h: h[0])
+    sim, u0 = gpu_sim(cfg)
+    assert rel_l2(u0.cpu().numpy(), ref_full(u0_ref)) <= TOL
+    sim.close()
+    sim, _ = gpu_sim(cfg, u0_full=ref_full(u0_ref))
+    sim.factor()
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u = sim.get_state()[0].cpu().numpy()
+        e = rel_l2(u, ref_full(pick(hist[k])))
+        assert e <= TOL, (k, e)
+    sim.close()
