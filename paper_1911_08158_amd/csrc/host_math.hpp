@@ -4,6 +4,7 @@
 // O(n) factorization).
 #pragma once
 
+#include <cstddef>
 #include <vector>
 
 namespace ads {

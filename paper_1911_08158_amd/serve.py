@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import json
 import time
 from typing import Callable, List, Optional
 
@@ -44,10 +45,23 @@ class RequestRecord:
     step_ms: List[float] = dataclasses.field(default_factory=list)
     result: Optional[object] = None
 
+    def as_json(self) -> dict:
+        """Per-request metrics record: times in seconds after the start of
+        the loop, per-step latency percentiles in ms, DOF-steps served."""
+        def num(x):
+            return None if x is None or x != x else float(x)
+        ms = np.asarray(self.step_ms)
+        return {"rid": self.rid, "status": self.status, "error": self.error,
+                "arrival_s": num(self.arrival), "admitted_s": num(self.admitted),
+                "finished_s": num(self.finished), "steps": self.steps,
+                "dof_steps": int(self.steps * self.dofs),
+                "step_ms_p50": float(np.percentile(ms, 50)) if ms.size else None,
+                "step_ms_p99": float(np.percentile(ms, 99)) if ms.size else None}
+
 
 def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable,
           keep_results: bool = False, clock=time.perf_counter, max_wall: float = 600.0,
-          check_every: int = 0, sleep=time.sleep):
+          check_every: int = 0, sleep=time.sleep, records_path: Optional[str] = None):
     """Run the request stream to completion.
 
     requests: objects with ``rid``, ``arrival`` (seconds after start), ``cfg``
@@ -55,7 +69,9 @@ def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable
     admitted slot (initial state, load, factor); steps_of(req) / dofs_of(req)
     give the step count and the DOFs counted by the throughput metric.
     check_every > 0: every that many steps of a simulation its state is
-    checked for non-finite values.  Returns (records, stats).
+    checked for non-finite values.  records_path: one JSON line per request
+    (RequestRecord.as_json) is written there at the end.  Returns
+    (records, stats).
     """
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     recs = {r.rid: RequestRecord(r.rid, r.arrival) for r in requests}
@@ -153,4 +169,8 @@ def serve(pool, requests, setup: Callable, steps_of: Callable, dofs_of: Callable
         "request_s_p50": float(np.percentile(req_lat, 50)) if req_lat.size else None,
         "request_s_p99": float(np.percentile(req_lat, 99)) if req_lat.size else None,
     }
+    if records_path is not None:
+        with open(records_path, "w") as fh:
+            for r in recs.values():
+                fh.write(json.dumps(r.as_json()) + "\n")
     return list(recs.values()), stats

@@ -176,3 +176,18 @@ def test_slots_bound_the_batch():
     assert all(r.status == "done" for r in recs.values())
     # at most two in flight: the third starts after one of the first two ends
     assert recs[2].admitted >= min(recs[0].finished, recs[1].finished)
+
+
+def test_per_request_records(tmp_path):
+    import json
+    path = str(tmp_path / "records.jsonl")
+    pool = FakePool(100, 8)
+    reqs = [Req(0, 0.0, Cfg(40, 3)), Req(1, 0.001, Cfg(500, 2)), Req(2, 0.002, Cfg(40, 2))]
+    clk = Clock()
+    recs, _ = serve(pool, reqs, setup=lambda sim, cfg: None, steps_of=lambda r: r.cfg.steps,
+                    dofs_of=lambda r: 10, clock=clk, sleep=clk.sleep, max_wall=1e4, records_path=path)
+    lines = [json.loads(x) for x in open(path)]
+    assert [x["rid"] for x in lines] == [0, 1, 2]
+    assert [x["status"] for x in lines] == ["done", "rejected", "done"]
+    assert lines[0]["dof_steps"] == 30 and lines[0]["steps"] == 3 and lines[0]["step_ms_p99"] == 1.0
+    assert lines[1]["admitted_s"] is None and lines[1]["dof_steps"] == 0
