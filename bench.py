@@ -49,9 +49,9 @@ def rhs_flops_per_element(p, q=None):
 
 
 SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_xy": 16,   # per free DOF; x and y in one in-plane launch: 16
-               "sweep_z": 56}                                 # z fused with the Newmark update
+               "sweep_z": 56}   # z fused with the Newmark update: reads the input and (w, u', u''), writes them
 
-RHS_BYTES = 32   # per free DOF: reads u, u', u'', writes R
+RHS_BYTES = 16   # per free DOF: reads the predictor u + tau u' + tau^2/4 u'', writes R
 
 # HBM traffic per launch of the batched step's kernels (4 simulations), from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by what the same counters
@@ -572,6 +572,7 @@ def main():
         return
     plain = measure_plain(cfg.with_(precision="fp64"), args.steps, args.warmup)
     batched = measure_batched(cfg.with_(precision="mixed_fp32"), args.batch, args.steps, args.warmup)
+    batched64 = measure_batched(cfg.with_(precision="fp64"), args.batch, args.steps, args.warmup, precision="fp64")
     band_b = batched["rhs_variant"] == 3
     dom = max(batched["kernels"], key=lambda k: k["ms"])
     roof = roofline_entry(dom, cfg, args.batch, band_b, True)
@@ -599,6 +600,7 @@ def main():
         "p50_step_ms": batched["step_ms_p50"],
         "p99_step_ms": batched["step_ms_p99"],
         "batched_mixed": batched,
+        "batched_fp64": batched64,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": batched["dof_steps_per_s"] / plain["dof_steps_per_s"],
         "roofline": roof,
@@ -609,7 +611,9 @@ def main():
                           "path is a band of width 2p+1 (dense MFMA tiles 15-38 % useful; FP32 MFMA issues at 2x "
                           "the non-packed FP32 VALU, FP64 MFMA at 1x) and the kernels are bound by memory and "
                           "latency; BF16 operands cannot meet 1e-6 on this stiffness action (cancellation ~40) "
-                          "without three-way splits. Mixed mode = FP32 stiffness passes on FP64 differences.",
+                          "without three-way splits. Mixed mode = FP32 stiffness passes on FP64 differences; "
+                          "non-packed FP32 vector FMAs issue at the FP64 rate on gfx950, so the FP64 Kronecker "
+                          "form (plain band, one FMA per entry) runs as fast (batched_fp64).",
     }
     out["accuracy"] = measure_accuracy(cfg, 100)
     # the quadrature right-hand side (a wave-speed field), FP64 and mixed

@@ -205,7 +205,13 @@ ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
  * before ads_factor. */
 ads_status ads_energy(ads_sim* sim, double* host_energy);
 
-/* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor. */
+/* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor.
+ * P-wave: the steps advance (w, u', u''), w = u + tau u' + tau^2/4 u'' the
+ * predictor of the next step (ADS_SCHEME_LITERAL: w = u + tau u'), so that
+ * each step's right-hand side reads one field; the z-sweep forms
+ * u_{n+1} = w_n + tau^2/4 u''_{n+1} and the next w.  u is formed from
+ * (w, u', u'') when it is read (ads_get_state, ads_energy,
+ * ads_check_finite), w from (u, u', u'') when the state is set. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 
 /* Autotuner of the right-hand side (measurement-driven): times every
@@ -246,6 +252,20 @@ ads_status ads_get_state(ads_sim* sim, double* dev_u, double* dev_v, double* dev
  * P-wave: u, u', u''; elasticity: U^n, U^{n-1}. */
 ads_status ads_set_state(ads_sim* sim, const double* dev_u, const double* dev_v,
                          const double* dev_a, int64_t step);
+
+/* Checkpoint: the time-stepping state itself (full layout; asynchronous on
+ * the sim's stream), so that a restored simulation continues bitwise as the
+ * original would (a round trip through ads_get_state / ads_set_state agrees
+ * to rounding only, since the P-wave u is formed from the stepping state).
+ * P-wave: dev_s0 = w = u + tau u' + tau^2/4 u'' (ADS_SCHEME_LITERAL:
+ * u + tau u'), dev_s1 = u', dev_s2 = u''; elasticity: dev_s0 = U^n,
+ * dev_s1 = U^{n-1}, dev_s2 ignored.  Every pointer but dev_s2 of
+ * elasticity must be non-NULL.  Save: ADS_ESTATE before ads_factor.  Load
+ * restores the state and the step index; stepping continues without
+ * ads_factor if the sim was factored (the load may precede ads_factor). */
+ads_status ads_checkpoint_save(ads_sim* sim, double* dev_s0, double* dev_s1, double* dev_s2);
+ads_status ads_checkpoint_load(ads_sim* sim, const double* dev_s0, const double* dev_s1, const double* dev_s2,
+                               int64_t step);
 
 /* Step index (number of steps taken since the start). Synchronizes. */
 ads_status ads_get_step(ads_sim* sim, int64_t* step);

@@ -115,6 +115,8 @@ def load_library():
         "ads_energy": [c_void_p, c_void_p],
         "ads_step": [c_void_p, c_int32],
         "ads_get_state": [c_void_p, c_void_p, c_void_p, c_void_p],
+        "ads_checkpoint_save": [c_void_p, c_void_p, c_void_p, c_void_p],
+        "ads_checkpoint_load": [c_void_p, c_void_p, c_void_p, c_void_p, c_int64],
         "ads_set_state": [c_void_p, c_void_p, c_void_p, c_void_p, c_int64],
         "ads_get_step": [c_void_p, POINTER(c_int64)],
         "ads_check_finite": [c_void_p],
@@ -311,6 +313,26 @@ class Sim:
         nf = self.prm.full_numel
         _check(load_library().ads_set_state(self._h, _ptr(u, nf, "u"), _ptr(v, nf, "v"), _ptr(a, nf, "a"),
                                             int(step)))
+
+    def checkpoint(self):
+        """The time-stepping state (full layout) and the step index, from
+        which checkpoint_restore continues bitwise: P-wave (w, u', u''),
+        w = u + tau u' + tau^2/4 u''; elasticity (U^n, U^{n-1}, None)."""
+        s0, s1 = self._empty_full(), self._empty_full()
+        s2 = self._empty_full() if self.prm.comps == 1 else None
+        self._pre()
+        nf = self.prm.full_numel
+        _check(load_library().ads_checkpoint_save(self._h, _ptr(s0, nf, "s0"), _ptr(s1, nf, "s1"),
+                                                  _ptr(s2, nf, "s2")))
+        self.stream.synchronize()
+        return (s0, s1, s2), self.step_index()
+
+    def checkpoint_restore(self, state, step):
+        self._pre()
+        nf = self.prm.full_numel
+        s0, s1, s2 = state
+        _check(load_library().ads_checkpoint_load(self._h, _ptr(s0, nf, "s0"), _ptr(s1, nf, "s1"),
+                                                  _ptr(s2, nf, "s2"), int(step)))
 
     def step_index(self):
         s = c_int64()

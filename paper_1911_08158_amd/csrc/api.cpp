@@ -175,6 +175,13 @@ struct ads_sim {
   double* red;          // dot-product partial sums + 3 results
   DevFactor fS[3], fS2[3], fM[3];  // P-wave: fS = M + eta K; elastic: fS = mu, fS2 = 2mu+lam
   double *u, *v, *a, *R, *X, *T, *Y, *Z, *load, *amp;
+  // P-wave: the time step advances (w, v, a), w = u + tau v + eta a the
+  // predictor of the next step (printed coefficient set: w = u + tau v), so
+  // that its right-hand side reads one field; u is formed from them when it
+  // is read (w_stale: w must be formed from u, v, a, after the state was
+  // set; u_stale: u must be formed from w, v, a, after time steps)
+  double* w = nullptr;
+  bool w_stale = true, u_stale = false;
   unsigned long long* counter;
   unsigned long long* flag;
   JobArena arena;
@@ -337,6 +344,7 @@ void carve(ads_sim* s, Carver& c) {
     }
   } else {
     s->a = c.dbl(nfr);
+    s->w = c.dbl(nfr);
     s->T = s->Y = s->Z = nullptr;
     for (int d = 0; d < 3; ++d) s->d_bandA[d] = c.dbl((size_t)s->nf[d] * (2 * p + 1));
   }
@@ -524,14 +532,12 @@ bool quadrature_ok(const ads_sim* s) { return quadrature_ok(s->p) && s->q == s->
 // Kronecker form.
 int fp64_aux_var(const ads_sim* s) { return quadrature_ok(s) ? 0 : 3; }
 
-RhsJob rhs_pwave_job(const ads_sim* s, double cu, double cv, double ca, int amp_shift, int mixed, int var) {
+// P-wave right-hand side R = F(t) - K src of one field (the time step's
+// predictor field, the state for the start and the energy diagnostic).
+RhsJob rhs_pwave_job(const ads_sim* s, const double* src, int amp_shift, int mixed, int var) {
   RhsJob J{};
-  J.u = s->u;
-  J.v = cv != 0.0 ? s->v : nullptr;
-  J.a = ca != 0.0 ? s->a : nullptr;
-  J.cu = cu;
-  J.cv = cv;
-  J.ca = ca;
+  J.u = src;
+  J.cu = 1.0;
   J.R = s->R;
   J.load = s->have_load ? s->load : nullptr;
   J.amp = s->amp;
@@ -724,6 +730,23 @@ ads_status upload_factor(ads_sim* s, const DevFactor& f, const Band& A) {
   return upload(s, f.rd, lu.rd.data(), lu.rd.size() * 8);
 }
 
+// P-wave: the predictor w from the state u, v, a (after the state was set
+// or started), and u back from w, v, a (after time steps), on the stream.
+ads_status sync_predictor(ads_sim* s) {
+  if (s->elastic || !s->w_stale) return ADS_OK;
+  const double tau = s->prm.tau;
+  HIPCHECK(launch_lin3(s->w, s->u, s->v, s->literal ? nullptr : s->a, tau, 0.25 * tau * tau, s->nfree, s->stream));
+  s->w_stale = false;
+  return ADS_OK;
+}
+ads_status materialize_u(ads_sim* s) {
+  if (s->elastic || !s->u_stale) return ADS_OK;
+  const double tau = s->prm.tau;
+  HIPCHECK(launch_lin3(s->u, s->w, s->v, s->literal ? nullptr : s->a, -tau, -0.25 * tau * tau, s->nfree, s->stream));
+  s->u_stale = false;
+  return ADS_OK;
+}
+
 // (Re)build every job table and launch list; uploads the arena.
 ads_status build_launches(ads_sim* s) {
   std::string err;
@@ -736,7 +759,7 @@ ads_status build_launches(ads_sim* s) {
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
     // (the printed coefficient set drops the u'' term of the predictor)
-    RhsJob rj = rhs_pwave_job(s, 1.0, tau, s->literal ? 0.0 : eta, 1, s->mixed ? 1 : 0, s->rhs_var);
+    RhsJob rj = rhs_pwave_job(s, s->w, 1, s->mixed ? 1 : 0, s->rhs_var);
     // BF16 inputs: the predictor rounded to BF16, then a second pass on the
     // remainder accumulated into R (the one-step correction)
     std::vector<RhsJob> passes{rj};
@@ -761,7 +784,7 @@ ads_status build_launches(ads_sim* s) {
     z.epi = s->literal ? EPI_NEWMARK_LITERAL : EPI_NEWMARK;
     z.c0 = tau;
     z.c1 = eta;
-    z.e0 = s->u;
+    z.e0 = s->w;
     z.e1 = s->v;
     z.e2 = s->a;
     z.counter = s->counter;
@@ -769,15 +792,14 @@ ads_status build_launches(ads_sim* s) {
     // start: u''_0 = G^{-1}(F_0 - K u_0)
     // the start is computed in FP64 in every precision mode
     const int av = rhs_form_var(fp64_aux_var(s), s->coef != nullptr);
-    RhsJob r0 = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, av);
+    RhsJob r0 = rhs_pwave_job(s, s->u, 0, 0, av);
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
     s->start_l.push_back(Launch{Launch::RHS_P, d, 1, r0.ntiles, 0, s->p, -1, av, 0, as_bytes(r0)});
     s->start_l.back().coef = s->coef != nullptr;
     // energy diagnostic: R = K u, R = K v (FP64 quadrature), R = G v (split operator)
     for (double* src : {s->u, s->v}) {
-      RhsJob ke = rhs_pwave_job(s, 1.0, 0.0, 0.0, 0, 0, av);
-      ke.u = src;
+      RhsJob ke = rhs_pwave_job(s, src, 0, 0, av);
       ke.load = nullptr;
       ke.amp = nullptr;
       ke.rscale = -1.0;
@@ -1106,7 +1128,8 @@ ads_status ads_energy(ads_sim* s, double* host_energy) {
   if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_energy before ads_factor");
   const int nd = dot_scratch_doubles();
   double* out = s->red + nd;
-  ads_status st;
+  ads_status st = materialize_u(s);
+  if (st != ADS_OK) return st;
   if (s->elastic) {
     // u = U^{n+1}, v = U^n
     const long long n3 = 3 * s->nfree;
@@ -1161,6 +1184,7 @@ ads_status ads_set_scheme(ads_sim* s, int32_t scheme) {
   if (s->elastic && scheme != ADS_SCHEME_NEWMARK) return fail(ADS_EINVAL, "the printed scheme is a P-wave diagnostic");
   if (s->factored) return fail(ADS_ESTATE, "ads_set_scheme after ads_factor");
   s->literal = scheme == ADS_SCHEME_LITERAL;
+  s->w_stale = true;   // the predictor's definition follows the scheme
   return build_launches(s);
 }
 
@@ -1192,7 +1216,9 @@ ads_status ads_factor(ads_sim* s) {
       HIPCHECK(launch_axpby(s->v, s->v, s->Z, 1.0, 0.5, n3, s->stream));
     }
     s->need_start = false;
+    s->w_stale = true;
   }
+  if ((st = sync_predictor(s)) != ADS_OK) return st;
   HIPCHECK(hipStreamSynchronize(s->stream));
   s->factored = true;
   return ADS_OK;
@@ -1202,6 +1228,9 @@ ads_status ads_step(ads_sim* s, int32_t nsteps) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   if (nsteps < 0) return fail(ADS_EINVAL, "nsteps < 0");
   if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_step before ads_factor");
+  ads_status st0 = sync_predictor(s);
+  if (st0 != ADS_OK) return st0;
+  if (nsteps > 0 && !s->elastic) s->u_stale = true;
   const size_t per = s->step_l.size() + 1;
   for (int k = 0; k < nsteps; ++k) {
     hipEvent_t* evs = nullptr;
@@ -1419,6 +1448,8 @@ ads_status ads_profile_read(ads_sim* s, double* ms, int32_t* kind, int32_t cap, 
 ads_status ads_check_finite(ads_sim* s) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
   const long long n = s->nfree * s->ncomp;
+  ads_status st = materialize_u(s);
+  if (st != ADS_OK) return st;
   HIPCHECK(launch_set_u64(s->flag, 0ull, s->stream));
   HIPCHECK(launch_nonfinite(s->u, n, s->flag, s->stream));
   HIPCHECK(launch_nonfinite(s->v, n, s->flag, s->stream));
@@ -1432,6 +1463,10 @@ ads_status ads_check_finite(ads_sim* s) {
 
 ads_status ads_get_state(ads_sim* s, double* u, double* v, double* a) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (u) {
+    ads_status st = materialize_u(s);
+    if (st != ADS_OK) return st;
+  }
   const int nc = s->ncomp;
   if (u) HIPCHECK(launch_free_to_full(s->u, u, s->n, s->nf, s->off, nc, s->stream));
   if (v) HIPCHECK(launch_free_to_full(s->v, v, s->n, s->nf, s->off, nc, s->stream));
@@ -1448,9 +1483,52 @@ ads_status ads_set_state(ads_sim* s, const double* u, const double* v, const dou
   if (!s->elastic) {
     if (a) HIPCHECK(launch_full_to_free(a, s->a, s->n, s->nf, s->off, 1, s->stream));
     s->need_start = (a == nullptr);
+    s->u_stale = false;
+    s->w_stale = true;
+    if (a) {
+      ads_status st = sync_predictor(s);
+      if (st != ADS_OK) return st;
+    }
   } else {
     s->need_start = (v == nullptr);
   }
+  HIPCHECK(launch_set_u64(s->counter, (unsigned long long)step, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_checkpoint_save(ads_sim* s, double* s0, double* s1, double* s2) {
+  if (!s || !s0 || !s1 || (!s->elastic && !s2)) return fail(ADS_EINVAL, "NULL argument");
+  if (!s->factored || s->need_start) return fail(ADS_ESTATE, "ads_checkpoint_save before ads_factor");
+  const int nc = s->ncomp;
+  if (s->elastic) {
+    HIPCHECK(launch_free_to_full(s->u, s0, s->n, s->nf, s->off, nc, s->stream));
+    HIPCHECK(launch_free_to_full(s->v, s1, s->n, s->nf, s->off, nc, s->stream));
+    return ADS_OK;
+  }
+  ads_status st = sync_predictor(s);
+  if (st != ADS_OK) return st;
+  HIPCHECK(launch_free_to_full(s->w, s0, s->n, s->nf, s->off, 1, s->stream));
+  HIPCHECK(launch_free_to_full(s->v, s1, s->n, s->nf, s->off, 1, s->stream));
+  HIPCHECK(launch_free_to_full(s->a, s2, s->n, s->nf, s->off, 1, s->stream));
+  return ADS_OK;
+}
+
+ads_status ads_checkpoint_load(ads_sim* s, const double* s0, const double* s1, const double* s2, int64_t step) {
+  if (!s || !s0 || !s1 || (!s->elastic && !s2)) return fail(ADS_EINVAL, "NULL argument");
+  if (step < 0) return fail(ADS_EINVAL, "step < 0");
+  const int nc = s->ncomp;
+  if (s->elastic) {
+    HIPCHECK(launch_full_to_free(s0, s->u, s->n, s->nf, s->off, nc, s->stream));
+    HIPCHECK(launch_full_to_free(s1, s->v, s->n, s->nf, s->off, nc, s->stream));
+  } else {
+    HIPCHECK(launch_full_to_free(s0, s->w, s->n, s->nf, s->off, 1, s->stream));
+    HIPCHECK(launch_full_to_free(s1, s->v, s->n, s->nf, s->off, 1, s->stream));
+    HIPCHECK(launch_full_to_free(s2, s->a, s->n, s->nf, s->off, 1, s->stream));
+    s->w_stale = false;
+    s->u_stale = true;
+  }
+  s->need_start = false;
   HIPCHECK(launch_set_u64(s->counter, (unsigned long long)step, s->stream));
   HIPCHECK(hipStreamSynchronize(s->stream));
   return ADS_OK;
@@ -1862,6 +1940,14 @@ ads_status ads_pool_activate(ads_pool* P, int32_t slot) {
 ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
   if (!P || nsteps < 0) return fail(ADS_EINVAL, "bad argument");
   ads_status st;
+  // the active simulations' predictor fields (a state set since the last
+  // step), then their u is formed from (w, v, a) when read
+  for (int i = 0; i < P->max_slots; ++i) {
+    ads_sim* s = P->slots[i].sim;
+    if (!s || !P->slots[i].active) continue;
+    if ((st = sync_predictor(s)) != ADS_OK) return st;
+    if (nsteps > 0 && !s->elastic) s->u_stale = true;
+  }
   if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
   // the graph holds the non-empty launch classes; re-capture only when that
   // set changes (tables alone change between replays without re-capture)

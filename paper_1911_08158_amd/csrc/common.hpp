@@ -65,9 +65,14 @@ struct Factor1D {
 // Epilogue applied by a sweep to every solved value x at global offset g.
 enum SweepEpi : int {
   EPI_STORE = 0,     // out[g] = x
-  EPI_NEWMARK = 1,   // a' = x; v += tau/2 (a + a'); u += tau v + eta (a + a'); a = a'
+  // Newmark on the state (w, v, a), w = u + tau v + eta a the predictor of
+  // the next step (u itself is w - tau v - eta a):
+  //   a' = x; v' = v + tau/2 (a + a'); u' = w + eta a'; w' = u' + tau v' + eta a'
+  EPI_NEWMARK = 1,
   EPI_THREELEVEL = 2, // out[g] = x; U^{n-1} <- U^n; U^n <- 2 U^n - U^{n-1} + x
-  EPI_NEWMARK_LITERAL = 3  // printed coefficient set: a' = x; u += tau v; v += tau/2 a'
+  // printed coefficient set on (w, v, a), w = u + tau v:
+  //   a' = x; u' = w (u + tau v, old v); v' = v + tau/2 a'; w' = u' + tau v'
+  EPI_NEWMARK_LITERAL = 3
 };
 
 // One set of line solves of a field along one direction.
@@ -84,7 +89,7 @@ struct SweepJob {
   int epi;
   double scale;     // the input is multiplied by this before the solve
   double c0, c1;    // EPI_NEWMARK: tau, eta
-  double* e0;       // EPI_NEWMARK: u   EPI_THREELEVEL: U^n
+  double* e0;       // EPI_NEWMARK: w   EPI_THREELEVEL: U^n
   double* e1;       // EPI_NEWMARK: v   EPI_THREELEVEL: U^{n-1}
   double* e2;       // EPI_NEWMARK: a
   unsigned long long* counter;  // incremented once by the job (end of a step)
@@ -106,8 +111,9 @@ struct PlaneJob {
 // Right-hand side by sum-factorized Gauss quadrature on one field
 // (P-wave) or three fields (elasticity).
 struct RhsJob {
-  // state: P-wave w = cu*u + cv*v + ca*a (free layout); elasticity uses u
-  // as U^n (3 components, comp stride nfree) and ignores v, a.
+  // state: P-wave w = cu*u + cv*v + ca*a (free layout; the Kronecker-form
+  // kernel takes v = a = null); elasticity uses u as U^n (3 components,
+  // comp stride nfree) and ignores v, a.
   const double* u;
   const double* v;
   const double* a;

@@ -79,6 +79,18 @@ __global__ void axpby_kernel(double* out, const double* x, const double* y, doub
     out[idx] = a * x[idx] + (y ? b * y[idx] : 0.0);
 }
 
+// out = x + b y + c z (z optional), as fma(c, z, fma(b, y, x)): the
+// Newmark predictor w = u + tau v + eta a of a state, and back u = w -
+// tau v - eta a.
+__global__ void lin3_kernel(double* out, const double* x, const double* y, const double* z, double b, double c,
+                            long long n) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const double t = fma(b, y[idx], x[idx]);
+    out[idx] = z ? fma(c, z[idx], t) : t;
+  }
+}
+
 // Count non-finite entries (any positive count means failure).
 __global__ void nonfinite_kernel(const double* x, long long n, unsigned long long* cnt) {
   unsigned long long local = 0;
@@ -165,6 +177,12 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
 hipError_t launch_axpby(double* out, const double* x, const double* y, double a, double b, long long n,
                         hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, x, y, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin3(double* out, const double* x, const double* y, const double* z, double b, double c,
+                       long long n, hipStream_t s) {
+  hipLaunchKernelGGL(lin3_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, x, y, z, b, c, n);
   return hipGetLastError();
 }
 

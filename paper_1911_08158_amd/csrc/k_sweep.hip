@@ -85,33 +85,35 @@ __device__ __forceinline__ void epilogue_batch(const EpiView& E, const long long
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) E.out[g[k]] = x[k];
   } else if (E.epi == EPI_NEWMARK) {
-    double u[kEpi], v[kEpi], a[kEpi];
+    double w[kEpi], v[kEpi], a[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
-      u[k] = E.e0[g[k]];
+      w[k] = E.e0[g[k]];
       v[k] = E.e1[g[k]];
       a[k] = E.e2[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
-        double s = a[k] + x[k];
-        E.e1[g[k]] = v[k] + 0.5 * E.c0 * s;
-        E.e0[g[k]] = u[k] + E.c0 * v[k] + E.c1 * s;
+        const double vn = v[k] + 0.5 * E.c0 * (a[k] + x[k]);
+        const double un = fma(E.c1, x[k], w[k]);
+        E.e0[g[k]] = fma(E.c1, x[k], fma(E.c0, vn, un));
+        E.e1[g[k]] = vn;
         E.e2[g[k]] = x[k];
       }
   } else if (E.epi == EPI_NEWMARK_LITERAL) {
-    double u[kEpi], v[kEpi];
+    double w[kEpi], v[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
-      u[k] = E.e0[g[k]];
+      w[k] = E.e0[g[k]];
       v[k] = E.e1[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
-        E.e0[g[k]] = u[k] + E.c0 * v[k];
-        E.e1[g[k]] = v[k] + 0.5 * E.c0 * x[k];
+        const double vn = v[k] + 0.5 * E.c0 * x[k];
+        E.e0[g[k]] = fma(E.c0, vn, w[k]);
+        E.e1[g[k]] = vn;
         E.e2[g[k]] = x[k];
       }
   } else {  // EPI_THREELEVEL

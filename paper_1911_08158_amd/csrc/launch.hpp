@@ -62,6 +62,8 @@ hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_axpby(double* out, const double* x, const double* y, double a, double b, long long n,
                         hipStream_t s);
+hipError_t launch_lin3(double* out, const double* x, const double* y, const double* z, double b, double c,
+                       long long n, hipStream_t s);
 hipError_t launch_nonfinite(const double* x, long long n, unsigned long long* cnt, hipStream_t s);
 // out = x . y (deterministic two-pass reduction through dot_scratch_doubles() partial sums)
 int dot_scratch_doubles();

@@ -32,7 +32,7 @@ def test_rhs_flop_count():
 
 def test_sweep_bytes_per_dof():
     # in-plane x+y: read R, write the y-solved field; z with the Newmark
-    # update: read X and u, u', u'', write u, u', u''
+    # update: read X and the state (w, u', u''), write the state
     assert bench.SWEEP_BYTES["sweep_xy"] == 8 + 8
     assert bench.SWEEP_BYTES["sweep_z"] == 8 + 3 * 8 + 3 * 8
 
@@ -45,10 +45,11 @@ def test_more_than_one_gpu_refused():
 
 
 def test_rhs_bytes_and_roofline_entries():
-    """Algorithmic bytes of the Kronecker-form right-hand side (u, u', u''
-    in, R out) and the roofline entries built from a kernel-table row."""
+    """Algorithmic bytes of the Kronecker-form right-hand side (the
+    predictor field in, R out) and the roofline entries built from a
+    kernel-table row."""
     import workloads as W
-    assert bench.RHS_BYTES == 3 * 8 + 8
+    assert bench.RHS_BYTES == 8 + 8
     cfg = W.C3
     nfree = 128 ** 3 * 4
     row = {"kernel": "sweep_z", "ms": 0.1, "gbs": round(56 * nfree / 1e-4 / 1e9, 1)}
