@@ -85,7 +85,9 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
   const long long sxy = (long long)nx * ny;
   double pf[MT][NS];
   // layer zs of every term (positions outside the field load offset 0 of
-  // the layer and are zeroed: no branch around the loads)
+  // the layer, no branch around the loads, and are zeroed when the layer is
+  // written to LDS: nothing consumes a load before then, so that the loads
+  // stay in flight during the previous layer's contractions)
   auto prefetch = [&](int zs) {
 #pragma unroll
     for (int term = 0; term < MT; ++term) {
@@ -95,10 +97,6 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
         for (int i = 0; i < NS; ++i) pf[term][i] = src[sval[i] ? soff[i] : 0];
       }
     }
-#pragma unroll
-    for (int term = 0; term < MT; ++term)
-#pragma unroll
-      for (int i = 0; i < NS; ++i) pf[term][i] = sval[i] ? pf[term][i] : 0.0;
   };
   const bool ocol = X0 + lx < nx && Y0 + ly < ny;
   const long long obase = (long long)(Y0 + ly) * nx + X0 + lx;
@@ -124,7 +122,7 @@ __device__ void kron_tile(const KronJob& J, int t, double* lds) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const int k = tid + i * KNT;
-          if (k < SY * SX) S[term * (SY * SX) + k] = pf[term][i];
+          if (k < SY * SX) S[term * (SY * SX) + k] = sval[i] ? pf[term][i] : 0.0;
         }
       }
     }

@@ -171,12 +171,17 @@ __global__ __launch_bounds__(ElBandGeom<p>::ENT, 2) void rhs_elastic_band_kernel
 
     double pf[kDepthE][3][NS];
     double pzb[kDepthE];
+    // loads only: nothing consumes them before the layer is committed (the
+    // z-band entry outside the free range is replaced by zero then), so that
+    // they stay in flight meanwhile
+    auto zband_ok = [&](int s) {
+      const int o = s - p + zk;
+      return zlane < 4 * B && o >= 0 && o < nfz;
+    };
     auto prefetch = [&](int s, double (&pf)[3][NS], double& pz) {
       {
         const int o = s - p + zk;
-        const bool ok = zlane < 4 * B && o >= 0 && o < nfz;
-        pz = bzg[ok ? (long long)o * B + (2 * p - zk) : 0];
-        pz = ok ? pz : 0.0;
+        pz = bzg[zband_ok(s) ? (long long)o * B + (2 * p - zk) : 0];
       }
       const long long zo = (long long)s * sxy;
 #pragma unroll
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(ElBandGeom<p>::ENT, 2) void rhs_elastic_band_kernel
         const int s = s0 + d;
         if (s > se) break;
         commit(pf[d]);
-        const double zbv = pzb[d];
+        const double zbv = zband_ok(s) ? pzb[d] : 0.0;
         if (s + kDepthE <= se) prefetch(s + kDepthE, pf[d], pzb[d]);
         process(s, zbv);
       }

@@ -45,7 +45,7 @@ __device__ __forceinline__ void wave_sync_sw() {
 template <int W>
 __device__ __forceinline__ int sidx(int i, int l) { return i * (W + 1) + l; }
 
-constexpr int kChunk = 16;   // global loads in flight per lane while staging a tile
+constexpr int kChunk = 32;   // global loads in flight per lane while staging a tile
 constexpr int kWaves = 4;    // waves per workgroup (one tile each)
 constexpr int kNT = 64 * kWaves;
 
@@ -77,7 +77,7 @@ struct EpiView {
 // Epilogue on K solved values at global offsets g[k] (ok[k] false = skip;
 // g[k] is then still a valid offset of the field, so the old-state loads
 // need no branch); all loads of the batch are issued before any is used.
-constexpr int kEpi = 4;
+constexpr int kEpi = 8;
 __device__ __forceinline__ void epilogue_batch(const EpiView& E, const long long* g, const double* x,
                                                const bool* ok) {
   if (E.epi == EPI_STORE) {
