@@ -60,9 +60,9 @@ RHS_BYTES = 16   # per free DOF: reads the predictor u + tau u' + tau^2/4 u'', w
 # launch's traffic is reported as null once its sources hash differently.
 TRAFFIC = {
     "rhs": {"sources": ["paper_1911_08158_amd/csrc/k_rhs_band.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-            "sha256": "57502d423aae62a74a2e658c72580b90064ceaf65299ff6e92a2c91fdc23c4d5", "fetch_kib": 107695.9, "write_kib": 65536.0},
+            "sha256": "e4968a98551f7f95822531d51a7c0e0df819a81bafe57fce000d274c93bfb0a3", "fetch_kib": 36047.5, "write_kib": 65536.0},
     "sweep_z": {"sources": ["paper_1911_08158_amd/csrc/k_sweep.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-                "sha256": "20e20094457929893f7a9af7fc7fec541d7e936348a414c6ff6b1e2b747f47bd", "fetch_kib": 131245.3, "write_kib": 196608.0},
+                "sha256": "de9cd1fe15df7ab3a9acae00200c7c506d2796bbcf88f8073c2aba276b8f19c3", "fetch_kib": 131268.0, "write_kib": 196608.1},
     "fetch_scale": 2.0, "write_scale": 1.0,
     "batch": 4,
 }
@@ -516,6 +516,39 @@ def calibration_copy():
     del x, y
 
 
+def measure_hbm_practical():
+    """Reference bandwidths of plain torch kernels on 512 MiB FP64 tensors
+    (beyond the 256 MB Infinity Cache; HIP events over 20 repetitions): the
+    rate a streaming kernel reaches on this machine, beside the datasheet peak
+    the roofline entries divide by."""
+    import torch
+    n = 64 << 20
+    a = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+
+    def rate(f, nbytes, reps=20):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9, 1)
+
+    out = {"copy_gbs": rate(lambda: b.copy_(a), 16 * n),
+           "fill_gbs": rate(lambda: b.fill_(1.0), 8 * n),
+           "read_sum_gbs": rate(lambda: a.sum(), 8 * n),
+           "add_gbs": rate(lambda: torch.add(a, b, out=c), 24 * n),
+           "note": "torch copy_ (read + write), fill_ (write), sum (read), add (2 reads + 1 write) of 512 MiB "
+                   "FP64 tensors; datasheet peak 8000 GB/s"}
+    del a, b, c
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -529,7 +562,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature", "grid"],
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature", "grid", "hbm"],
                     default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
@@ -566,6 +599,9 @@ def main():
     if args.only == "grid":
         print(json.dumps({"form": "grid_sweep", **measure_grid_sweep((32, 48, 64, 96, 128, 192, 256), 50, 5)}),
               flush=True)
+        return
+    if args.only == "hbm":
+        print(json.dumps({"form": "hbm_practical", **measure_hbm_practical()}), flush=True)
         return
     if args.only == "accuracy":
         print(json.dumps({"form": "accuracy", **measure_accuracy(cfg, args.steps)}), flush=True)
@@ -615,6 +651,8 @@ def main():
                           "non-packed FP32 vector FMAs issue at the FP64 rate on gfx950, so the FP64 Kronecker "
                           "form (plain band, one FMA per entry) runs as fast (batched_fp64).",
     }
+    out["hbm_practical"] = measure_hbm_practical()
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / out["hbm_practical"]["copy_gbs"], 4)
     out["accuracy"] = measure_accuracy(cfg, 100)
     # the quadrature right-hand side (a wave-speed field), FP64 and mixed
     quad = {}
