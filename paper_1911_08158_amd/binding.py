@@ -98,6 +98,11 @@ def load_library():
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run `python -m paper_1911_08158_amd.build`)")
+    # torch ships its own HIP runtime under the same soname as the system's;
+    # loading torch first makes the library bind to that one copy (loaded
+    # the other way round, two runtimes meet in the process and the
+    # library's finds no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     P = POINTER(Params)
     sig = {
