@@ -326,8 +326,20 @@ ads_status ads_pool_admit(ads_pool* pool, const ads_params* prm, int32_t* slot);
 ads_status ads_pool_sim(ads_pool* pool, int32_t slot, ads_sim** sim);
 /* Join the batch from the next pool step (the simulation must be factored). */
 ads_status ads_pool_activate(ads_pool* pool, int32_t slot);
-/* Advance every active simulation by nsteps steps (asynchronous). */
+/* Advance every active simulation by nsteps steps (asynchronous).  The
+ * active simulations are split into two branches of about equal unknowns
+ * (largest first, each to the branch with fewer so far) whose launch
+ * sequences run concurrently: the second branch on a stream of the pool's
+ * own, forked from the pool's stream by an event at the start of a step and
+ * joined back into it at its end, so that one branch's latency-bound
+ * stages overlap the other's bandwidth-bound ones (a captured graph holds
+ * the two chains).  Each simulation's launches stay in order on one
+ * stream; the results are the same bits with one branch or two. */
 ads_status ads_pool_step(ads_pool* pool, int32_t nsteps);
+/* Number of concurrent branches of the following steps: 2 (the default) or
+ * 1 (every launch class of the batch in one launch on the pool's stream).
+ * Profiled steps (ads_pool_profile) use one.  ADS_EINVAL otherwise. */
+ads_status ads_pool_set_branches(ads_pool* pool, int32_t n);
 /* Leave the batch and release the slot's memory (read the state first with
  * ads_get_state on ads_pool_sim's handle; the release is stream-ordered). */
 ads_status ads_pool_retire(ads_pool* pool, int32_t slot);

@@ -137,6 +137,7 @@ def load_library():
         "ads_pool_sim": [c_void_p, c_int32, POINTER(c_void_p)],
         "ads_pool_activate": [c_void_p, c_int32],
         "ads_pool_step": [c_void_p, c_int32],
+        "ads_pool_set_branches": [c_void_p, c_int32],
         "ads_pool_retire": [c_void_p, c_int32],
         "ads_pool_step_times": [c_void_p, c_void_p, c_int32, POINTER(c_int32)],
         "ads_pool_info": [c_void_p, POINTER(c_int32), POINTER(c_size_t), POINTER(c_size_t)],
@@ -444,6 +445,10 @@ class Pool:
 
     def step(self, n=1):
         _check(load_library().ads_pool_step(self._h, int(n)))
+
+    def set_branches(self, n):
+        """Concurrent branches of the following steps (1 or 2)."""
+        _check(load_library().ads_pool_set_branches(self._h, int(n)))
 
     def tune(self):
         """Autotune the launch shapes of the current batch; returns the

@@ -1574,9 +1574,17 @@ struct PoolLaunch {
   int grid;
   int w;            // sweeps: lines per wave tile (chosen per batch)
   size_t lds;       // in-plane sweeps: dynamic LDS bytes (largest plane of the batch)
-  size_t off, cap;  // table offset/capacity (bytes) in the pool's table region
+  size_t off, cap;  // table offset/capacity (bytes) in the pool's table region: one table
+                    // (header + max_slots jobs) per branch, `boff` bytes apart
   size_t job_size;
+  size_t boff;
 };
+
+// Concurrent branches of a pool step: the active simulations are split into
+// up to two groups whose launch sequences run on two streams (forked from
+// and joined back into the pool's stream), so that one group's latency-bound
+// stages overlap the other's bandwidth-bound ones.
+constexpr int kPoolBranches = 2;
 
 }  // namespace
 
@@ -1599,8 +1607,8 @@ struct ads_pool {
   std::vector<PoolLaunch> seq;
   bool dirty = true;
   bool use_graph = true;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph2 = nullptr;      // a step of branch 0 (pool stream) and 1 (side)
+  hipGraphExec_t exec = nullptr, exec2 = nullptr;
   std::vector<hipEvent_t> ev;
   int nev = 0;
   // P-wave right-hand-side variant per [p-1][mixed][wave-speed field]: by
@@ -1617,9 +1625,24 @@ struct ads_pool {
                                    // launch shape (sweeps: tile width)
   std::vector<int> captured;       // ... when the graph was captured
   int ncu = 0;
+  // branches: the number asked for (ads_pool_set_branches), the number the
+  // tables are built with (one while profiling), the branch of every slot,
+  // and the second stream with the fork and join events
+  int want_branches = kPoolBranches, nbranch = kPoolBranches;
+  std::vector<int> branch;
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   ~ads_pool() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (exec2) (void)hipGraphExecDestroy(exec2);
+    if (graph2) (void)hipGraphDestroy(graph2);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : pev) (void)hipEventDestroy(e);
     for (Slot& s : slots) delete s.sim;
@@ -1632,8 +1655,10 @@ void pool_build_seq(ads_pool* P, int ncu) {
   P->seq.clear();
   size_t off = 0;
   auto add = [&](Launch::Kind k, int p, int mixed, int var, int coef, int stage, int grid, size_t js) {
-    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, 0, off, sizeof(LaunchHdr) + (size_t)P->max_slots * js, js};
-    off += (L.cap + kAlign - 1) / kAlign * kAlign;
+    const size_t one = sizeof(LaunchHdr) + (size_t)P->max_slots * js;
+    const size_t boff = (one + kAlign - 1) / kAlign * kAlign;
+    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, 0, off, one, js, boff};
+    off += kPoolBranches * boff;
     P->seq.push_back(L);
   };
   // right-hand-side classes: P-wave per degree, precision and wave-speed
@@ -1675,22 +1700,42 @@ ads_status pool_align(ads_pool* P) {
   return ADS_OK;
 }
 
-// Gathers the jobs of every active simulation into the merged tables.
+// Gathers the jobs of every active simulation into the merged tables, one
+// table per launch class and branch.
 ads_status pool_rebuild(ads_pool* P) {
   {
     ads_status st = pool_align(P);
     if (st != ADS_OK) return st;
   }
   std::fill(P->h_tab.begin(), P->h_tab.end(), 0);
-  P->nonempty.assign(P->seq.size(), 0);
+  const int nb = P->nbranch;
+  P->nonempty.assign(P->seq.size() * kPoolBranches, 0);
+  // branches: the active simulations by their unknowns, largest first, each
+  // to the branch with fewer so far
+  P->branch.assign(P->slots.size(), 0);
+  {
+    std::vector<std::pair<long long, int>> w;
+    for (size_t i = 0; i < P->slots.size(); ++i)
+      if (P->slots[i].active) w.push_back({P->slots[i].sim->nfree * P->slots[i].sim->ncomp, (int)i});
+    std::stable_sort(w.begin(), w.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    long long load[kPoolBranches] = {};
+    for (const auto& e : w) {
+      int b = 0;
+      for (int c = 1; c < nb; ++c)
+        if (load[c] < load[b]) b = c;
+      P->branch[e.second] = b;
+      load[b] += e.first;
+    }
+  }
   // launches of each active simulation taken by some launch class: every
   // one of them must be, or that simulation would be stepped incompletely
   std::vector<int> taken(P->slots.size(), 0);
   for (size_t li = 0; li < P->seq.size(); ++li) {
     PoolLaunch& L = P->seq[li];
-    std::vector<std::vector<char>> sel;
-    bool fixed_tz = false;
-    for (ads_pool::Slot& sl : P->slots) {
+    std::vector<std::vector<char>> sel[kPoolBranches];
+    bool fixed_tz = false, any = false;
+    for (size_t i = 0; i < P->slots.size(); ++i) {
+      const ads_pool::Slot& sl = P->slots[i];
       if (!sl.active) continue;
       const std::vector<Launch>& st = sl.sim->step_l;
       if ((int)st.size() <= L.stage) continue;
@@ -1699,101 +1744,119 @@ ads_status pool_rebuild(ads_pool* P) {
       if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || l.var != L.var ||
                            (l.kind == Launch::RHS_P && l.coef != L.coef)))
         continue;
-      sel.push_back(l.host_jobs);
-      taken[&sl - P->slots.data()]++;
+      sel[P->branch[i]].push_back(l.host_jobs);
+      taken[i]++;
       fixed_tz = fixed_tz || sl.sim->tz > 0;
+      any = true;
     }
-    // P-wave right-hand sides: z-chunks chosen for the whole batch on the
-    // persistent grid of this launch
-    if ((L.kind == Launch::RHS_P || L.kind == Launch::RHS_E) && !sel.empty() && !fixed_tz) {
-      std::vector<std::pair<long long, int>> xy_nfz;
-      for (const auto& j : sel) {
-        const RhsJob* r = (const RhsJob*)j.data();
-        xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nf[2]});
+    if (!any) {
+      for (int b = 0; b < kPoolBranches; ++b) {
+        LaunchHdr h{};
+        std::memcpy(P->h_tab.data() + L.off + b * L.boff, &h, sizeof(h));
       }
-      const int k = best_zchunks(xy_nfz, L.var == 3 ? 2 * L.p : L.p, L.grid);
-      for (auto& j : sel) {
-        RhsJob* r = (RhsJob*)j.data();
-        set_zchunks(*r, r->nf[2], k);
-      }
+      continue;
     }
-    // couplings: z-chunks chosen for the whole batch on the persistent grid
-    // (the launch's LDS and instantiation follow the largest degree)
-    if (L.kind == Launch::KRON && !sel.empty()) {
-      std::vector<std::pair<long long, int>> xy_nfz;
+    // the launch shape is the class's, over both branches: the couplings'
+    // largest degree (LDS and instantiation) and grid, the in-plane sweeps'
+    // largest plane, the sweeps' tile width for the class's line count
+    if (L.kind == Launch::KRON) {
       int pmax = 1;
-      for (const auto& j : sel) {
-        const KronJob* r = (const KronJob*)j.data();
-        xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nz});
-        pmax = std::max(pmax, r->p);
-      }
+      for (int b = 0; b < nb; ++b)
+        for (const auto& j : sel[b]) pmax = std::max(pmax, ((const KronJob*)j.data())->p);
       L.p = pmax;
       L.grid = kron_blocks_per_cu(pmax) * P->ncu;
-      const int k = best_zchunks(xy_nfz, 2 * pmax, L.grid);
-      for (auto& j : sel) set_kron_zchunks(*(KronJob*)j.data(), k);
     }
-    // in-plane sweeps: LDS of the largest plane, persistent grid for it
-    if (L.kind == Launch::PLANE && !sel.empty()) {
+    if (L.kind == Launch::PLANE) {
       L.lds = 0;
       L.p = 1;
-      for (const auto& j : sel) {
-        const PlaneJob* r = (const PlaneJob*)j.data();
-        L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p));
-        L.p = std::max(L.p, r->p);
-      }
+      for (int b = 0; b < nb; ++b)
+        for (const auto& j : sel[b]) {
+          const PlaneJob* r = (const PlaneJob*)j.data();
+          L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p));
+          L.p = std::max(L.p, r->p);
+        }
       L.grid = plane_blocks_per_cu(L.lds, L.p) * P->ncu;
     }
-    // sweeps: tile width and persistent grid for the batch's line count
-    if (L.kind == Launch::SWEEP && !sel.empty()) {
+    if (L.kind == Launch::SWEEP) {
       long long lines = 0;
       L.p = 1;
-      for (const auto& j : sel) {
-        lines += ((const SweepJob*)j.data())->nlines;
-        L.p = std::max(L.p, ((const SweepJob*)j.data())->p);
-      }
+      for (int b = 0; b < nb; ++b)
+        for (const auto& j : sel[b]) {
+          lines += ((const SweepJob*)j.data())->nlines;
+          L.p = std::max(L.p, ((const SweepJob*)j.data())->p);
+        }
       const int wf = P->w_force[li];
       L.w = (wf > 0 && sweep_width_fits(wf, kPoolMaxM, L.p)) ? wf : sweep_width_for(lines, kPoolMaxM, P->ncu, L.p);
       L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM, L.p) * P->ncu;
-      for (auto& j : sel) {
-        SweepJob* r = (SweepJob*)j.data();
-        r->ntiles = sweep_groups(r->nlines, L.w);
-      }
     }
-    std::vector<char> jobs;
-    int n = 0, total = 0;
-    for (std::vector<char>& j : sel) {
-      // every job struct starts its tiling fields the same way: patch tile0
-      if (L.kind == Launch::SWEEP) {
-        SweepJob* s = (SweepJob*)j.data();
-        s->tile0 = total;
-        total += s->ntiles;
-      } else if (L.kind == Launch::KRON) {
-        KronJob* s = (KronJob*)j.data();
-        s->tile0 = total;
-        total += s->ntiles;
-      } else if (L.kind == Launch::PLANE) {
-        PlaneJob* s = (PlaneJob*)j.data();
-        s->tile0 = total;
-        total += s->ntiles;
-      } else {
-        RhsJob* s = (RhsJob*)j.data();
-        s->tile0 = total;
-        total += s->ntiles;
+    const int shape = L.kind == Launch::SWEEP ? L.w * 8 + L.p
+                      : L.kind == Launch::PLANE ? (int)L.lds * 8 + L.p
+                      : L.kind == Launch::KRON ? L.p : 1 + L.var;
+    for (int b = 0; b < nb; ++b) {
+      std::vector<std::vector<char>>& sb = sel[b];
+      // right-hand sides: z-chunks chosen for the branch's jobs on the
+      // persistent grid of this launch
+      if ((L.kind == Launch::RHS_P || L.kind == Launch::RHS_E) && !sb.empty() && !fixed_tz) {
+        std::vector<std::pair<long long, int>> xy_nfz;
+        for (const auto& j : sb) {
+          const RhsJob* r = (const RhsJob*)j.data();
+          xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nf[2]});
+        }
+        const int k = best_zchunks(xy_nfz, L.var == 3 ? 2 * L.p : L.p, L.grid);
+        for (auto& j : sb) {
+          RhsJob* r = (RhsJob*)j.data();
+          set_zchunks(*r, r->nf[2], k);
+        }
       }
-      jobs.insert(jobs.end(), j.begin(), j.end());
-      ++n;
+      // couplings: z-chunks for the branch's jobs
+      if (L.kind == Launch::KRON && !sb.empty()) {
+        std::vector<std::pair<long long, int>> xy_nfz;
+        for (const auto& j : sb) {
+          const KronJob* r = (const KronJob*)j.data();
+          xy_nfz.push_back({(long long)r->tiles[0] * r->tiles[1], r->nz});
+        }
+        const int k = best_zchunks(xy_nfz, 2 * L.p, L.grid);
+        for (auto& j : sb) set_kron_zchunks(*(KronJob*)j.data(), k);
+      }
+      if (L.kind == Launch::SWEEP)
+        for (auto& j : sb) {
+          SweepJob* r = (SweepJob*)j.data();
+          r->ntiles = sweep_groups(r->nlines, L.w);
+        }
+      std::vector<char> jobs;
+      int n = 0, total = 0;
+      for (std::vector<char>& j : sb) {
+        // every job struct has its own tiling fields: patch tile0
+        if (L.kind == Launch::SWEEP) {
+          SweepJob* r = (SweepJob*)j.data();
+          r->tile0 = total;
+          total += r->ntiles;
+        } else if (L.kind == Launch::KRON) {
+          KronJob* r = (KronJob*)j.data();
+          r->tile0 = total;
+          total += r->ntiles;
+        } else if (L.kind == Launch::PLANE) {
+          PlaneJob* r = (PlaneJob*)j.data();
+          r->tile0 = total;
+          total += r->ntiles;
+        } else {
+          RhsJob* r = (RhsJob*)j.data();
+          r->tile0 = total;
+          total += r->ntiles;
+        }
+        jobs.insert(jobs.end(), j.begin(), j.end());
+        ++n;
+      }
+      LaunchHdr h{};
+      h.njobs = n;
+      h.total_tiles = total;
+      // launch shape (a captured graph holds it): sweep tile width, in-plane
+      // LDS size, and the largest degree (instantiation and factor rows)
+      P->nonempty[li * kPoolBranches + b] = n == 0 ? 0 : shape;
+      char* dst = P->h_tab.data() + L.off + b * L.boff;
+      std::memcpy(dst, &h, sizeof(h));
+      if (!jobs.empty()) std::memcpy(dst + sizeof(LaunchHdr), jobs.data(), jobs.size());
     }
-    LaunchHdr h{};
-    h.njobs = n;
-    h.total_tiles = total;
-    // launch shape (a captured graph holds it): sweep tile width, in-plane
-    // LDS size, and the largest degree (instantiation and factor rows)
-    P->nonempty[li] = n == 0 ? 0
-                             : (L.kind == Launch::SWEEP ? L.w * 8 + L.p
-                                : L.kind == Launch::PLANE ? (int)L.lds * 8 + L.p
-                                : L.kind == Launch::KRON ? L.p : 1 + L.var);
-    std::memcpy(P->h_tab.data() + L.off, &h, sizeof(h));
-    if (!jobs.empty()) std::memcpy(P->h_tab.data() + L.off + sizeof(LaunchHdr), jobs.data(), jobs.size());
   }
   for (size_t i = 0; i < P->slots.size(); ++i) {
     const ads_pool::Slot& sl = P->slots[i];
@@ -1809,27 +1872,43 @@ ads_status pool_rebuild(ads_pool* P) {
   return ADS_OK;
 }
 
-ads_status pool_enqueue(ads_pool* P, hipEvent_t* evs = nullptr) {
-  if (evs) HIPCHECK(hipEventRecord(evs[0], P->stream));
+// True when launch class li has jobs in some branch.
+bool class_used(const ads_pool* P, size_t li) {
+  for (int b = 0; b < kPoolBranches; ++b)
+    if (P->nonempty[li * kPoolBranches + b]) return true;
+  return false;
+}
+
+// One pool step of branch b on stream s: the branch's launch of every
+// non-empty class, in class order (with per-launch events when profiling,
+// where the tables hold one branch).
+ads_status pool_enqueue(ads_pool* P, int b, hipStream_t s, hipEvent_t* evs = nullptr) {
+  if (evs) HIPCHECK(hipEventRecord(evs[0], s));
   for (size_t li = 0; li < P->seq.size(); ++li) {
     const PoolLaunch& L = P->seq[li];
-    if (!P->nonempty[li]) {   // no simulation of this class in the batch
-      if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
-      continue;
+    if (P->nonempty[li * kPoolBranches + b]) {
+      const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off + b * L.boff);
+      hipError_t e = hipSuccess;
+      switch (L.kind) {
+        case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, s); break;
+        case Launch::RHS_E: e = launch_rhs_elastic_band(L.p, L.mixed, h, L.grid, s); break;
+        case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, L.p, s); break;
+        case Launch::KRON: e = launch_kron(h, L.grid, L.p, s); break;
+        case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, L.p, s); break;
+      }
+      if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
     }
-    const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
-    hipError_t e = hipSuccess;
-    switch (L.kind) {
-      case Launch::RHS_P: e = launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); break;
-      case Launch::RHS_E: e = launch_rhs_elastic_band(L.p, L.mixed, h, L.grid, P->stream); break;
-      case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, L.p, P->stream); break;
-      case Launch::KRON: e = launch_kron(h, L.grid, L.p, P->stream); break;
-      case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, L.p, P->stream); break;
-    }
-    if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
-    if (evs) HIPCHECK(hipEventRecord(evs[li + 1], P->stream));
+    // every class closes its interval (empty ones with no launch)
+    if (evs) HIPCHECK(hipEventRecord(evs[li + 1], s));
   }
   return ADS_OK;
+}
+
+// True when branch 1 has any launch.
+bool second_branch(const ads_pool* P) {
+  for (size_t li = 0; li < P->seq.size(); ++li)
+    if (P->nonempty[li * kPoolBranches + 1]) return true;
+  return false;
 }
 
 }  // namespace
@@ -1859,6 +1938,12 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
       b[1] = 0;   // with one: the quadrature's first tile variant
     }
   P->ncu = ncu;
+  if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) {
+    delete P;
+    return fail(ADS_EDEVICE, "pool side stream or events");
+  }
   pool_build_seq(P, ncu);
   P->arena_off = (P->tab_bytes + kAlign - 1) / kAlign * kAlign;
   if (P->arena_off >= bytes) {
@@ -1948,26 +2033,49 @@ ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
     if ((st = sync_predictor(s)) != ADS_OK) return st;
     if (nsteps > 0 && !s->elastic) s->u_stale = true;
   }
-  if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
-  // the graph holds the non-empty launch classes; re-capture only when that
-  // set changes (tables alone change between replays without re-capture)
-  if (P->exec && P->captured != P->nonempty) {
-    HIPCHECK(hipStreamSynchronize(P->stream));
-    (void)hipGraphExecDestroy(P->exec);
-    (void)hipGraphDestroy(P->graph);
-    P->exec = nullptr;
-    P->graph = nullptr;
+  // profiled steps time every launch class over the whole batch: one branch
+  const int nb = P->prof ? 1 : P->want_branches;
+  if (nb != P->nbranch) {
+    P->nbranch = nb;
+    P->dirty = true;
   }
-  if (P->use_graph && !P->exec) {
-    P->captured = P->nonempty;
-    HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
-    st = pool_enqueue(P);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(P->stream, &g);
-    if (st != ADS_OK) return st;
+  if (P->dirty && (st = pool_rebuild(P)) != ADS_OK) return st;
+  const bool two = second_branch(P);
+  // the graphs hold the non-empty launch classes of each branch; re-capture
+  // only when that set changes (tables alone change between replays)
+  if ((P->exec || P->exec2) && P->captured != P->nonempty) {
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    HIPCHECK(hipStreamSynchronize(P->side));
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->exec2) (void)hipGraphExecDestroy(P->exec2);
+    if (P->graph2) (void)hipGraphDestroy(P->graph2);
+    P->exec = P->exec2 = nullptr;
+    P->graph = P->graph2 = nullptr;
+  }
+  auto capture = [&](int b, hipStream_t s, hipGraph_t* g, hipGraphExec_t* x) -> ads_status {
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ads_status cs = pool_enqueue(P, b, s);
+    hipGraph_t gg = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &gg);
+    if (cs != ADS_OK) return cs;
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    P->graph = g;
-    HIPCHECK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+    *g = gg;
+    HIPCHECK(hipGraphInstantiate(x, gg, nullptr, nullptr, 0));
+    return ADS_OK;
+  };
+  if (P->use_graph && !P->prof && !P->exec) {
+    P->captured = P->nonempty;
+    if ((st = capture(0, P->stream, &P->graph, &P->exec)) != ADS_OK) return st;
+    if (two && (st = capture(1, P->side, &P->graph2, &P->exec2)) != ADS_OK) return st;
+  }
+  // two branches: the side stream starts after the pool stream's earlier
+  // work and runs its steps beside the pool stream's; it is joined back
+  // before the last step's event, so that the call's steps are complete on
+  // the pool stream (stream-ordered reads of any simulation see them)
+  if (two && nsteps > 0) {
+    HIPCHECK(hipEventRecord(P->fork_ev, P->stream));
+    HIPCHECK(hipStreamWaitEvent(P->side, P->fork_ev, 0));
   }
   for (int k = 0; k < nsteps; ++k) {
     if (P->nev == 0) {
@@ -1986,12 +2094,18 @@ ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
         HIPCHECK(hipEventCreate(&e));
         P->pev.push_back(e);
       }
-      if ((st = pool_enqueue(P, &P->pev[(size_t)P->prof_steps * per])) != ADS_OK) return st;
+      if ((st = pool_enqueue(P, 0, P->stream, &P->pev[(size_t)P->prof_steps * per])) != ADS_OK) return st;
       P->prof_steps++;
     } else if (P->use_graph) {
       HIPCHECK(hipGraphLaunch(P->exec, P->stream));
-    } else if ((st = pool_enqueue(P)) != ADS_OK) {
-      return st;
+      if (two) HIPCHECK(hipGraphLaunch(P->exec2, P->side));
+    } else {
+      if ((st = pool_enqueue(P, 0, P->stream)) != ADS_OK) return st;
+      if (two && (st = pool_enqueue(P, 1, P->side)) != ADS_OK) return st;
+    }
+    if (two && k == nsteps - 1) {
+      HIPCHECK(hipEventRecord(P->join_ev, P->side));
+      HIPCHECK(hipStreamWaitEvent(P->stream, P->join_ev, 0));
     }
     // step times are kept for at most kStepEventCap steps between reads
     if (P->nev > kStepEventCap) continue;
@@ -2035,17 +2149,22 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
     *ms = f / reps;
     return ADS_OK;
   };
-  // the class's gathered jobs (header + table in the host copy)
+  // the class's gathered jobs of branch tb (header + table in the host
+  // copy): a launch is timed alone on the table of its first non-empty
+  // branch, the launch a step runs
+  size_t tb = 0;
+  auto table = [&](const PoolLaunch& L) { return L.off + tb * L.boff; };
   auto jobs_of = [&](const PoolLaunch& L, auto* tag) {
     using J = std::remove_pointer_t<decltype(tag)>;
     LaunchHdr h;
-    std::memcpy(&h, P->h_tab.data() + L.off, sizeof(h));
+    std::memcpy(&h, P->h_tab.data() + table(L), sizeof(h));
     std::vector<J> v(h.njobs);
-    if (h.njobs) std::memcpy(v.data(), P->h_tab.data() + L.off + sizeof(LaunchHdr), h.njobs * sizeof(J));
+    if (h.njobs) std::memcpy(v.data(), P->h_tab.data() + table(L) + sizeof(LaunchHdr), h.njobs * sizeof(J));
     return v;
   };
   for (size_t li = 0; li < P->seq.size(); ++li) {
-    if (!P->nonempty[li]) continue;
+    if (!class_used(P, li)) continue;
+    tb = P->nonempty[li * kPoolBranches] ? 0 : 1;
     PoolLaunch& L = P->seq[li];
     if (L.kind == Launch::RHS_P && quadrature_ok(L.p)) {
       // right-hand side: quadrature tile variants (and the Kronecker form
@@ -2070,7 +2189,7 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
           L.var = v;
           L.grid = rhs_blocks_per_cu(L.p, L.mixed, v, L.coef) * P->ncu;
           if ((st = pool_rebuild(P)) != ADS_OK) return st;
-          const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off);
+          const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + table(L));
           double ms = 0.0;
           if ((st = timed([&] { return launch_rhs_pwave(L.p, L.mixed, L.var, L.coef, h, L.grid, P->stream); },
                           &ms)) != ADS_OK)
@@ -2112,7 +2231,7 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
             j.counter = nullptr;
           }
           LaunchHdr th{};
-          std::memcpy(&th, P->h_tab.data() + L.off, sizeof(th));
+          std::memcpy(&th, P->h_tab.data() + table(L), sizeof(th));
           std::vector<char> buf(sizeof(LaunchHdr) + js.size() * sizeof(SweepJob));
           std::memcpy(buf.data(), &th, sizeof(th));
           std::memcpy(buf.data() + sizeof(LaunchHdr), js.data(), js.size() * sizeof(SweepJob));
@@ -2137,7 +2256,7 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
   if (host_shape)
     for (size_t li = 0; li < P->seq.size() && (int)li < cap; ++li) {
       const PoolLaunch& L = P->seq[li];
-      host_shape[li] = !P->nonempty[li] ? -1
+      host_shape[li] = !class_used(P, li) ? -1
                        : (L.kind == Launch::RHS_P || L.kind == Launch::RHS_E) ? L.var
                        : L.kind == Launch::SWEEP ? L.w : 0;
     }
@@ -2148,6 +2267,13 @@ ads_status ads_pool_profile(ads_pool* P, int32_t enable) {
   if (!P) return fail(ADS_EINVAL, "NULL pool");
   P->prof = enable != 0;
   P->prof_steps = 0;
+  return ADS_OK;
+}
+
+ads_status ads_pool_set_branches(ads_pool* P, int32_t n) {
+  if (!P) return fail(ADS_EINVAL, "NULL pool");
+  if (n < 1 || n > kPoolBranches) return fail(ADS_EINVAL, "branches must be 1 or 2");
+  P->want_branches = n;
   return ADS_OK;
 }
 
@@ -2164,7 +2290,7 @@ ads_status ads_pool_profile_read(ads_pool* P, double* ms, int32_t* kind, int32_t
       sum += t;
     }
     const PoolLaunch& l = P->seq[i];
-    if (ms) ms[i] = (i < P->nonempty.size() && !P->nonempty[i]) ? -1.0 : (P->prof_steps ? sum / P->prof_steps : 0.0);
+    if (ms) ms[i] = !class_used(P, i) ? -1.0 : (P->prof_steps ? sum / P->prof_steps : 0.0);
     if (kind) {
       // 0 / 5 right-hand sides, 6 in-plane sweeps, 3 z-sweeps, 4 couplings
       kind[i] = l.kind == Launch::RHS_P ? 0 : l.kind == Launch::RHS_E ? 5 : l.kind == Launch::KRON ? 4

@@ -47,13 +47,16 @@ def _alone(cfg, nsteps):
     return out
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_alone_equals_mix_with_staggered_joins(use_graph):
+@pytest.mark.parametrize("use_graph,branches", [(True, 2), (False, 2), (True, 1), (False, 1)])
+def test_alone_equals_mix_with_staggered_joins(use_graph, branches):
+    """Two concurrent branches (the default) or one; a profiled step (one
+    branch, direct launches) in the middle of the run."""
     _cuda()
     from paper_1911_08158_amd import Pool
     nsteps = 6
     ref = [_alone(c, nsteps) for c in MIX]
     pool = Pool(512 << 20, max_slots=16, use_graph=use_graph)
+    pool.set_branches(branches)
     sims = []
     done = {}
     # first half joins at step 0, second half after two pool steps
@@ -69,7 +72,13 @@ def test_alone_equals_mix_with_staggered_joins(use_graph):
         pool.activate(s)
         sims.append((s, c, 2))
     for k in range(2, 2 + nsteps):
-        pool.step(1)
+        if k == 3:
+            pool.profile(True)
+            pool.step(1)
+            pool.profile_read()
+            pool.profile(False)
+        else:
+            pool.step(1)
         for s, c, t0 in sims:
             if s.slot in done:
                 continue
