@@ -1633,14 +1633,14 @@ struct ads_pool {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   ~ads_pool() {
+    // replays still in flight finish before their graphs and streams go
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (side) (void)hipStreamSynchronize(side);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (exec2) (void)hipGraphExecDestroy(exec2);
     if (graph2) (void)hipGraphDestroy(graph2);
-    if (side) {
-      (void)hipStreamSynchronize(side);
-      (void)hipStreamDestroy(side);
-    }
+    if (side) (void)hipStreamDestroy(side);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
