@@ -183,7 +183,8 @@ def measure_plain(cfg, steps, warmup, precision="fp64", coef=False, tune=True):
         xs = [sim.quad_points(d) for d in range(3)]
         sim.set_coefficient(torch.from_numpy(W.wave_speed_field(*xs)).to("cuda:0"), 1.5)
     setup_sim(sim, cfg)
-    var = int(sim.tune()[0]) if tune else None
+    var, vms = sim.tune() if tune else (None, [])
+    var = None if var is None else int(var)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -205,6 +206,7 @@ def measure_plain(cfg, steps, warmup, precision="fp64", coef=False, tune=True):
         "step_ms_p50": float(np.percentile(step_ms, 50)),
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "rhs_variant": var,
+        "rhs_variant_ms": {str(i): round(float(x), 4) for i, x in enumerate(vms) if x == x},
         "timing": f"wall clock over {steps} steps without events; kernels and per-step latency from HIP events "
                   f"in {nprof} profiled steps",
     }
@@ -643,9 +645,12 @@ def main():
         "roofline_batched_rhs": roofline_entry(rhs_b, cfg, args.batch, band_b, True),
         "roofline_plain_fp64_rhs": roofline_entry(rhs64, cfg, 1, band_p, False),
         "gpu": gpu_info(),
-        "precision_note": "right-hand-side contractions on the VALU, not on MFMA: every contraction of the "
-                          "path is a band of width 2p+1 (dense MFMA tiles 15-38 % useful; FP32 MFMA issues at 2x "
-                          "the non-packed FP32 VALU, FP64 MFMA at 1x) and the kernels are bound by memory and "
+        "precision_note": "right-hand-side contractions on the VALU by the tuners' choice: the quadrature's "
+                          "x-stage on FP32 MFMA (4x4x1 blocks, variant 4 with a wave-speed field) is built and "
+                          "timed by the tuner, and loses (see quadrature_rhs.*.rhs_variant_ms: its chain of "
+                          "dependent MFMAs and lane permutes is latency-bound, 6.7 % MFMA busy); every contraction "
+                          "of the path is a band of width 2p+1 (dense MFMA tiles 15-38 % useful; FP32 MFMA issues "
+                          "at 2x the non-packed FP32 VALU, FP64 MFMA at 1x) and the kernels are bound by memory and "
                           "latency; BF16 operands cannot meet 1e-6 on this stiffness action (cancellation ~40) "
                           "without three-way splits. Mixed mode = FP32 stiffness passes on FP64 differences; "
                           "non-packed FP32 vector FMAs issue at the FP64 rate on gfx950, so the FP64 Kronecker "

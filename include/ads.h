@@ -218,7 +218,9 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * variant on this mesh (HIP events, a few launches each; synchronizes) and
  * keeps the fastest.  P-wave: 0-2 are tile shapes of the quadrature kernel,
  * 3 is the Kronecker form (the default; not offered with a wave-speed
- * field).  Elasticity: 0 is the quadrature (FP64), 3 the Kronecker form
+ * field), 4 the quadrature with its x-contractions on the matrix cores
+ * (FP32 MFMA; offered in the mixed modes with a wave-speed field only,
+ * elsewhere it runs as 0).  Elasticity: 0 is the quadrature (FP64), 3 the Kronecker form
  * (the default).  Then, per direction, it times the tile widths 4, 8 and 16
  * lines per wave of the step's sweeps (on copies of their jobs that solve in
  * place with a plain store: only the step's temporaries change, the state
@@ -348,8 +350,9 @@ ads_status ads_pool_retire(ads_pool* pool, int32_t slot);
 ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int32_t* n);
 /* Autotuner of the pool's launch shapes for the current batch (measurement-
  * driven; synchronizes): every P-wave right-hand-side class (degrees 2, 3)
- * times the quadrature tile variants and, without a wave-speed field, the
- * Kronecker form on the batch's own jobs; every sweep class times tile
+ * times the quadrature tile variants, without a wave-speed field the
+ * Kronecker form, and in mixed mode with one the MFMA x-stage (variant 4),
+ * on the batch's own jobs; every sweep class times tile
  * widths of 4, 8 and 16 lines per wave (on a copy of its jobs that solves
  * in place with a plain store, so that no state changes).  Each class keeps
  * its fastest shape; the choices are cached per class and batch shape and

@@ -518,8 +518,14 @@ void rhs_tiles(const ads_sim* s, RhsJob& J, int TX, int TY, long long resident =
 }
 
 // Variant actually run: the Kronecker form (3) has no wave-speed field, so
-// jobs with one take the quadrature kernel's variant 0 instead.
-int rhs_form_var(int var, bool coef) { return (coef && var == 3) ? 0 : var; }
+// jobs with one take the quadrature kernel's variant 0 instead; the MFMA
+// x-stage (4) exists only in mixed mode with a field, other jobs take
+// variant 0 too.
+int rhs_form_var(int var, bool coef, bool mixed) {
+  if (coef && var == 3) return 0;
+  if (var == 4 && !(coef && mixed)) return 0;
+  return var;
+}
 
 // The quadrature kernels (P-wave tile variants 0-2, elasticity variant 0)
 // are instantiated for p = 2 and 3 with q = p+1 Gauss points; every degree
@@ -547,7 +553,7 @@ RhsJob rhs_pwave_job(const ads_sim* s, const double* src, int amp_shift, int mix
   J.rscale = 1.0;
   J.coef = s->coef;
   fill_tables(s, J);
-  var = rhs_form_var(var, s->coef != nullptr);
+  var = rhs_form_var(var, s->coef != nullptr, mixed != 0);
   rhs_tiles(s, J, rhs_tile_x(s->p, var), rhs_tile_y(s->p, mixed, var),
             (long long)rhs_blocks_per_cu(s->p, mixed, var, s->coef != nullptr) * s->ncu,
             var == 3 ? 2 * s->p : s->p);
@@ -776,7 +782,7 @@ ads_status build_launches(ads_sim* s) {
       d = s->arena.add(std::vector<RhsJob>{pj}, err);
       if (!d) return fail(ADS_ENOMEM, err);
       s->step_l.push_back(
-          Launch{Launch::RHS_P, d, 1, pj.ntiles, 0, s->p, -1, rhs_form_var(s->rhs_var, s->coef != nullptr),
+          Launch{Launch::RHS_P, d, 1, pj.ntiles, 0, s->p, -1, rhs_form_var(s->rhs_var, s->coef != nullptr, s->mixed),
                  s->mixed ? 1 : 0, as_bytes(pj)});
       s->step_l.back().coef = s->coef != nullptr;
     }
@@ -791,7 +797,7 @@ ads_status build_launches(ads_sim* s) {
     if (!add_ads_solve(s, s->step_l, s->fS, s->R, s->R, nullptr, 1.0, z, err)) return fail(ADS_ENOMEM, err);
     // start: u''_0 = G^{-1}(F_0 - K u_0)
     // the start is computed in FP64 in every precision mode
-    const int av = rhs_form_var(fp64_aux_var(s), s->coef != nullptr);
+    const int av = rhs_form_var(fp64_aux_var(s), s->coef != nullptr, false);
     RhsJob r0 = rhs_pwave_job(s, s->u, 0, 0, av);
     d = s->arena.add(std::vector<RhsJob>{r0}, err);
     if (!d) return fail(ADS_ENOMEM, err);
@@ -1255,7 +1261,7 @@ ads_status ads_set_launch_shape(ads_sim* s, int32_t rhs_var, int32_t rhs_tz, con
   if (s->pooled) return fail(ADS_ESTATE, "launch shapes of a pooled simulation are the pool's");
   int var = s->rhs_var;
   if (rhs_var >= 0) {
-    const bool ok = rhs_var == 3 || (quadrature_ok(s) && (s->elastic ? rhs_var == 0 : rhs_var <= 2));
+    const bool ok = rhs_var == 3 || (quadrature_ok(s) && (s->elastic ? rhs_var == 0 : (rhs_var <= 2 || rhs_var == 4)));
     if (!ok) return fail(ADS_EINVAL, "right-hand-side variant not available for this problem and degree");
     var = rhs_var;
   }
@@ -1305,7 +1311,8 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!quadrature_ok(s)) cands = {3};
   else if (s->elastic) cands = {0, 3};
   else
-    for (int v = 0; v < rhs_num_variants(s->p, s->coef != nullptr); ++v) cands.push_back(v);
+    for (int v = 0; v <= 4; ++v)
+      if (rhs_variant_exists(s->p, s->mixed, v, s->coef != nullptr)) cands.push_back(v);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
@@ -1692,7 +1699,7 @@ ads_status pool_align(ads_pool* P) {
     if (!sl.active || sl.sim->elastic || !quadrature_ok(sl.sim->p)) continue;
     ads_sim* s = sl.sim;
     const int want = P->var[s->p - 1][s->mixed ? 1 : 0][s->coef != nullptr ? 1 : 0];
-    if (rhs_form_var(s->rhs_var, s->coef != nullptr) == want) continue;
+    if (rhs_form_var(s->rhs_var, s->coef != nullptr, s->mixed) == want) continue;
     s->rhs_var = want;
     ads_status st = build_launches(s);
     if (st != ADS_OK) return st;
@@ -2184,7 +2191,8 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
         best = it->second;
       } else {
         double best_ms = 1e30;
-        for (int v = 0; v < (L.coef ? 3 : 4); ++v) {
+        for (int v = 0; v <= 4; ++v) {
+          if (!rhs_variant_exists(L.p, L.mixed, v, L.coef)) continue;
           cur = v;
           L.var = v;
           L.grid = rhs_blocks_per_cu(L.p, L.mixed, v, L.coef) * P->ncu;

@@ -27,6 +27,14 @@
 //   * a z-layer is written once its last contributing element is done.
 // With a wave-speed field (c^2 at the Gauss points) the three point
 // gradients are scaled by it between the x-forward and x-backward stages.
+// Variant MX (FP32 with a field) runs that x-stage on the matrix cores: one
+// 4x4x1 MFMA block per x-element (16 per wave), its four columns four Gauss
+// rows, the element's own x-tables as the A operand (boundary elements need
+// no special case); the forward result lands in the registers that the
+// backward contraction takes as its B operand, and the backward result is
+// assembled across elements with lane permutes.  It is slower than the
+// VALU form (its chain of dependent MFMAs and permutes per row group is
+// latency-bound), so the autotuner keeps it only where it measures faster.
 // Without one (CF false) nothing pointwise separates a channel's forward and
 // backward contraction in any direction, and each pair collapses to an
 // element matrix, M_d = sum_g w_g N_g N_g^T or K_d = sum_g w_g D_g D_g^T:
@@ -95,6 +103,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One 4x4x1 MFMA step over 16 blocks: block b (lanes 4b..4b+3) adds the
+// outer product of a (lane 4b+i gives row i) and b (lane 4b+j gives column
+// j); lane 4b+j holds column j of its block, element i in register i.
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// value of lane - 4 (the previous 4x4 block); lanes 0-3 get lanes 60-63
+__device__ __forceinline__ float lane_sub4(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane - 4) & 63) << 2, __float_as_int(v)));
+}
+
 template <typename T, int P, int Q, int TY_, int NT_, bool CF>
 struct RhsGeom {
   static constexpr int p = P - 1;
@@ -138,7 +160,7 @@ struct RhsGeom {
 // the four-wave workgroups without one, whose LDS allows five per CU).  CF:
 // the jobs carry a wave-speed field (a separate instantiation, so that the
 // constant coefficient kernels keep their registers).
-template <typename T, int P, int Q, int TY_, int NT_, bool CF>
+template <typename T, int P, int Q, int TY_, int NT_, bool CF, bool MX = false>
 __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <= 256 ? 5 : 4)) : 1) void rhs_pwave_kernel(
     const LaunchHdr* __restrict__ hdr) {
   const int njobs = hdr->njobs, total_tiles = hdr->total_tiles;
@@ -188,6 +210,13 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
   // x-stage rows of this row group: wave rows 4i + grp (same parity as
   // grp, so row i sits 2i rows of TXH further on)
   const int xrow0 = rowpos(wv * WE * Q + grp);
+  // MFMA x-stage (variant MX): lane = 4 * (x-element slot mb) + mj, mj the
+  // Gauss row of the group of four for the B operand and the output, and
+  // the Gauss point (forward) or slot (backward) row of the A operand
+  constexpr bool MF = MX && CF && sizeof(T) == 4;
+  static_assert(!MF || (P <= 4 && Q <= 4), "an element's x-tables fit one 4x4 block");
+  const int mb = lane >> 2, mj = lane & 3;
+  const int xrowm0 = rowpos(wv * WE * Q + mj) + mb;
   // b-stage rows of the owned column: cyo*Q + (p - b)*Q + gy
   const int brow0 = rowpos(cyo * Q) + cxo, bpar = (cyo * Q) & 1;
 
@@ -279,7 +308,28 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
     const int ex = X0 - p + j;
     const bool exv = ex >= 0 && ex < Ex;
     T xN[Q][P], xD[Q][P], xNw[QW][P], xDw[QW][P], xW[QX];
-    {
+    // MFMA x-stage: the tables of x-element mb as A operands: forward
+    // N[g = mj][k], D[g = mj][k]; backward (x-weights folded in)
+    // w_k N[k][a = mj], w_k D[k][a = mj]; zero in padding rows
+    const int exm = X0 - p + mb;
+    const bool exvm = exm >= 0 && exm < Ex;
+    float mfN[P], mfD[P], mbN[Q], mbD[Q];
+    if constexpr (MF) {
+      const gmem<double>* txg = gview(J.tab[0]);
+      const bool fv = exvm && mj < Q, bv = exvm && mj < P;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        mfN[k] = fv ? (float)txg[((long long)exm * Q + mj) * P + k] : 0.f;
+        mfD[k] = fv ? (float)txg[((long long)(Ex + exm) * Q + mj) * P + k] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const double w = bv ? txg[2ll * Ex * Q * P + (long long)exm * Q + k] : 0.0;
+        mbN[k] = bv ? (float)(w * txg[((long long)exm * Q + k) * P + mj]) : 0.f;
+        mbD[k] = bv ? (float)(w * txg[((long long)(Ex + exm) * Q + k) * P + mj]) : 0.f;
+      }
+    }
+    if constexpr (!MF) {
       const gmem<double>* txg = gview(J.tab[0]);
 #pragma unroll
       for (int g = 0; g < Q; ++g) {
@@ -605,6 +655,60 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
         // are x-elements
 #pragma unroll
         for (int i = 0; i < NRW; ++i) {
+          if constexpr (MF) {
+            // rows 4i + mj of the three channels, column of x-element mb
+            T* rm = sbb + xrowm0 + 2 * i * TXH;
+            const int r = wv * WE * Q + 4 * i + mj;
+            const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
+            const bool ok = exvm && ey >= 0 && ey < Ey;
+            const gmem<double>* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
+                                       ((long long)Ex * Q) + (long long)exm * Q;
+            float cq[4];
+#pragma unroll
+            for (int gx = 0; gx < 4; ++gx) cq[gx] = (gx < Q && ok) ? (float)cp[gx] : 0.f;
+            // forward: x-derivative of channel 0 (on differences: the
+            // derivative tables annihilate constants), values of channels
+            // 1 and 2, at the element's Gauss points (register = point)
+            f4 gX = {0.f, 0.f, 0.f, 0.f}, gY = gX, gZ = gX;
+            const float base = rm[0];
+#pragma unroll
+            for (int k = 1; k < P; ++k) gX = mfma4(mfD[k], rm[k] - base, gX);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+              gY = mfma4(mfN[k], rm[SBC + k], gY);
+              gZ = mfma4(mfN[k], rm[2 * SBC + k], gZ);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              gX[g] *= cq[g];
+              gY[g] *= cq[g];
+              gZ[g] *= cq[g];
+            }
+            // backward: point values in registers are the B operand of the
+            // K-steps (register k = Gauss point k); register = slot
+            f4 oX = {0.f, 0.f, 0.f, 0.f}, oY = oX, oZ = oX;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              oX = mfma4(mbD[k], gX[k], oX);
+              oY = mfma4(mbN[k], gY[k], oY);
+              oZ = mfma4(mbN[k], gZ[k], oZ);
+            }
+            // coefficient of slot mb - p collects slot a of element mb - a
+            // (the block 4a lanes down)
+            float tX = oX[P - 1], tY = oY[P - 1], tZ = oZ[P - 1];
+#pragma unroll
+            for (int a = P - 2; a >= 0; --a) {
+              tX = oX[a] + lane_sub4(tX, lane);
+              tY = oY[a] + lane_sub4(tY, lane);
+              tZ = oZ[a] + lane_sub4(tZ, lane);
+            }
+            if (mb >= p) {
+              rm[-p] = tX;
+              rm[SBC - p] = tY;
+              rm[2 * SBC - p] = tZ;
+            }
+            continue;
+          }
           T* row = sbb + xrow0 + 2 * i * TXH;
           // wave-speed field: the lane's q points of this Gauss row (0 outside the mesh)
           T cq[Q];
@@ -773,32 +877,48 @@ static const RhsVariant kVarP3F[] = {{13, 256}, {29, 512}, {21, 384}};
 static const RhsVariant kVarP3D[] = {{13, 256}, {21, 384}, {9, 192}};
 
 // variant 3: the Kronecker (assembled band) form of k_rhs_band.hip, for
-// jobs without a wave-speed field
-int rhs_num_variants(int, int coef) { return coef ? 3 : 4; }
+// jobs without a wave-speed field; variant 4: the MFMA x-stage (FP32 with a
+// field), at one tile shape per degree
+static constexpr RhsVariant kVarMX[] = {{10, 192}, {13, 256}};
+bool rhs_variant_exists(int p, int mixed, int var, int coef) {
+  const bool quad = p == 2 || p == 3;
+  if (var == 3) return !coef;
+  if (var == 4) return quad && coef && mixed;
+  return quad && var >= 0 && var <= 2;
+}
 int rhs_tile_x(int p, int var) { return var == 3 ? rhs_band_tile_x() : 16 - p; }
 int rhs_tile_y(int p, int mixed, int var) {
   if (var == 3) return rhs_band_tile_y();
+  if (var == 4) return kVarMX[p <= 2 ? 0 : 1].TY;
   if (var < 0 || var > 2) var = 0;
   if (p <= 2) return mixed ? kVarP2F[var].TY : kVarP2D[var].TY;
   return mixed ? kVarP3F[var].TY : kVarP3D[var].TY;
 }
 
 // op 0: launch; op 1: *out = resident workgroups per CU (persistent grids)
-template <typename T, int P, int TY, int NT, bool CF>
+template <typename T, int P, int TY, int NT, bool CF, bool MX = false>
 static hipError_t launch_one(const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
   using Gm = RhsGeom<T, P, P, TY, NT, CF>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF>,
+    hipError_t e = hipFuncSetAttribute((const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF, MX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::lds_bytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (op == 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF>, NT,
-                                                        Gm::lds_bytes);
-  hipLaunchKernelGGL((rhs_pwave_kernel<T, P, P, TY, NT, CF>), dim3(grid), dim3(NT), Gm::lds_bytes, s, d_hdr);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)rhs_pwave_kernel<T, P, P, TY, NT, CF, MX>,
+                                                        NT, Gm::lds_bytes);
+  hipLaunchKernelGGL((rhs_pwave_kernel<T, P, P, TY, NT, CF, MX>), dim3(grid), dim3(NT), Gm::lds_bytes, s, d_hdr);
   return hipGetLastError();
+}
+
+// variant 4 (mixed mode with a field only)
+static hipError_t launch_mx(int p, const LaunchHdr* d_hdr, int grid, hipStream_t s, int op, int* out) {
+  static_assert(kVarMX[0].TY == 10 && kVarMX[0].NT == 192 && kVarMX[1].TY == 13 && kVarMX[1].NT == 256,
+                "variant 4 instantiations");
+  if (p == 2) return launch_one<float, 3, 10, 192, true, true>(d_hdr, grid, s, op, out);
+  return launch_one<float, 4, 13, 256, true, true>(d_hdr, grid, s, op, out);
 }
 
 template <bool CF>
@@ -843,6 +963,7 @@ hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr
   if (grid <= 0) return hipSuccess;
   if (var == 3) return coef ? hipErrorInvalidValue : launch_rhs_band(p, mixed, d_hdr, grid, s);
   if (p != 2 && p != 3) return hipErrorInvalidValue;   // the quadrature is instantiated for p = 2, 3
+  if (var == 4) return (coef && mixed) ? launch_mx(p, d_hdr, grid, s, 0, nullptr) : hipErrorInvalidValue;
   if (var < 0 || var > 2) var = 0;
   return dispatch(p, mixed, var, coef, d_hdr, grid, s, 0, nullptr);
 }
@@ -850,8 +971,12 @@ hipError_t launch_rhs_pwave(int p, int mixed, int var, int coef, const LaunchHdr
 int rhs_blocks_per_cu(int p, int mixed, int var, int coef) {
   if (var == 3 && !coef) return rhs_band_blocks_per_cu(p, mixed);
   if (p != 2 && p != 3) return 1;
-  if (var < 0 || var > 2) var = 0;
   int n = 1;
+  if (var == 4 && coef && mixed) {
+    (void)launch_mx(p, nullptr, 0, nullptr, 1, &n);
+    return n < 1 ? 1 : n;
+  }
+  if (var < 0 || var > 2) var = 0;
   (void)dispatch(p, mixed, var, coef, nullptr, 0, nullptr, 1, &n);
   return n < 1 ? 1 : n;
 }

@@ -27,7 +27,7 @@ hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int
 // kernel; variant 3 is the Kronecker (assembled band) form, for jobs
 // without a wave-speed field only.  coef: the jobs carry a wave-speed
 // field (RhsJob::coef).
-int rhs_num_variants(int p, int coef);
+bool rhs_variant_exists(int p, int mixed, int var, int coef);
 int rhs_tile_x(int p, int var);
 int rhs_tile_y(int p, int mixed, int var);
 int rhs_blocks_per_cu(int p, int mixed, int var, int coef);
