@@ -85,7 +85,9 @@ __device__ __forceinline__ float bf16_round_band(float x) {
 // in which FP32-rounded entries still annihilate constants (s_i is zero
 // away from eliminated boundary coefficients); z keeps K (FP64 pass).
 
-// workgroups per CU: two (four waves per SIMD) at p <= 3, one above
+// at least two waves per SIMD at p <= 3 (the second launch-bounds argument
+// is waves per SIMD); at p = 2 the registers (128) allow four, i.e. two
+// workgroups per CU
 template <typename T, int p>
 __global__ __launch_bounds__(BNT, p <= 3 ? 2 : 1) void rhs_band_kernel(const LaunchHdr* __restrict__ hdr) {
   using Gm = BandGeom<T, p>;
