@@ -49,7 +49,7 @@ def rhs_flops_per_element(p, q=None):
 
 
 SWEEP_BYTES = {"sweep_x": 16, "sweep_y": 16, "sweep_xy": 16,   # per free DOF; x and y in one in-plane launch: 16
-               "sweep_z": 56}   # z fused with the Newmark update: reads the input and (w, u', u''), writes them
+               "sweep_z": 48}   # z fused with the Newmark update: reads the input and (w, b), writes (w, b, u'')
 
 RHS_BYTES = 16   # per free DOF: reads the predictor u + tau u' + tau^2/4 u'', writes R
 

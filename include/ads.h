@@ -206,12 +206,15 @@ ads_status ads_set_scheme(ads_sim* sim, int32_t scheme);
 ads_status ads_energy(ads_sim* sim, double* host_energy);
 
 /* Advance nsteps time steps (asynchronous).  ADS_ESTATE before ads_factor.
- * P-wave: the steps advance (w, u', u''), w = u + tau u' + tau^2/4 u'' the
- * predictor of the next step (ADS_SCHEME_LITERAL: w = u + tau u'), so that
- * each step's right-hand side reads one field; the z-sweep forms
- * u_{n+1} = w_n + tau^2/4 u''_{n+1} and the next w.  u is formed from
- * (w, u', u'') when it is read (ads_get_state, ads_energy,
- * ads_check_finite), w from (u, u', u'') when the state is set. */
+ * P-wave: the steps advance (w, b, u''), w = u + tau u' + tau^2/4 u'' the
+ * predictor of the next step and b = u' + tau/2 u'' the half-step velocity
+ * (ADS_SCHEME_LITERAL: (w, u', u''), w = u + tau u'), so that each step's
+ * right-hand side reads one field and its update two: with the solved
+ * u''_{n+1}, the z-sweep forms w_{n+1} = w_n + tau b_n + tau^2 u''_{n+1} and
+ * b_{n+1} = b_n + tau u''_{n+1} (the Newmark update of u and u' written in
+ * these fields).  u and u' are formed from (w, b, u'') when they are read
+ * (ads_get_state, ads_energy, ads_check_finite), w and b from (u, u', u'')
+ * when the state is set. */
 ads_status ads_step(ads_sim* sim, int32_t nsteps);
 
 /* Autotuner of the right-hand side (measurement-driven): times every
@@ -258,10 +261,12 @@ ads_status ads_set_state(ads_sim* sim, const double* dev_u, const double* dev_v,
 /* Checkpoint: the time-stepping state itself (full layout; asynchronous on
  * the sim's stream), so that a restored simulation continues bitwise as the
  * original would (a round trip through ads_get_state / ads_set_state agrees
- * to rounding only, since the P-wave u is formed from the stepping state).
- * P-wave: dev_s0 = w = u + tau u' + tau^2/4 u'' (ADS_SCHEME_LITERAL:
- * u + tau u'), dev_s1 = u', dev_s2 = u''; elasticity: dev_s0 = U^n,
- * dev_s1 = U^{n-1}, dev_s2 ignored.  Every pointer but dev_s2 of
+ * to rounding only, since the P-wave u and u' are formed from the stepping
+ * state).
+ * P-wave: dev_s0 = w = u + tau u' + tau^2/4 u'', dev_s1 = b = u' + tau/2 u''
+ * (ADS_SCHEME_LITERAL: w = u + tau u', dev_s1 = u'), dev_s2 = u'';
+ * elasticity: dev_s0 = U^n, dev_s1 = U^{n-1}, dev_s2 ignored.  Every
+ * pointer but dev_s2 of
  * elasticity must be non-NULL.  Save: ADS_ESTATE before ads_factor.  Load
  * restores the state and the step index; stepping continues without
  * ads_factor if the sim was factored (the load may precede ads_factor). */

@@ -175,12 +175,15 @@ struct ads_sim {
   double* red;          // dot-product partial sums + 3 results
   DevFactor fS[3], fS2[3], fM[3];  // P-wave: fS = M + eta K; elastic: fS = mu, fS2 = 2mu+lam
   double *u, *v, *a, *R, *X, *T, *Y, *Z, *load, *amp;
-  // P-wave: the time step advances (w, v, a), w = u + tau v + eta a the
-  // predictor of the next step (printed coefficient set: w = u + tau v), so
-  // that its right-hand side reads one field; u is formed from them when it
-  // is read (w_stale: w must be formed from u, v, a, after the state was
-  // set; u_stale: u must be formed from w, v, a, after time steps)
+  // P-wave: the time step advances (w, b, a), w = u + tau v + eta a the
+  // predictor of the next step and b = v + tau/2 a the half-step velocity
+  // (printed coefficient set: (w, v, a), w = u + tau v), so that its
+  // right-hand side reads one field and its update two; u and v are formed
+  // from them when read (w_stale: w and b must be formed from u, v, a,
+  // after the state was set; u_stale: u and v must be formed from w, b, a,
+  // after time steps)
   double* w = nullptr;
+  double* b = nullptr;
   bool w_stale = true, u_stale = false;
   unsigned long long* counter;
   unsigned long long* flag;
@@ -345,6 +348,7 @@ void carve(ads_sim* s, Carver& c) {
   } else {
     s->a = c.dbl(nfr);
     s->w = c.dbl(nfr);
+    s->b = c.dbl(nfr);
     s->T = s->Y = s->Z = nullptr;
     for (int d = 0; d < 3; ++d) s->d_bandA[d] = c.dbl((size_t)s->nf[d] * (2 * p + 1));
   }
@@ -736,22 +740,27 @@ ads_status upload_factor(ads_sim* s, const DevFactor& f, const Band& A) {
   return upload(s, f.rd, lu.rd.data(), lu.rd.size() * 8);
 }
 
-// P-wave: the predictor w from the state u, v, a (after the state was set
-// or started), and u back from w, v, a (after time steps), on the stream.
+// P-wave: the stepping state (w, b) from u, v, a (after the state was set or
+// started), and u, v back from w, b, a (after time steps), on the stream.
+// The printed coefficient set steps (w, v, a): only w and u convert.
 ads_status sync_predictor(ads_sim* s) {
   if (s->elastic || !s->w_stale) return ADS_OK;
   const double tau = s->prm.tau;
   HIPCHECK(launch_lin3(s->w, s->u, s->v, s->literal ? nullptr : s->a, tau, 0.25 * tau * tau, s->nfree, s->stream));
+  if (!s->literal) HIPCHECK(launch_lin3(s->b, s->v, s->a, nullptr, 0.5 * tau, 0.0, s->nfree, s->stream));
   s->w_stale = false;
   return ADS_OK;
 }
 ads_status materialize_u(ads_sim* s) {
   if (s->elastic || !s->u_stale) return ADS_OK;
   const double tau = s->prm.tau;
+  if (!s->literal) HIPCHECK(launch_lin3(s->v, s->b, s->a, nullptr, -0.5 * tau, 0.0, s->nfree, s->stream));
   HIPCHECK(launch_lin3(s->u, s->w, s->v, s->literal ? nullptr : s->a, -tau, -0.25 * tau * tau, s->nfree, s->stream));
   s->u_stale = false;
   return ADS_OK;
 }
+// the stepping state's second field: b (Newmark) or v (printed set)
+double* step_field1(const ads_sim* s) { return s->literal ? s->v : s->b; }
 
 // (Re)build every job table and launch list; uploads the arena.
 ads_status build_launches(ads_sim* s) {
@@ -761,7 +770,7 @@ ads_status build_launches(ads_sim* s) {
   s->start_l.clear();
   s->projM_l.clear();
   s->energy_l.clear();
-  const double tau = s->prm.tau, eta = 0.25 * tau * tau;
+  const double tau = s->prm.tau;
   if (!s->elastic) {
     // step: RHS with the Newmark predictor, sweeps, z-sweep fused with the update
     // (the printed coefficient set drops the u'' term of the predictor)
@@ -789,9 +798,9 @@ ads_status build_launches(ads_sim* s) {
     SweepJob z{};
     z.epi = s->literal ? EPI_NEWMARK_LITERAL : EPI_NEWMARK;
     z.c0 = tau;
-    z.c1 = eta;
+    z.c1 = tau * tau;
     z.e0 = s->w;
-    z.e1 = s->v;
+    z.e1 = step_field1(s);
     z.e2 = s->a;
     z.counter = s->counter;
     if (!add_ads_solve(s, s->step_l, s->fS, s->R, s->R, nullptr, 1.0, z, err)) return fail(ADS_ENOMEM, err);
@@ -1470,7 +1479,7 @@ ads_status ads_check_finite(ads_sim* s) {
 
 ads_status ads_get_state(ads_sim* s, double* u, double* v, double* a) {
   if (!s) return fail(ADS_EINVAL, "NULL sim");
-  if (u) {
+  if (u || v) {
     ads_status st = materialize_u(s);
     if (st != ADS_OK) return st;
   }
@@ -1516,7 +1525,7 @@ ads_status ads_checkpoint_save(ads_sim* s, double* s0, double* s1, double* s2) {
   ads_status st = sync_predictor(s);
   if (st != ADS_OK) return st;
   HIPCHECK(launch_free_to_full(s->w, s0, s->n, s->nf, s->off, 1, s->stream));
-  HIPCHECK(launch_free_to_full(s->v, s1, s->n, s->nf, s->off, 1, s->stream));
+  HIPCHECK(launch_free_to_full(step_field1(s), s1, s->n, s->nf, s->off, 1, s->stream));
   HIPCHECK(launch_free_to_full(s->a, s2, s->n, s->nf, s->off, 1, s->stream));
   return ADS_OK;
 }
@@ -1530,7 +1539,7 @@ ads_status ads_checkpoint_load(ads_sim* s, const double* s0, const double* s1, c
     HIPCHECK(launch_full_to_free(s1, s->v, s->n, s->nf, s->off, nc, s->stream));
   } else {
     HIPCHECK(launch_full_to_free(s0, s->w, s->n, s->nf, s->off, 1, s->stream));
-    HIPCHECK(launch_full_to_free(s1, s->v, s->n, s->nf, s->off, 1, s->stream));
+    HIPCHECK(launch_full_to_free(s1, step_field1(s), s->n, s->nf, s->off, 1, s->stream));
     HIPCHECK(launch_full_to_free(s2, s->a, s->n, s->nf, s->off, 1, s->stream));
     s->w_stale = false;
     s->u_stale = true;

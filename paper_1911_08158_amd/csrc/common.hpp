@@ -65,9 +65,12 @@ struct Factor1D {
 // Epilogue applied by a sweep to every solved value x at global offset g.
 enum SweepEpi : int {
   EPI_STORE = 0,     // out[g] = x
-  // Newmark on the state (w, v, a), w = u + tau v + eta a the predictor of
-  // the next step (u itself is w - tau v - eta a):
-  //   a' = x; v' = v + tau/2 (a + a'); u' = w + eta a'; w' = u' + tau v' + eta a'
+  // Newmark on the state (w, b, a): w = u + tau v + eta a the predictor of
+  // the next step, b = v + tau/2 a the half-step velocity (v = b - tau/2 a,
+  // u = w - tau v - eta a).  With a' = x, v' = v + tau/2 (a + a') and
+  // u' = w + eta a' (eta = tau^2/4) they advance as
+  //   w' = u' + tau v' + eta a' = w + tau b + tau^2 a',  b' = b + tau a'
+  // (two fields read, three written: a' is kept for the state's readers)
   EPI_NEWMARK = 1,
   EPI_THREELEVEL = 2, // out[g] = x; U^{n-1} <- U^n; U^n <- 2 U^n - U^{n-1} + x
   // printed coefficient set on (w, v, a), w = u + tau v:
@@ -88,10 +91,10 @@ struct SweepJob {
   int ntiles;
   int epi;
   double scale;     // the input is multiplied by this before the solve
-  double c0, c1;    // EPI_NEWMARK: tau, eta
-  double* e0;       // EPI_NEWMARK: w   EPI_THREELEVEL: U^n
-  double* e1;       // EPI_NEWMARK: v   EPI_THREELEVEL: U^{n-1}
-  double* e2;       // EPI_NEWMARK: a
+  double c0, c1;    // EPI_NEWMARK: tau, tau^2   EPI_NEWMARK_LITERAL: tau
+  double* e0;       // EPI_NEWMARK(_LITERAL): w   EPI_THREELEVEL: U^n
+  double* e1;       // EPI_NEWMARK: b (literal: v)   EPI_THREELEVEL: U^{n-1}
+  double* e2;       // EPI_NEWMARK(_LITERAL): a
   unsigned long long* counter;  // incremented once by the job (end of a step)
 };
 

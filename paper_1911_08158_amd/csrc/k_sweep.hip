@@ -85,20 +85,17 @@ __device__ __forceinline__ void epilogue_batch(const EpiView& E, const long long
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) E.out[g[k]] = x[k];
   } else if (E.epi == EPI_NEWMARK) {
-    double w[kEpi], v[kEpi], a[kEpi];
+    double w[kEpi], b[kEpi];
 #pragma unroll
     for (int k = 0; k < kEpi; ++k) {
       w[k] = E.e0[g[k]];
-      v[k] = E.e1[g[k]];
-      a[k] = E.e2[g[k]];
+      b[k] = E.e1[g[k]];
     }
 #pragma unroll
     for (int k = 0; k < kEpi; ++k)
       if (ok[k]) {
-        const double vn = v[k] + 0.5 * E.c0 * (a[k] + x[k]);
-        const double un = fma(E.c1, x[k], w[k]);
-        E.e0[g[k]] = fma(E.c1, x[k], fma(E.c0, vn, un));
-        E.e1[g[k]] = vn;
+        E.e0[g[k]] = fma(E.c1, x[k], fma(E.c0, b[k], w[k]));
+        E.e1[g[k]] = fma(E.c0, x[k], b[k]);
         E.e2[g[k]] = x[k];
       }
   } else if (E.epi == EPI_NEWMARK_LITERAL) {

@@ -60,11 +60,11 @@ def test_workspace_scales_linearly(lib):
     b1 = binding.workspace_bytes(_params(nelem=(30, 30, 30)))
     b2 = binding.workspace_bytes(_params(nelem=(60, 60, 60)))
     nf1, nf2 = 30 ** 3, 60 ** 3
-    # 7 FP64 fields (u, v, a, R, X, load, the predictor) plus O(n) tables
+    # 8 FP64 fields (u, v, a, R, X, load, the predictor w, the half-step velocity b) plus O(n) tables
     assert 6 * 8 * nf1 < b1 < 12 * 8 * nf1
     assert 6 * 8 * nf2 < b2 < 12 * 8 * nf2
     be = binding.workspace_bytes(_params(problem="elastic", nelem=(30, 30, 30)))
-    assert be > 2.5 * b1
+    assert be > 2.2 * b1   # elasticity: 20 FP64 fields (3 components of u, v, R, load, Y, Z; X, T) against 8
 
 
 def test_two_dimensional_layout(lib):

@@ -32,9 +32,9 @@ def test_rhs_flop_count():
 
 def test_sweep_bytes_per_dof():
     # in-plane x+y: read R, write the y-solved field; z with the Newmark
-    # update: read X and the state (w, u', u''), write the state
+    # update: read X and the stepping fields (w, b), write (w, b, u'')
     assert bench.SWEEP_BYTES["sweep_xy"] == 8 + 8
-    assert bench.SWEEP_BYTES["sweep_z"] == 8 + 3 * 8 + 3 * 8
+    assert bench.SWEEP_BYTES["sweep_z"] == 8 + 2 * 8 + 3 * 8
 
 
 def test_more_than_one_gpu_refused():
@@ -52,10 +52,10 @@ def test_rhs_bytes_and_roofline_entries():
     assert bench.RHS_BYTES == 8 + 8
     cfg = W.C3
     nfree = 128 ** 3 * 4
-    row = {"kernel": "sweep_z", "ms": 0.1, "gbs": round(56 * nfree / 1e-4 / 1e9, 1)}
+    row = {"kernel": "sweep_z", "ms": 0.1, "gbs": round(48 * nfree / 1e-4 / 1e9, 1)}
     e = bench.roofline_entry(row, cfg, 4, True, True)
     assert e["bound"] == "hbm" and e["unit"] == "GB/s" and e["peak"] == 8000.0
-    assert abs(e["frac"] - 56 * nfree / 1e-4 / 1e9 / 8000.0) < 1e-4
+    assert abs(e["frac"] - 48 * nfree / 1e-4 / 1e9 / 8000.0) < 1e-4
     row = {"kernel": "rhs", "ms": 0.1, "gbs": 100.0, "tflops": 1.0}
     assert bench.roofline_entry(row, cfg, 4, True, True)["bound"] == "hbm"
     q = bench.roofline_entry(row, cfg, 4, False, True)
