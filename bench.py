@@ -60,9 +60,9 @@ RHS_BYTES = 16   # per free DOF: reads the predictor u + tau u' + tau^2/4 u'', w
 # launch's traffic is reported as null once its sources hash differently.
 TRAFFIC = {
     "rhs": {"sources": ["paper_1911_08158_amd/csrc/k_rhs_band.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-            "sha256": "e4968a98551f7f95822531d51a7c0e0df819a81bafe57fce000d274c93bfb0a3", "fetch_kib": 36047.5, "write_kib": 65536.0},
+            "sha256": "271389f7f6887f3aa213f9b0ad3774af340dc51eb96fa4cbf3ff264da3bce267", "fetch_kib": 36047.5, "write_kib": 65536.0},
     "sweep_z": {"sources": ["paper_1911_08158_amd/csrc/k_sweep.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-                "sha256": "de9cd1fe15df7ab3a9acae00200c7c506d2796bbcf88f8073c2aba276b8f19c3", "fetch_kib": 131268.0, "write_kib": 196608.1},
+                "sha256": "9ef6f2f7d1359b1777cc74f89cf3d96457930709c581413ad99a6f119acc9a40", "fetch_kib": 98499.2, "write_kib": 196608.1},
     "fetch_scale": 2.0, "write_scale": 1.0,
     "batch": 4,
 }
