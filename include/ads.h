@@ -324,12 +324,14 @@ typedef struct ads_pool ads_pool;
  * use_graph = 0 enqueues the launches directly instead of replaying. */
 ads_status ads_pool_create(void* dev_workspace, size_t bytes, int32_t max_slots, void* hip_stream,
                            int32_t use_graph, ads_pool** out);
-/* Admission by memory: carves a simulation (zero state) for prm from the
- * pool workspace; ADS_ENOMEM when no slot or not enough contiguous bytes
- * are free right now (try again after a retirement).  The new slot is
- * inactive: configure it through ads_pool_sim (ads_project, ads_set_state,
- * ads_set_load, ads_factor), then ads_pool_activate. */
-ads_status ads_pool_admit(ads_pool* pool, const ads_params* prm, int32_t* slot);
+/* Admission by memory: carves a simulation for prm from the pool
+ * workspace, with initial coefficients dev_u0 / dev_v0 as in ads_create
+ * (full layout; NULL = zero); ADS_ENOMEM when no slot or not enough
+ * contiguous bytes are free right now (try again after a retirement).  The
+ * new slot is inactive: configure it through ads_pool_sim (ads_project,
+ * ads_set_state, ads_set_load, ads_factor), then ads_pool_activate. */
+ads_status ads_pool_admit(ads_pool* pool, const ads_params* prm, const double* dev_u0, const double* dev_v0,
+                          int32_t* slot);
 ads_status ads_pool_sim(ads_pool* pool, int32_t slot, ads_sim** sim);
 /* Join the batch from the next pool step (the simulation must be factored). */
 ads_status ads_pool_activate(ads_pool* pool, int32_t slot);
@@ -347,9 +349,12 @@ ads_status ads_pool_step(ads_pool* pool, int32_t nsteps);
  * 1 (every launch class of the batch in one launch on the pool's stream).
  * Profiled steps (ads_pool_profile) use one.  ADS_EINVAL otherwise. */
 ads_status ads_pool_set_branches(ads_pool* pool, int32_t n);
-/* Leave the batch and release the slot's memory (read the state first with
- * ads_get_state on ads_pool_sim's handle; the release is stream-ordered). */
-ads_status ads_pool_retire(ads_pool* pool, int32_t slot);
+/* Leave the batch and release the slot's memory.  dev_u, dev_v, dev_a
+ * (each may be NULL) receive the final state as ads_get_state gives it
+ * (P-wave u, u', u''; elasticity U^n, U^{n-1}, dev_a ignored), copied on the
+ * pool's stream before the release; the release is stream-ordered, so
+ * later admissions reuse the memory after the copies. */
+ads_status ads_pool_retire(ads_pool* pool, int32_t slot, double* dev_u, double* dev_v, double* dev_a);
 /* Durations (ms) of the pool steps since the last call (synchronizes); at
  * most 65536 steps are timed between two calls, later ones are not. */
 ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int32_t* n);

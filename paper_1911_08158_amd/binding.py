@@ -133,12 +133,12 @@ def load_library():
                              POINTER(c_int32)],
         "ads_destroy": [c_void_p],
         "ads_pool_create": [c_void_p, c_size_t, c_int32, c_void_p, c_int32, POINTER(c_void_p)],
-        "ads_pool_admit": [c_void_p, P, POINTER(c_int32)],
+        "ads_pool_admit": [c_void_p, P, c_void_p, c_void_p, POINTER(c_int32)],
         "ads_pool_sim": [c_void_p, c_int32, POINTER(c_void_p)],
         "ads_pool_activate": [c_void_p, c_int32],
         "ads_pool_step": [c_void_p, c_int32],
         "ads_pool_set_branches": [c_void_p, c_int32],
-        "ads_pool_retire": [c_void_p, c_int32],
+        "ads_pool_retire": [c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
         "ads_pool_step_times": [c_void_p, c_void_p, c_int32, POINTER(c_int32)],
         "ads_pool_info": [c_void_p, POINTER(c_int32), POINTER(c_size_t), POINTER(c_size_t)],
         "ads_pool_destroy": [c_void_p],
@@ -322,8 +322,10 @@ class Sim:
 
     def checkpoint(self):
         """The time-stepping state (full layout) and the step index, from
-        which checkpoint_restore continues bitwise: P-wave (w, u', u''),
-        w = u + tau u' + tau^2/4 u''; elasticity (U^n, U^{n-1}, None)."""
+        which checkpoint_restore continues bitwise: P-wave (w, b, u''),
+        w = u + tau u' + tau^2/4 u'' and b = u' + tau/2 u'' (printed
+        coefficient set: (w, u', u''), w = u + tau u'); elasticity
+        (U^n, U^{n-1}, None)."""
         s0, s1 = self._empty_full(), self._empty_full()
         s2 = self._empty_full() if self.prm.comps == 1 else None
         self._pre()
@@ -428,11 +430,14 @@ class Pool:
         self._h = h
         self.sims = {}
 
-    def admit(self, cfg=None, **kw):
-        """Returns a PooledSim, or None when memory or slots are exhausted."""
+    def admit(self, cfg=None, u0=None, v0=None, **kw):
+        """Returns a PooledSim, or None when memory or slots are exhausted.
+        u0 / v0: initial coefficients (full layout, FP64 device tensors) or
+        None (zero)."""
         prm = Params.of(cfg, **kw)
         slot = c_int32()
-        st = load_library().ads_pool_admit(self._h, byref(prm), byref(slot))
+        nf = prm.full_numel
+        st = load_library().ads_pool_admit(self._h, byref(prm), _ptr(u0, nf, "u0"), _ptr(v0, nf, "v0"), byref(slot))
         if st == -2:
             return None
         _check(st)
@@ -459,10 +464,23 @@ class Pool:
         _check(load_library().ads_pool_tune(self._h, byref(n), shape.ctypes.data, shape.size))
         return n.value, shape
 
-    def retire(self, sim):
-        _check(load_library().ads_pool_retire(self._h, sim.slot))
+    def retire(self, sim, state=False):
+        """Release the slot; with state=True first copy out and return its
+        final (u, v, a) as ads_get_state gives it (a None for elasticity)."""
+        out = None
+        if state:
+            u, v = sim._empty_full(), sim._empty_full()
+            a = sim._empty_full() if sim.prm.comps == 1 else None
+            nf = sim.prm.full_numel
+            _check(load_library().ads_pool_retire(self._h, sim.slot, _ptr(u, nf, "u"), _ptr(v, nf, "v"),
+                                                  _ptr(a, nf, "a")))
+            self.stream.synchronize()
+            out = (u, v, a)
+        else:
+            _check(load_library().ads_pool_retire(self._h, sim.slot, None, None, None))
         self.sims.pop(sim.slot, None)
         sim.close()
+        return out
 
     def step_times(self, cap=1 << 16):
         ms = np.zeros(cap)

@@ -1977,7 +1977,8 @@ ads_status ads_pool_create(void* ws, size_t bytes, int32_t max_slots, void* stre
   return ADS_OK;
 }
 
-ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
+ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, const double* dev_u0, const double* dev_v0,
+                          int32_t* slot) {
   if (!P || !prm || !slot) return fail(ADS_EINVAL, "NULL argument");
   std::string why;
   if (!valid_params(prm, why)) return fail(ADS_EINVAL, why);
@@ -2012,7 +2013,7 @@ ads_status ads_pool_admit(ads_pool* P, const ads_params* prm, int32_t* slot) {
   // elasticity takes the Kronecker form in every pool
   g_force_var = (prm->problem == ADS_ELASTIC || !quadrature_ok(prm->p))
                     ? 3 : P->var[prm->p - 1][prm->precision == ADS_MIXED_FP32 ? 1 : 0][0];
-  ads_status st = ads_create(prm, P->ws + found, need, P->stream, nullptr, nullptr, &s);
+  ads_status st = ads_create(prm, P->ws + found, need, P->stream, dev_u0, dev_v0, &s);
   g_force_var = -1;
   if (st != ADS_OK) return st;
   s->pooled = true;
@@ -2321,9 +2322,15 @@ ads_status ads_pool_profile_read(ads_pool* P, double* ms, int32_t* kind, int32_t
   return ADS_OK;
 }
 
-ads_status ads_pool_retire(ads_pool* P, int32_t slot) {
+ads_status ads_pool_retire(ads_pool* P, int32_t slot, double* dev_u, double* dev_v, double* dev_a) {
   if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].sim) return fail(ADS_EINVAL, "bad slot");
   ads_pool::Slot& sl = P->slots[slot];
+  // the final state, copied out on the pool's stream before the memory is
+  // released (later admissions reuse it in stream order)
+  if (dev_u || dev_v || dev_a) {
+    ads_status st = ads_get_state(sl.sim, dev_u, dev_v, dev_a);
+    if (st != ADS_OK) return st;
+  }
   delete sl.sim;
   P->used.erase(sl.off);
   if (sl.active) P->dirty = true;

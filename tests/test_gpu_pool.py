@@ -119,6 +119,50 @@ def test_pool_matches_oracle_and_mixed_error():
     pool.close()
 
 
+@pytest.mark.parametrize("cfg", [W.C1.with_(nelem=(14, 12, 10), tau=0.01, steps=6),
+                                 W.C4.with_(nelem=(7, 6, 8), tau=0.02, steps=4)], ids=["pwave", "elastic"])
+def test_admit_with_fields_and_retire_with_state(cfg):
+    """ads_pool_admit takes the initial coefficients and ads_pool_retire
+    hands back the final state: bitwise the run of the same fields alone
+    (ads_create with them); the P-wave also against the oracle; the freed
+    memory takes the next admission."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool, Sim
+    if cfg.problem == "pwave":
+        pw, u0r, (ur, vr, ar) = oracle_pwave(cfg, cfg.steps)
+        u0 = torch.from_numpy(pw.to_full(u0r)).cuda()
+        v0 = torch.zeros_like(u0)
+    else:
+        from paper_1911_08158_amd.binding import Params
+        n = Params.of(cfg).full_numel
+        g = np.random.default_rng(7)
+        u0 = torch.from_numpy(g.uniform(-1, 1, n)).cuda()
+        v0 = torch.from_numpy(g.uniform(-1, 1, n)).cuda()
+    alone = Sim(cfg, device="cuda", u0=u0, v0=v0)
+    alone.factor()
+    alone.step(cfg.steps)
+    ref = [t.cpu().numpy() for t in alone.get_state() if t is not None]
+    alone.close()
+    pool = Pool(128 << 20, max_slots=4)
+    s = pool.admit(cfg, u0=u0, v0=v0)
+    slot = s.slot
+    s.factor()
+    pool.activate(s)
+    pool.step(cfg.steps)
+    got = [t.cpu().numpy() for t in pool.retire(s, state=True) if t is not None]
+    assert len(got) == len(ref)
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    if cfg.problem == "pwave":
+        for x, r in zip(got, (ur, vr, ar)):
+            assert rel_l2(x, pw.to_full(r)) <= 1e-12
+    nxt = pool.admit(cfg)
+    assert nxt is not None and nxt.slot == slot
+    assert pool.retire(nxt) is None
+    pool.close()
+
+
 def test_admission_by_memory():
     _cuda()
     from paper_1911_08158_amd import Pool
