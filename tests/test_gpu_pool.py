@@ -341,3 +341,38 @@ def test_pool_tune_keeps_results_and_caches():
         for x, r in zip((u, v, a), hist[5]):
             assert rel_l2(x, pw.to_full(r)) <= 1e-12
     pool.close()
+
+
+def test_pool_tune_with_field_in_mixed_mode():
+    """The pool's tuner on a class of mixed-mode simulations with a
+    wave-speed field (its candidates include the MFMA x-stage, variant 4):
+    the tuned batch stays within the mixed bar of the FP64 oracle."""
+    _cuda()
+    import torch
+    from oracle import pwave
+    from runners import oracle_bc
+    from paper_1911_08158_amd import Pool
+    cfgs = [W.C1.with_(nelem=(12, 10, 9), tau=0.01, steps=6),
+            W.C1.with_(nelem=(11, 9, 10), p=3, q=4, tau=0.01, steps=6)]
+    pool = Pool(128 << 20, max_slots=4)
+    runs = []
+    for c in cfgs:
+        base = pwave.PWave(c.nelem, c.p, c.q, c.tau, bc=oracle_bc(c))
+        xs = [base.quad_points(d) for d in range(3)]
+        c2 = W.wave_speed_field(*xs)
+        pw = pwave.PWave(c.nelem, c.p, c.q, c.tau, bc=oracle_bc(c), coef=c2, c2ref=1.5)
+        u0 = pw.project(W.initial_values(c, *xs))
+        _, hist = pw.run(u0, None, c.steps, history=True)
+        s = pool.admit(c, precision="mixed_fp32", u0=torch.from_numpy(pw.to_full(u0)).cuda())
+        s.set_coefficient(torch.from_numpy(c2).cuda(), 1.5)
+        s.factor()
+        pool.activate(s)
+        runs.append((s, pw, hist))
+    n, shapes = pool.tune()
+    print(f"tuned shapes {shapes[shapes >= 0].tolist()}", flush=True)
+    pool.step(cfgs[0].steps)
+    for s, pw, hist in runs:
+        u = s.get_state()[0].cpu().numpy()
+        e = rel_l2(u, pw.to_full(hist[-1][0]))
+        assert 0 < e <= 1e-6, e
+    pool.close()
