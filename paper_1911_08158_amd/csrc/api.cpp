@@ -2042,8 +2042,8 @@ ads_status ads_pool_activate(ads_pool* P, int32_t slot) {
 ads_status ads_pool_step(ads_pool* P, int32_t nsteps) {
   if (!P || nsteps < 0) return fail(ADS_EINVAL, "bad argument");
   ads_status st;
-  // the active simulations' predictor fields (a state set since the last
-  // step), then their u is formed from (w, v, a) when read
+  // the active simulations' stepping fields w, b (a state set since the
+  // last step), then their u and u' are formed from (w, b, a) when read
   for (int i = 0; i < P->max_slots; ++i) {
     ads_sim* s = P->slots[i].sim;
     if (!s || !P->slots[i].active) continue;

@@ -134,7 +134,7 @@ def test_deterministic_bitwise():
 @pytest.mark.parametrize("problem", ["pwave", "elastic"])
 def test_checkpoint_resume_bitwise(problem):
     """50 = 25 + checkpoint + destroy + create + restore + factor + 25: the
-    stepping state itself (P-wave (w, u', u''), elasticity (U^n, U^{n-1}))
+    stepping state itself (P-wave (w, b, u''), elasticity (U^n, U^{n-1}))
     resumes bitwise."""
     _cuda()
     base = W.C1 if problem == "pwave" else W.C4
