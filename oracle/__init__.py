@@ -22,6 +22,8 @@ for hyperbolic wave propagation problems", arXiv:1911.08158):
                  reading, see the module header).
 * ``elastic``    alternating-triangular elasticity step (Section 5,
                  eq. decom, eq. pre, eq. corr, eq. spill, eq. gen).
+* ``pwave2d``, ``elastic2d``  the same two problems in two dimensions, the
+                 dimension of the paper's exposition (Sections 2 and 5).
 * ``quadref``    element-by-element quadrature of the bilinear forms, used
                  only to pin the Kronecker routes.
 
