@@ -89,14 +89,17 @@ typedef enum { ADS_BC_DIRICHLET0 = 0, ADS_BC_NATURAL = 1 } ads_bc;
  * taken by the Kronecker-form right-hand sides only: no wave-speed field,
  * no quadrature variant, not in pools), time step tau, density rho and Lame constants lambda, mu
  * (elasticity only; the P-wave has unit wave speed).  nelem[2] = 0 selects
- * the two-dimensional P-wave on the unit square, the setting of the paper's
- * exposition (Section 2: K = K_x (x) M_y + M_x (x) K_y, split left-hand side
- * (M_x + eta K_x) (x) (M_y + eta K_y)); its arrays have one z-layer
- * (n_z = 1) and the z-index of Gauss-point data runs over q points whose
- * weights sum to 1. */
+ * the two-dimensional problem on the unit square, the setting of the paper's
+ * exposition: the P-wave of Section 2 (K = K_x (x) M_y + M_x (x) K_y, split
+ * left-hand side (M_x + eta K_x) (x) (M_y + eta K_y)), and elasticity in
+ * plane strain, Section 5's 2D blocks (components x then y in the
+ * predictor, y then x in the corrector), with the antiplane displacement
+ * u_z as a third, decoupled component (it stays zero when it starts at
+ * zero without load); the arrays have one z-layer (n_z = 1) and the
+ * z-index of Gauss-point data runs over q points whose weights sum to 1. */
 typedef struct {
   int32_t problem;     /* ads_problem   */
-  int32_t nelem[3];    /* >= 1 each; nelem[2] = 0: two-dimensional P-wave */
+  int32_t nelem[3];    /* >= 1 each; nelem[2] = 0: two-dimensional */
   int32_t p;           /* 1 to 5 (the quadrature right-hand side, and with
                           it a wave-speed field, needs 2 or 3)          */
   int32_t nquad;       /* 0 (= p+1) or p+1 .. p+3 (above p+1: Kronecker

@@ -217,8 +217,10 @@ namespace {
 
 // Free coefficients of direction d: all n = nelem + p of them with natural
 // conditions, the n - 2 interior ones with zero Dirichlet conditions.
-// nelem[2] = 0: a two-dimensional P-wave problem (x, y); the z-direction is
-// one constant function (one free coefficient).
+// nelem[2] = 0: a two-dimensional problem (x, y); the z-direction is one
+// constant function (one free coefficient).  Elasticity there is plane
+// strain in (u_x, u_y), its blocks with z-derivatives vanishing, beside the
+// decoupled antiplane component u_z.
 bool flat_z(const ads_params& P) { return P.nelem[2] == 0; }
 int free_count(const ads_params& P, int d) {
   if (d == 2 && flat_z(P)) return 1;
@@ -239,9 +241,9 @@ bool valid_params(const ads_params* prm, std::string& why) {
     return false;
   }
   for (int d = 0; d < 3; ++d) {
-    if (d == 2 && prm->nelem[2] == 0 && prm->problem == ADS_PWAVE) continue;   // two-dimensional
+    if (d == 2 && prm->nelem[2] == 0) continue;   // two-dimensional
     if (prm->nelem[d] < 1 || prm->nelem[d] > 4096) {
-      why = "nelem must be in [1, 4096] (nelem[2] = 0: two-dimensional P-wave)";
+      why = "nelem must be in [1, 4096] (nelem[2] = 0: two-dimensional)";
       return false;
     }
   }

@@ -41,7 +41,7 @@ def _params(**kw):
                                  dict(problem="elastic", precision="mixed_bf16"),
                                  dict(nelem=(600, 4, 4)), dict(bc=2), dict(bc=-1),
                                  dict(nelem=(511, 4, 4), bc="natural"),
-                                 dict(problem="elastic", nelem=(4, 4, 0)), dict(nelem=(0, 4, 4))])
+                                 dict(problem="elastic", nelem=(4, 0, 4)), dict(nelem=(0, 4, 4))])
 def test_invalid_params_rejected(lib, bad):
     from paper_1911_08158_amd import binding
     with pytest.raises(binding.AdsError) as e:
@@ -65,6 +65,14 @@ def test_workspace_scales_linearly(lib):
     assert 6 * 8 * nf2 < b2 < 12 * 8 * nf2
     be = binding.workspace_bytes(_params(problem="elastic", nelem=(30, 30, 30)))
     assert be > 2.2 * b1   # elasticity: 20 FP64 fields (3 components of u, v, R, load, Y, Z; X, T) against 8
+
+
+def test_two_dimensional_elasticity_accepted(lib):
+    """nelem[2] = 0 is accepted for elasticity too (plane strain with the
+    antiplane component): 20 component fields of (E + p - 2)^2 coefficients."""
+    from paper_1911_08158_amd import binding
+    b2 = binding.workspace_bytes(_params(problem="elastic", nelem=(30, 20, 0)))
+    assert 20 * 8 * 30 * 20 < b2 < 20 * 8 * 30 * 20 + (4 << 20)   # 20 component fields
 
 
 def test_two_dimensional_layout(lib):

@@ -1,0 +1,107 @@
+"""Two-dimensional elasticity on the GPU (nelem[2] = 0: plane strain, the
+blocks of Section 5, beside the decoupled antiplane component) against the
+2D oracle from identical coefficients: U^n and U^{n-1} after every step
+within 1e-12 relative L2 (FP64), the antiplane component exactly zero, the
+device energy constant, and a pooled run bitwise the run alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+from runners import rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle(cfg, steps):
+    from oracle import elastic2d
+    el = elastic2d.Elastic2D(cfg.nelem[:2], cfg.p, cfg.q, cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu,
+                             bc="neumann" if cfg.bc == "natural" else "dirichlet")
+    rng = np.random.default_rng(cfg.seed + 5)
+    U0 = rng.uniform(-1.0, 1.0, size=(2,) + el.free_shape)
+    V0 = rng.uniform(-1.0, 1.0, size=(2,) + el.free_shape)
+    _, hist = el.run(U0, V0, nsteps=steps, history=True)
+    return el, U0, V0, hist
+
+
+def _full3(el, U2):
+    """[3, 1, ny, nx] full-layout field from the two in-plane components."""
+    f = el.to_full(U2)
+    out = np.zeros((3, 1) + f.shape[1:])
+    out[0, 0], out[1, 0] = f[0], f[1]
+    return out
+
+
+CASES = [
+    W.C4.with_(nelem=(9, 7, 0), p=2, q=3, tau=0.02, lam=0.8, mu=0.6, rho=1.3, steps=5),
+    W.C4.with_(nelem=(6, 8, 0), p=3, q=4, tau=0.02, lam=2.0, mu=0.5, steps=4, bc="natural"),
+    W.C4.with_(nelem=(40, 23, 0), p=2, q=3, tau=0.01, steps=3),    # several tiles, ragged
+]
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"{c.nelem[:2]}-p{c.p}-{c.bc}")
+def test_elastic2d_matches_oracle(cfg):
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Sim
+    el, U0, V0, hist = _oracle(cfg, cfg.steps)
+    u0 = torch.from_numpy(_full3(el, U0)).cuda()
+    v0 = torch.from_numpy(_full3(el, V0)).cuda()
+    sim = Sim(cfg, device="cuda", u0=u0, v0=v0)
+    sim.factor()
+    E = []
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, _ = (t.cpu().numpy() if t is not None else None for t in sim.get_state())
+        assert np.array_equal(u[2], np.zeros_like(u[2])) and np.array_equal(v[2], np.zeros_like(v[2]))
+        eu = rel_l2(u[:2, 0], el.to_full(hist[k][0]))
+        ev = rel_l2(v[:2, 0], el.to_full(hist[k][1]))
+        assert max(eu, ev) <= TOL, (k, eu, ev)
+        E.append(sim.energy())
+    E = np.array(E)
+    ref = el.energy(hist[-1][0], hist[-1][1])
+    print(f"2D elasticity {cfg.nelem[:2]} p={cfg.p} {cfg.bc}: energy {E[-1]:.12e} (oracle {ref:.12e})", flush=True)
+    assert np.all(np.abs(E / E[0] - 1) < 1e-12)
+    assert abs(E[-1] / ref - 1) < 1e-12
+    sim.close()
+
+
+def test_elastic2d_pool_bitwise_and_mixed():
+    """A 2D elasticity simulation in a pool (beside a 3D one) equals its run
+    alone bitwise; in mixed mode it stays within 1e-6 of the oracle."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool, Sim
+    cfg = CASES[0]
+    el, U0, V0, hist = _oracle(cfg, cfg.steps)
+    u0 = torch.from_numpy(_full3(el, U0)).cuda()
+    v0 = torch.from_numpy(_full3(el, V0)).cuda()
+    alone = Sim(cfg, device="cuda", u0=u0, v0=v0)
+    alone.factor()
+    alone.step(cfg.steps)
+    ref = [t.cpu().numpy() for t in alone.get_state() if t is not None]
+    alone.close()
+    pool = Pool(128 << 20, max_slots=4)
+    s = pool.admit(cfg, u0=u0, v0=v0)
+    s.factor()
+    other = pool.admit(W.C4.with_(nelem=(5, 6, 4), tau=0.02))
+    other.factor()
+    pool.activate(s)
+    pool.activate(other)
+    mixed = pool.admit(cfg, precision="mixed_fp32", u0=u0, v0=v0)
+    mixed.factor()
+    pool.activate(mixed)
+    pool.step(cfg.steps)
+    got = [t.cpu().numpy() for t in pool.retire(s, state=True) if t is not None]
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    um = pool.retire(mixed, state=True)[0].cpu().numpy()
+    e = rel_l2(um[:2, 0], el.to_full(hist[-1][0]))
+    assert 0 < e <= 1e-6, e
+    pool.close()

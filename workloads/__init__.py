@@ -52,7 +52,7 @@ class SimConfig:
     @property
     def n(self):
         """Basis functions per direction (open knots, maximal continuity);
-        nelem[2] = 0 is the two-dimensional P-wave (one z-layer)."""
+        nelem[2] = 0 is the two-dimensional problem (one z-layer)."""
         return tuple(1 if (d == 2 and e == 0) else e + self.p for d, e in enumerate(self.nelem))
 
     @property
