@@ -42,6 +42,8 @@ CASES = [
     W.C4.with_(nelem=(9, 7, 0), p=2, q=3, tau=0.02, lam=0.8, mu=0.6, rho=1.3, steps=5),
     W.C4.with_(nelem=(6, 8, 0), p=3, q=4, tau=0.02, lam=2.0, mu=0.5, steps=4, bc="natural"),
     W.C4.with_(nelem=(40, 23, 0), p=2, q=3, tau=0.01, steps=3),    # several tiles, ragged
+    W.C4.with_(nelem=(7, 5, 0), p=1, q=2, tau=0.02, steps=4, bc="natural"),
+    W.C4.with_(nelem=(5, 6, 0), p=4, q=5, tau=0.02, lam=1.5, steps=3),
 ]
 
 
