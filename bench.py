@@ -648,7 +648,7 @@ def main():
         "precision_note": "right-hand-side contractions on the VALU by the tuners' choice: the quadrature's "
                           "x-stage on FP32 MFMA (4x4x1 blocks, variant 4 with a wave-speed field) is built and "
                           "timed by the tuner, and loses (see quadrature_rhs.*.rhs_variant_ms: its chain of "
-                          "dependent MFMAs and lane permutes is latency-bound, 6.7 % MFMA busy); every contraction "
+                          "dependent MFMAs and lane permutes is latency-bound, 11 % MFMA busy); every contraction "
                           "of the path is a band of width 2p+1 (dense MFMA tiles 15-38 % useful; FP32 MFMA issues "
                           "at 2x the non-packed FP32 VALU, FP64 MFMA at 1x) and the kernels are bound by memory and "
                           "latency; BF16 operands cannot meet 1e-6 on this stiffness action (cancellation ~40) "

@@ -545,6 +545,28 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
 #pragma unroll 1
       for (int gz = 0; gz < Q; ++gz) {
         T* sbb = sb + buf * Gm::NCH * SBC;
+        // wave-speed field of this lane's x-element at the Gauss rows of its
+        // x-stage (lane mapping of the VALU or of the MFMA form), loaded
+        // here, before the y-stage, and used raw (no select or conversion
+        // before the x-stage, which would wait for the loads at once); rows
+        // outside the mesh load the first entry and are zeroed at use
+        double cqr[CF ? NRW : 1][Q];
+        bool cqok[CF ? NRW : 1];
+        if constexpr (CF) {
+          const int xr = MF ? mj : grp, xe = MF ? exm : ex;
+          const bool xv = MF ? exvm : exv;
+#pragma unroll
+          for (int i = 0; i < NRW; ++i) {
+            const int r = wv * WE * Q + 4 * i + xr;
+            const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
+            cqok[i] = xv && ey >= 0 && ey < Ey;
+            const long long o = (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
+                                    ((long long)Ex * Q) + (long long)xe * Q;
+            const gmem<double>* cp = C + (cqok[i] ? o : 0ll);
+#pragma unroll
+            for (int gx = 0; gx < Q; ++gx) cqr[i][gx] = cp[gx];
+          }
+        }
         // (Y) y-contraction of this wave's y-elements: value, y-derivative,
         // z-derivative per y Gauss row
         {
@@ -658,14 +680,9 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
           if constexpr (MF) {
             // rows 4i + mj of the three channels, column of x-element mb
             T* rm = sbb + xrowm0 + 2 * i * TXH;
-            const int r = wv * WE * Q + 4 * i + mj;
-            const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
-            const bool ok = exvm && ey >= 0 && ey < Ey;
-            const gmem<double>* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
-                                       ((long long)Ex * Q) + (long long)exm * Q;
             float cq[4];
 #pragma unroll
-            for (int gx = 0; gx < 4; ++gx) cq[gx] = (gx < Q && ok) ? (float)cp[gx] : 0.f;
+            for (int gx = 0; gx < 4; ++gx) cq[gx] = (gx < Q && cqok[i]) ? (float)cqr[i][gx < Q ? gx : 0] : 0.f;
             // forward: x-derivative of channel 0 (on differences: the
             // derivative tables annihilate constants), values of channels
             // 1 and 2, at the element's Gauss points (register = point)
@@ -713,13 +730,8 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
           // wave-speed field: the lane's q points of this Gauss row (0 outside the mesh)
           T cq[Q];
           if constexpr (CF) {
-            const int r = wv * WE * Q + 4 * i + grp;
-            const int ey = Y0 - p + r / Q, gy = r - (r / Q) * Q;
-            const bool ok = exv && ey >= 0 && ey < Ey;
-            const gmem<double>* cp = C + (((long long)ez * Q + gz) * ((long long)Ey * Q) + (long long)ey * Q + gy) *
-                                       ((long long)Ex * Q) + (long long)ex * Q;
 #pragma unroll
-            for (int gx = 0; gx < Q; ++gx) cq[gx] = ok ? (T)cp[gx] : T(0);
+            for (int gx = 0; gx < Q; ++gx) cq[gx] = cqok[i] ? (T)cqr[i][gx] : T(0);
           }
           T c0[P], c1[P], c2[P];
 #pragma unroll
