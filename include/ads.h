@@ -227,7 +227,8 @@ ads_status ads_step(ads_sim* sim, int32_t nsteps);
  * field), 4 the quadrature with its x-contractions on the matrix cores
  * (FP32 MFMA; offered in the mixed modes with a wave-speed field only,
  * elsewhere it runs as 0).  Elasticity: 0 is the quadrature (FP64), 3 the Kronecker form
- * (the default).  Then, per direction, it times the tile widths 4, 8 and 16
+ * (the default); for elasticity it then times the two forms of the
+ * couplings (ads_set_coupling).  Then, per direction, it times the tile widths 4, 8 and 16
  * lines per wave of the step's sweeps (on copies of their jobs that solve in
  * place with a plain store: only the step's temporaries change, the state
  * does not) and keeps the fastest.  The choices are cached per (problem,
@@ -249,6 +250,23 @@ ads_status ads_tune(ads_sim* sim, int32_t* chosen, double* host_ms, int32_t cap)
  * differently).  ADS_EINVAL for a variant the problem or degree lacks or a
  * width that does not fit the LDS, ADS_ESTATE for a pooled simulation. */
 ads_status ads_set_launch_shape(ads_sim* sim, int32_t rhs_var, int32_t rhs_tz, const int32_t* sweep_w);
+
+/* Where the elasticity couplings of the alternating-triangular stages are
+ * applied (eq. pre: -tau^2/2 Upsilon_ij Y_j, j < i; eq. corr: rho M Y_i -
+ * tau^2/2 Upsilon_ij Z_j, j > i; five per step).  fused = 0 (the default):
+ * by separate launches that write the coupled right-hand side to memory.
+ * fused = 1: in the input stage of the in-plane (x, y) sweep of the solve
+ * that consumes them, where a z-plane of at most 4,608 unknowns with its
+ * work space fits the LDS (elsewhere by separate launches).  One workgroup
+ * per z-plane then does the coupling's work, so the form pays only where
+ * z-planes are many and small; ads_tune times both and keeps the faster.
+ * The two forms round differently (z-band first, against x-band first).
+ * ADS_EINVAL for a
+ * P-wave simulation or fused not 0 or 1, ADS_ESTATE for a pooled
+ * simulation.  ads_coupling_fused returns 1 when the step applies them in
+ * the in-plane sweeps, else 0. */
+ads_status ads_set_coupling(ads_sim* sim, int32_t fused);
+int32_t ads_coupling_fused(const ads_sim* sim);
 
 /* Copy the state out (full layout; asynchronous on the sim's stream).
  * P-wave: u, u', u'' (any pointer may be NULL).  Elasticity: U^n into dev_u,

@@ -127,6 +127,8 @@ def load_library():
         "ads_check_finite": [c_void_p],
         "ads_tune": [c_void_p, POINTER(c_int32), c_void_p, c_int32],
         "ads_set_launch_shape": [c_void_p, c_int32, c_int32, c_void_p],
+        "ads_set_coupling": [c_void_p, c_int32],
+        "ads_coupling_fused": [c_void_p],
         "ads_pool_tune": [c_void_p, POINTER(c_int32), c_void_p, c_int32],
         "ads_profile": [c_void_p, c_int32],
         "ads_profile_read": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32), c_void_p, c_int32,
@@ -357,6 +359,16 @@ class Sim:
         if sweep_w is not None:
             w = (c_int32 * 3)(*[int(x) for x in sweep_w])
         _check(load_library().ads_set_launch_shape(self._h, int(rhs_var), int(rhs_tz), w))
+
+    def set_coupling(self, fused=True):
+        """Elasticity couplings in the in-plane sweeps (True, where the
+        plane fits) or by separate launches (False, the default)."""
+        _check(load_library().ads_set_coupling(self._h, 1 if fused else 0))
+
+    @property
+    def coupling_fused(self):
+        """True when the step applies the couplings in the in-plane sweeps."""
+        return bool(load_library().ads_coupling_fused(self._h))
 
     def tune(self):
         """Autotune the right-hand-side tiling on this mesh; returns the

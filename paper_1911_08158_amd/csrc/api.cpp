@@ -109,6 +109,7 @@ struct Launch {
   int w = 4;      // sweeps: lines per wave tile
   int coef = 0;   // P-wave right-hand side: jobs carry a wave-speed field
   size_t lds = 0; // in-plane sweeps: dynamic LDS bytes
+  bool coupled = false;  // in-plane sweeps: jobs carry coupling terms
 };
 
 struct DevFactor {
@@ -193,6 +194,10 @@ struct ads_sim {
   int namp = 0;
   int tz = 0;           // right-hand side: owned z-layers per tile (0: chosen from the occupancy)
   int sweep_w[3] = {0, 0, 0};   // sweeps per direction: lines per wave tile (0: default)
+  // elasticity couplings: true = applied in the input stage of the in-plane
+  // sweep that consumes them where the plane fits, false = separate launches
+  // (the default; ads_tune times both)
+  bool couple_fused = false;
   int ncu = 0;          // compute units of the device (tiling of the right-hand side)
   // P-wave right-hand side: 3 = the Kronecker form (jobs with a wave-speed
   // field take the quadrature kernel's variant 0); ads_tune may choose another
@@ -393,12 +398,21 @@ SweepJob sweep_job(const ads_sim* s, int dir, const DevFactor& f, const double* 
 
 // Three sweeps x (in -> X), y (X -> tmp), z (tmp -> out/epilogue) with one
 // factor per direction; when a z-plane fits in LDS the x- and y-sweeps are
-// one in-plane launch (in -> tmp).
+// one in-plane launch (in -> tmp).  With coupling terms (the caller has
+// checked plane_couple_fits) the in-plane launch adds them to `in` (which
+// may then be null).
 bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], const double* in, double* tmp,
-                   double* out, double scale, SweepJob zlast, std::string& err) {
-  const bool fused = plane_fits(s->nf[0], s->nf[1], s->p);
+                   double* out, double scale, SweepJob zlast, std::string& err, const KronTerm* terms = nullptr,
+                   int nterm = 0) {
+  const bool fused = nterm > 0 || plane_fits(s->nf[0], s->nf[1], s->p);
+  if (nterm > kPlaneMaxTerms || (nterm > 0 && !plane_couple_fits(s->nf[0], s->nf[1], s->p))) {
+    err = "coupling terms do not fit the in-plane sweep";
+    return false;
+  }
   if (fused) {
     PlaneJob jp{};
+    jp.nterm = nterm;
+    for (int t = 0; t < nterm; ++t) jp.term[t] = terms[t];
     jp.in = in;
     jp.out = tmp;
     jp.fx = Factor1D{f[0].L, f[0].U, f[0].rd, f[0].m};
@@ -413,7 +427,8 @@ bool add_ads_solve(ads_sim* s, std::vector<Launch>& L, const DevFactor f[3], con
     const LaunchHdr* d = s->arena.add(std::vector<PlaneJob>{jp}, err);
     if (!d) return false;
     L.push_back(Launch{Launch::PLANE, d, 1, jp.ntiles, max_m(s), s->p, -1, 0, 0, as_bytes(jp)});
-    L.back().lds = plane_lds_bytes(jp.nx, jp.ny, jp.p);
+    L.back().lds = plane_lds_bytes(jp.nx, jp.ny, jp.p, nterm > 0);
+    L.back().coupled = nterm > 0;
   }
   SweepJob jx = sweep_job(s, 0, f[0], in, s->X, scale);
   SweepJob jy = sweep_job(s, 1, f[1], s->X, tmp, 1.0);
@@ -642,6 +657,15 @@ bool push_kron(ads_sim* s, std::vector<Launch>& L, const KronJob& K, std::string
   return true;
 }
 
+// The coupling of a stage goes into the in-plane sweep of the solve that
+// consumes it when the plane takes it; its launch slot then stays, empty
+// (no tiles, nothing launched), so that every elasticity step has the same
+// launch sequence (the pool's stages).
+bool couple_in_plane(const ads_sim* s) { return s->couple_fused && plane_couple_fits(s->nf[0], s->nf[1], s->p); }
+void push_empty_kron(ads_sim* s, std::vector<Launch>& L) {
+  L.push_back(Launch{Launch::KRON, nullptr, 0, 0, 0, s->p, -1, 0, 0, {}});
+}
+
 // Alternating-triangular solve Z = D^{-1} R (three-level form of eq. pre /
 // eq. corr with the split diagonal blocks of eq. spill); with `update` the
 // last sweep of every component also performs U^{n+1} = 2U^n - U^{n-1} + Z.
@@ -651,18 +675,24 @@ bool add_at_solve(ads_sim* s, std::vector<Launch>& L, bool update, bool count, s
   auto facs = [&](int i, DevFactor out[3]) {
     for (int d = 0; d < 3; ++d) out[d] = (d == i) ? s->fS2[d] : s->fS[d];
   };
+  const bool in_plane = couple_in_plane(s);
   // stage 1 (block lower): components x, y, z
   for (int i = 0; i < 3; ++i) {
     const double* rhs = s->R + i * nf;
+    KronJob K = kron_base(s, s->T, s->R + i * nf, 1.0);
     if (i > 0) {
-      KronJob K = kron_base(s, s->T, s->R + i * nf, 1.0);
       for (int jj = 0; jj < i; ++jj) kron_add_upsilon(s, K, i, jj, s->Y + jj * nf, -h);
-      if (!push_kron(s, L, K, err)) return false;
-      rhs = s->T;
+      if (in_plane) {
+        push_empty_kron(s, L);
+      } else {
+        if (!push_kron(s, L, K, err)) return false;
+        rhs = s->T;
+      }
     }
     DevFactor f[3];
     facs(i, f);
-    if (!add_ads_solve(s, L, f, rhs, s->Z + i * nf /*tmp*/, s->Y + i * nf, 1.0 / rho, plain_epi(), err))
+    const int nt = (i > 0 && in_plane) ? K.nterm : 0;
+    if (!add_ads_solve(s, L, f, rhs, s->Z + i * nf /*tmp*/, s->Y + i * nf, 1.0 / rho, plain_epi(), err, K.term, nt))
       return false;
   }
   // stage 2 (block upper): components z, y, x
@@ -670,7 +700,8 @@ bool add_at_solve(ads_sim* s, std::vector<Launch>& L, bool update, bool count, s
     KronJob K = kron_base(s, s->T, nullptr, 0.0);
     kron_add_mass(s, K, s->Y + i * nf, rho);
     for (int jj = i + 1; jj < 3; ++jj) kron_add_upsilon(s, K, i, jj, s->Z + jj * nf, -h);
-    if (!push_kron(s, L, K, err)) return false;
+    if (in_plane) push_empty_kron(s, L);
+    else if (!push_kron(s, L, K, err)) return false;
     DevFactor f[3];
     facs(i, f);
     SweepJob z{};
@@ -683,7 +714,12 @@ bool add_at_solve(ads_sim* s, std::vector<Launch>& L, bool update, bool count, s
     }
     if (count && i == 0) z.counter = s->counter;
     // tmp for the y-sweep: R_i is no longer needed in stage 2
-    if (!add_ads_solve(s, L, f, s->T, s->R + i * nf, s->Z + i * nf, 1.0 / rho, z, err)) return false;
+    if (in_plane) {
+      if (!add_ads_solve(s, L, f, nullptr, s->R + i * nf, s->Z + i * nf, 1.0 / rho, z, err, K.term, K.nterm))
+        return false;
+    } else if (!add_ads_solve(s, L, f, s->T, s->R + i * nf, s->Z + i * nf, 1.0 / rho, z, err)) {
+      return false;
+    }
   }
   return true;
 }
@@ -710,7 +746,7 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
         e = launch_kron(l.d_hdr, grid_of(l, grid_cap), l.p, s->stream);
         break;
       case Launch::PLANE:
-        e = launch_planes(l.d_hdr, grid_of(l, grid_cap), l.lds, l.p, s->stream);
+        e = launch_planes(l.d_hdr, grid_of(l, grid_cap), l.lds, l.p, l.coupled, s->stream);
         break;
     }
     if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -719,7 +755,6 @@ ads_status enqueue(ads_sim* s, const std::vector<Launch>& L, int grid_cap = 0, h
   return ADS_OK;
 }
 
-// 0 = right-hand side, 1..3 = x/y/z sweep, 4 = coupling apply
 // 0 right-hand side, 1/2/3 x/y/z sweep, 4 coupling, 6 in-plane (x and y) sweeps
 int launch_kind_code(const Launch& l) {
   if (l.kind == Launch::RHS_P || l.kind == Launch::RHS_E) return 0;
@@ -1292,6 +1327,17 @@ ads_status ads_set_launch_shape(ads_sim* s, int32_t rhs_var, int32_t rhs_tz, con
   return build_launches(s);
 }
 
+ads_status ads_set_coupling(ads_sim* s, int32_t fused) {
+  if (!s) return fail(ADS_EINVAL, "NULL sim");
+  if (!s->elastic) return fail(ADS_EINVAL, "the couplings are elasticity's");
+  if (fused != 0 && fused != 1) return fail(ADS_EINVAL, "fused must be 0 or 1");
+  if (s->pooled) return fail(ADS_ESTATE, "launch shapes of a pooled simulation are the pool's");
+  s->couple_fused = fused != 0;
+  return build_launches(s);
+}
+
+int32_t ads_coupling_fused(const ads_sim* s) { return (s && s->elastic && couple_in_plane(s)) ? 1 : 0; }
+
 ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
   if (!s || !chosen) return fail(ADS_EINVAL, "NULL argument");
   if (!s->factored) return fail(ADS_ESTATE, "ads_tune before ads_factor");
@@ -1368,6 +1414,27 @@ ads_status ads_tune(ads_sim* s, int32_t* chosen, double* host_ms, int32_t cap) {
     remember(key, best);
   }
   s->rhs_var = best;
+  // elasticity: the couplings by separate launches or in the in-plane
+  // sweeps, timed over the step's coupling and in-plane launches (they
+  // write only the step's temporaries)
+  if (s->elastic && plane_couple_fits(s->nf[0], s->nf[1], s->p)) {
+    const std::string ckey = key + "/v" + std::to_string(best) + "/C";
+    int fused = 0;
+    if (!cached(ckey, &fused)) {
+      double ms[2] = {0.0, 0.0};
+      for (int f = 0; f < 2; ++f) {
+        s->couple_fused = f != 0;
+        if ((st = build_launches(s)) != ADS_OK) return st;
+        std::vector<Launch> cl;
+        for (const Launch& l : s->step_l)
+          if (l.kind == Launch::KRON || l.kind == Launch::PLANE) cl.push_back(l);
+        if ((st = timed([&] { return enqueue(s, cl); }, &ms[f])) != ADS_OK) return st;
+      }
+      fused = ms[1] < ms[0] ? 1 : 0;
+      remember(ckey, fused);
+    }
+    s->couple_fused = fused != 0;
+  }
   // sweep tile widths, per direction: the step's sweeps of that direction,
   // timed on copies of their jobs that solve in place with a plain store (no
   // time update, no step counter), placed after the job arena's tables, so
@@ -1592,6 +1659,7 @@ struct PoolLaunch {
   int grid;
   int w;            // sweeps: lines per wave tile (chosen per batch)
   size_t lds;       // in-plane sweeps: dynamic LDS bytes (largest plane of the batch)
+  bool coupled;     // in-plane sweeps: some job carries coupling terms
   size_t off, cap;  // table offset/capacity (bytes) in the pool's table region: one table
                     // (header + max_slots jobs) per branch, `boff` bytes apart
   size_t job_size;
@@ -1675,7 +1743,7 @@ void pool_build_seq(ads_pool* P, int ncu) {
   auto add = [&](Launch::Kind k, int p, int mixed, int var, int coef, int stage, int grid, size_t js) {
     const size_t one = sizeof(LaunchHdr) + (size_t)P->max_slots * js;
     const size_t boff = (one + kAlign - 1) / kAlign * kAlign;
-    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, 0, off, one, js, boff};
+    PoolLaunch L{k, p, mixed, var, coef, stage, grid, 4, 0, false, off, one, js, boff};
     off += kPoolBranches * boff;
     P->seq.push_back(L);
   };
@@ -1759,6 +1827,10 @@ ads_status pool_rebuild(ads_pool* P) {
       if ((int)st.size() <= L.stage) continue;
       const Launch& l = st[L.stage];
       if (l.kind != L.kind) continue;
+      if (l.kind == Launch::KRON && l.total_tiles == 0) {   // coupling applied in the in-plane sweep
+        taken[i]++;
+        continue;
+      }
       if (L.stage == 0 && (l.p != L.p || l.mixed != L.mixed || l.var != L.var ||
                            (l.kind == Launch::RHS_P && l.coef != L.coef)))
         continue;
@@ -1787,13 +1859,15 @@ ads_status pool_rebuild(ads_pool* P) {
     if (L.kind == Launch::PLANE) {
       L.lds = 0;
       L.p = 1;
+      L.coupled = false;
       for (int b = 0; b < nb; ++b)
         for (const auto& j : sel[b]) {
           const PlaneJob* r = (const PlaneJob*)j.data();
-          L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p));
+          L.lds = std::max(L.lds, plane_lds_bytes(r->nx, r->ny, r->p, r->nterm > 0));
           L.p = std::max(L.p, r->p);
+          L.coupled = L.coupled || r->nterm > 0;
         }
-      L.grid = plane_blocks_per_cu(L.lds, L.p) * P->ncu;
+      L.grid = plane_blocks_per_cu(L.lds, L.p, L.coupled) * P->ncu;
     }
     if (L.kind == Launch::SWEEP) {
       long long lines = 0;
@@ -1808,7 +1882,7 @@ ads_status pool_rebuild(ads_pool* P) {
       L.grid = sweep_blocks_per_cu(L.w, kPoolMaxM, L.p) * P->ncu;
     }
     const int shape = L.kind == Launch::SWEEP ? L.w * 8 + L.p
-                      : L.kind == Launch::PLANE ? (int)L.lds * 8 + L.p
+                      : L.kind == Launch::PLANE ? ((int)L.lds * 8 + L.p) * 2 + (L.coupled ? 1 : 0)
                       : L.kind == Launch::KRON ? L.p : 1 + L.var;
     for (int b = 0; b < nb; ++b) {
       std::vector<std::vector<char>>& sb = sel[b];
@@ -1912,7 +1986,7 @@ ads_status pool_enqueue(ads_pool* P, int b, hipStream_t s, hipEvent_t* evs = nul
         case Launch::RHS_E: e = launch_rhs_elastic_band(L.p, L.mixed, h, L.grid, s); break;
         case Launch::SWEEP: e = launch_sweeps(h, L.grid, L.w, kPoolMaxM, L.p, s); break;
         case Launch::KRON: e = launch_kron(h, L.grid, L.p, s); break;
-        case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, L.p, s); break;
+        case Launch::PLANE: e = launch_planes(h, L.grid, L.lds, L.p, L.coupled, s); break;
       }
       if (e != hipSuccess) return fail(ADS_EDEVICE, std::string("pool launch: ") + hipGetErrorString(e));
     }

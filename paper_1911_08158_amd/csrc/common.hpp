@@ -98,8 +98,21 @@ struct SweepJob {
   unsigned long long* counter;  // incremented once by the job (end of a step)
 };
 
+// One tensor-product term coef * (T_x (x) T_y (x) T_z) src of an elasticity
+// coupling.
+struct KronTerm {
+  const double* src;
+  const double* T[3];     // banded [m][2p+1], band[i*(2p+1) + (j-i+p)]
+  double coef;
+};
+constexpr int kPlaneMaxTerms = 5;   // PlaneJob::term
+
 // The x- then the y-sweep of every z-plane of a field, the plane held in
-// LDS (the in-plane pair of a direction-split solve).
+// LDS (the in-plane pair of a direction-split solve).  With nterm > 0 the
+// input of plane z is  in + sum_t coef_t (T^t_x (x) T^t_y (x) T^t_z) src_t
+// at that plane (in may then be null: no base), formed in LDS before the
+// solve (the coupling of an alternating-triangular stage fused into the
+// solve that consumes it).
 struct PlaneJob {
   const double* in;
   double* out;
@@ -109,6 +122,8 @@ struct PlaneJob {
   double scale;     // the input is multiplied by this before the solve
   int tile0;        // first global tile (plane) index of this job
   int ntiles;       // = nz
+  int nterm;
+  KronTerm term[kPlaneMaxTerms];
 };
 
 // Right-hand side by sum-factorized Gauss quadrature on one field
@@ -142,11 +157,6 @@ struct RhsJob {
 
 // Apply of a sum of tensor products of 1D banded matrices (elasticity
 // couplings):  out = alpha*base + sum_t coef_t * (T^t_x (x) T^t_y (x) T^t_z) src_t
-struct KronTerm {
-  const double* src;
-  const double* T[3];     // banded [m][2p+1], band[i*(2p+1) + (j-i+p)]
-  double coef;
-};
 struct KronJob {
   double* out;
   const double* base;

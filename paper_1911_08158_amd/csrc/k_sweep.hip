@@ -372,6 +372,10 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
 // adjacent) are free of bank conflicts.
 
 constexpr int kPT = 256;   // threads per plane workgroup
+// coupled input (plane_couple): plane positions per thread, and the
+// largest plane it takes
+constexpr int kCoupleNC = 18;
+constexpr int kCoupleMaxN = kCoupleNC * kPT;
 
 __device__ __forceinline__ int find_job_plane(const PlaneJob* jobs, int njobs, int tile) {
   int lo = 0, hi = njobs - 1;
@@ -545,6 +549,15 @@ size_t plane_lds_bytes(int nx, int ny, int p) {
   return ((size_t)ny * (nx + 1) + (size_t)(2 * p + 1) * (nx + ny)) * sizeof(double);
 }
 bool plane_fits(int nx, int ny, int p) { return plane_lds_bytes(nx, ny, p) <= (size_t)160 * 1024; }
+// With coupling terms: the work space of plane_couple after the factor rows.
+size_t plane_lds_bytes(int nx, int ny, int p, bool coupled) {
+  size_t b = plane_lds_bytes(nx, ny, p);
+  if (coupled) b += (2 * (size_t)nx * ny + 2 * (size_t)(2 * p + 1) * (nx + ny)) * sizeof(double);
+  return b;
+}
+bool plane_couple_fits(int nx, int ny, int p) {
+  return (long long)nx * ny <= kCoupleMaxN && plane_lds_bytes(nx, ny, p, true) <= (size_t)160 * 1024;
+}
 
 // x-lines of a plane: forward pass from global memory, backward in LDS
 template <int P>
@@ -585,7 +598,200 @@ __device__ __forceinline__ void plane_y_p(int p, double* col, int PX, gmem<doubl
   else plane_y<3>(col, PX, dst, nx, ny, fyl);
 }
 
+// Coupled input of plane z (PlaneJob with nterm > 0), written to the plane
+// buffer pl as scale * (in + sum_t coef_t (T^t_x (x) T^t_y (x) T^t_z) src_t).
+// Sum factorization over the whole plane, z first: per term the 2p+1 source
+// planes that reach z are combined with row z of T_z into A (terms with the
+// source and z-band of the term before them reuse its A), the x-band takes
+// A to B, and the y-band of B is accumulated into pl (which holds the base
+// input from the first term on).  A thread owns the positions tid + i kPT
+// of the plane and takes them in groups of G, the loads of a group in
+// flight together.  Work space wk (after the factor rows): A [n], B [n],
+// the band rows of two terms [2][(nx + ny)(2p+1)] (double-buffered, so that
+// staging the next term's rows needs no barrier of its own).  Two barriers
+// per term.
+template <int P>
+__device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
+  constexpr int B = 2 * P + 1;
+  constexpr int G = P <= 2 ? 6 : (P == 3 ? 4 : 3);   // positions per group (global loads)
+  constexpr int GL = 3;               // ... in the LDS passes
+  const int nx = J.nx, ny = J.ny, nz = J.nz, n = nx * ny, PX = nx + 1;
+  const int tid = threadIdx.x;
+  // (y, x) of position k + kPT from those of k
+  const int dy = kPT / nx, dx = kPT - dy * nx;
+  auto next = [&](int& y, int& x) {
+    y += dy;
+    x += dx;
+    if (x >= nx) {
+      x -= nx;
+      ++y;
+    }
+  };
+  const int ty0 = tid / nx, tx0 = tid - ty0 * nx;
+  double* A = wk;
+  double* Bx = A + n;
+  double* TB = Bx + n;
+  const int tbs = (nx + ny) * B;
+  for (int t = 0; t < J.nterm; ++t) {
+    const KronTerm& T = J.term[t];
+    double* tb = TB + (t & 1) * tbs;
+    {
+      const gmem<double>* tx = gview(T.T[0]);
+      const gmem<double>* ty = gview(T.T[1]);
+      for (int k0 = 0; k0 < tbs; k0 += 4 * kPT) {
+        double v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = min(k0 + tid + r * kPT, tbs - 1);
+          v[r] = k < nx * B ? tx[k] : ty[k - nx * B];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (k0 + tid + r * kPT < tbs) tb[k0 + tid + r * kPT] = v[r];
+      }
+    }
+    if (t == 0 || T.src != J.term[t - 1].src || T.T[2] != J.term[t - 1].T[2]) {
+      // A = sum_zs T_z[z][zs] src(zs): row z of the z-band (wave-uniform:
+      // scalar loads); planes outside the field read a plane of it with
+      // weight zero, and positions past the plane its last position, so
+      // that no load waits behind a branch.  The first term also moves the
+      // base input into pl.
+      const cmem<double>* tz = cview(T.T[2]) + (long long)z * B;
+      const gmem<double>* src = gview(T.src);
+      const gmem<double>* in = (t == 0 && J.in != nullptr) ? gview(J.in) + (long long)z * n : nullptr;
+      double w[B];
+      long long zo[B];
+#pragma unroll
+      for (int kk = 0; kk < B; ++kk) {
+        const int zs = z + kk - P;
+        const bool ok = zs >= 0 && zs < nz;
+        w[kk] = ok ? tz[kk] : 0.0;
+        zo[kk] = (long long)(ok ? zs : z) * n;
+      }
+      int y = ty0, x = tx0;
+#pragma unroll 1
+      for (int i0 = 0; i0 < kCoupleNC; i0 += G) {
+        const int kb = tid + i0 * kPT;
+        if (kb >= n) break;
+        double a[G], b[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          a[j] = 0.0;
+          b[j] = in != nullptr ? in[min(kb + j * kPT, n - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk) {
+          const gmem<double>* sp = src + zo[kk];
+#pragma unroll
+          for (int j = 0; j < G; ++j) a[j] = fma(w[kk], sp[min(kb + j * kPT, n - 1)], a[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          if (kb + j * kPT < n) {
+            A[kb + j * kPT] = a[j];
+            if (t == 0) pl[y * PX + x] = b[j];
+          }
+          next(y, x);
+        }
+      }
+    }
+    __syncthreads();
+    // B = x-band of A (columns outside the line read an edge value with
+    // weight zero)
+    {
+      int y = ty0, x = tx0;
+#pragma unroll 1
+      for (int i0 = 0; i0 < kCoupleNC; i0 += GL) {
+        const int kb = tid + i0 * kPT;
+        if (kb >= n) break;
+#pragma unroll
+        for (int j = 0; j < GL; ++j) {
+          const int k = kb + j * kPT;
+          if (k < n) {
+            const double* tr = tb + x * B;
+            const double* ar = A + y * nx;
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+              const int xs = x + c - P;
+              v = fma((xs >= 0 && xs < nx) ? tr[c] : 0.0, ar[min(max(xs, 0), nx - 1)], v);
+            }
+            Bx[k] = v;
+          }
+          next(y, x);
+        }
+      }
+    }
+    __syncthreads();
+    // pl += coef * y-band of B
+    {
+      const double cf = T.coef;
+      int y = ty0, x = tx0;
+#pragma unroll 1
+      for (int i0 = 0; i0 < kCoupleNC; i0 += GL) {
+        const int kb = tid + i0 * kPT;
+        if (kb >= n) break;
+#pragma unroll
+        for (int j = 0; j < GL; ++j) {
+          const int k = kb + j * kPT;
+          if (k < n) {
+            const double* tr = tb + (nx + y) * B;
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+              const int ys = y + c - P;
+              v = fma((ys >= 0 && ys < ny) ? tr[c] : 0.0, Bx[min(max(ys, 0), ny - 1) * nx + x], v);
+            }
+            double* o = pl + y * PX + x;
+            *o = fma(cf, v, *o);
+          }
+          next(y, x);
+        }
+      }
+    }
+  }
+  // the scale of the solve's input
+  const double scale = J.scale;
+  {
+    int y = ty0, x = tx0;
+    for (int k = tid; k < n; k += kPT) {
+      pl[y * PX + x] *= scale;
+      next(y, x);
+    }
+  }
+}
+
 template <bool HI>
+__device__ __forceinline__ void plane_couple_p(const PlaneJob& J, int z, double* pl, double* wk) {
+  if constexpr (HI) {
+    if (J.p == 5) return plane_couple<5>(J, z, pl, wk);
+    if (J.p == 4) return plane_couple<4>(J, z, pl, wk);
+  }
+  if (J.p == 1) plane_couple<1>(J, z, pl, wk);
+  else if (J.p == 2) plane_couple<2>(J, z, pl, wk);
+  else plane_couple<3>(J, z, pl, wk);
+}
+
+// x-lines of a plane already in LDS (the coupled input): both passes in LDS
+template <int P>
+__device__ __forceinline__ void plane_x_lds(double* col, int nx, const double* fxl) {
+  fwd_st<P>(col, 1, nx, fxl);
+  bwd_st<P, false>(col, 1, nullptr, 0, nx, fxl);
+}
+template <bool HI>
+__device__ __forceinline__ void plane_x_lds_p(int p, double* col, int nx, const double* fxl) {
+  if constexpr (HI) {
+    if (p == 5) return plane_x_lds<5>(col, nx, fxl);
+    if (p == 4) return plane_x_lds<4>(col, nx, fxl);
+  }
+  if (p == 1) plane_x_lds<1>(col, nx, fxl);
+  else if (p == 2) plane_x_lds<2>(col, nx, fxl);
+  else plane_x_lds<3>(col, nx, fxl);
+}
+
+// CPL: the launch holds jobs with coupling terms (a separate instantiation,
+// so that the plain in-plane sweeps keep their registers).
+template <bool HI, bool CPL>
 __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __restrict__ hdr) {
   extern __shared__ double lds[];
   const int njobs = hdr->njobs, total = hdr->total_tiles;
@@ -621,16 +827,23 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
       __syncthreads();
     }
     const long long gb = (long long)(t - J.tile0) * n;
-    const gmem<double>* __restrict__ gin = gview(J.in) + gb;
     gmem<double>* __restrict__ gout = gview(J.out) + gb;
-    const double scale = J.scale;
-    // x-lines: the forward pass reads the line from global memory (the
-    // plane's loads overlap the recurrences), the backward pass works in
-    // LDS; a thread per line, lanes a padded row apart
-    for (int y = tid; y < ny; y += kPT) {
-      double* col = pl + y * PX;
-      const gmem<double>* src = gin + (long long)y * nx;
-      plane_x_p<HI>(p, src, scale, col, nx, fxl);
+    if (CPL && J.nterm > 0) {
+      // coupled input formed in LDS, then the x-lines in LDS
+      plane_couple_p<HI>(J, t - J.tile0, pl, fyl + (2 * p + 1) * ny);
+      __syncthreads();
+      for (int y = tid; y < ny; y += kPT) plane_x_lds_p<HI>(p, pl + y * PX, nx, fxl);
+    } else {
+      const gmem<double>* __restrict__ gin = gview(J.in) + gb;
+      const double scale = J.scale;
+      // x-lines: the forward pass reads the line from global memory (the
+      // plane's loads overlap the recurrences), the backward pass works in
+      // LDS; a thread per line, lanes a padded row apart
+      for (int y = tid; y < ny; y += kPT) {
+        double* col = pl + y * PX;
+        const gmem<double>* src = gin + (long long)y * nx;
+        plane_x_p<HI>(p, src, scale, col, nx, fxl);
+      }
     }
     __syncthreads();
     // y-lines: forward pass in LDS, the backward pass stores each final
@@ -644,20 +857,32 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
 // Launches whose jobs have a degree above 3 take the HI instantiations.
 static bool hi_degree(int pmax) { return pmax >= 4; }
 
-int plane_blocks_per_cu(size_t lds_bytes, int pmax) {
+template <bool CPL>
+static const void* plane_fn(int pmax) {
+  return hi_degree(pmax) ? (const void*)sweep_plane_kernel<true, CPL> : (const void*)sweep_plane_kernel<false, CPL>;
+}
+
+int plane_blocks_per_cu(size_t lds_bytes, int pmax, bool coupled) {
   int n = 0;
-  const void* k = hi_degree(pmax) ? (const void*)sweep_plane_kernel<true> : (const void*)sweep_plane_kernel<false>;
+  const void* k = coupled ? plane_fn<true>(pmax) : plane_fn<false>(pmax);
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kPT, lds_bytes);
   const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds_bytes, 1));
   if (e != hipSuccess || n <= 0) n = by_lds;
   return std::max(1, std::min(n, by_lds));
 }
 
-hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, hipStream_t s) {
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, bool coupled, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (lds_bytes > (size_t)160 * 1024) return hipErrorInvalidValue;
-  if (hi_degree(pmax)) hipLaunchKernelGGL(sweep_plane_kernel<true>, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
-  else hipLaunchKernelGGL(sweep_plane_kernel<false>, dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  if (pmax < 1 || pmax > kMaxP) return hipErrorInvalidValue;
+  const bool hi = hi_degree(pmax);
+  if (coupled) {
+    if (hi) hipLaunchKernelGGL((sweep_plane_kernel<true, true>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+    else hipLaunchKernelGGL((sweep_plane_kernel<false, true>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  } else {
+    if (hi) hipLaunchKernelGGL((sweep_plane_kernel<true, false>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+    else hipLaunchKernelGGL((sweep_plane_kernel<false, false>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+  }
   return hipGetLastError();
 }
 
@@ -729,7 +954,7 @@ hipError_t launch_sweeps(const LaunchHdr* d_hdr, int grid, int W, int max_m, int
 }
 
 hipError_t sweep_set_attributes() {
-  const void* ks[] = {(const void*)sweep_plane_kernel<false>, (const void*)sweep_plane_kernel<true>,
+  const void* ks[] = {plane_fn<false>(1), plane_fn<false>(5), plane_fn<true>(1), plane_fn<true>(5),
                       sweep_fn<false>(16), sweep_fn<false>(8), sweep_fn<false>(4),
                       sweep_fn<true>(16), sweep_fn<true>(8), sweep_fn<true>(4)};
   for (const void* k : ks) {

@@ -20,8 +20,13 @@ hipError_t sweep_set_attributes();
 // a plane of nx x ny unknowns fits when plane_lds_bytes <= 160 KiB.
 size_t plane_lds_bytes(int nx, int ny, int p);
 bool plane_fits(int nx, int ny, int p);
-int plane_blocks_per_cu(size_t lds_bytes, int pmax);
-hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, hipStream_t s);
+// ... with coupling terms (PlaneJob::nterm > 0): the LDS, and whether a
+// plane takes them (at most 4,608 unknowns, and the LDS fits).
+size_t plane_lds_bytes(int nx, int ny, int p, bool coupled);
+bool plane_couple_fits(int nx, int ny, int p);
+// coupled: the launch holds jobs with coupling terms.
+int plane_blocks_per_cu(size_t lds_bytes, int pmax, bool coupled);
+hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int pmax, bool coupled, hipStream_t s);
 
 // P-wave right-hand side: variants 0-2 are tile shapes of the quadrature
 // kernel; variant 3 is the Kronecker (assembled band) form, for jobs

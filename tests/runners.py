@@ -48,7 +48,8 @@ def oracle_elastic(cfg: W.SimConfig, nsteps: int, history: bool = False):
 
 
 # ------------------------------------------------------------------- GPU side
-def gpu_sim(cfg: W.SimConfig, device="cuda", precision=None, u0_full=None, rhs_var=None, rhs_tz=None):
+def gpu_sim(cfg: W.SimConfig, device="cuda", precision=None, u0_full=None, rhs_var=None, rhs_tz=None,
+            coupling=None):
     """Create the GPU simulation.  Without ``u0_full`` the initial field is
     the library's own L2 projection of the seeded data; with it (a full
     coefficient array, e.g. the oracle's projection) both implementations
@@ -56,13 +57,17 @@ def gpu_sim(cfg: W.SimConfig, device="cuda", precision=None, u0_full=None, rhs_v
     parity of the stepping is not blurred by the rounding noise of two
     independent projections (u'' = G^{-1}(-K u) amplifies high-frequency
     differences of u by the stiffness).  rhs_var / rhs_tz: right-hand-side
-    variant and z-tile depth set through ads_set_launch_shape."""
+    variant and z-tile depth set through ads_set_launch_shape; coupling
+    (elasticity): True / False = the couplings in the in-plane sweeps or by
+    separate launches (ads_set_coupling)."""
     import torch
     from paper_1911_08158_amd import Sim
     kw = {} if precision is None else {"precision": precision}
     sim = Sim(cfg, device=device, **kw)
     if rhs_var is not None or rhs_tz is not None:
         sim.set_launch_shape(-1 if rhs_var is None else rhs_var, -1 if rhs_tz is None else rhs_tz)
+    if coupling is not None:
+        sim.set_coupling(coupling)
     if u0_full is None:
         xs = [sim.quad_points(d) for d in range(3)]
         vals = torch.from_numpy(np.ascontiguousarray(W.initial_values(cfg, *xs))).to(device)

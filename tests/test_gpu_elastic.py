@@ -48,6 +48,68 @@ def test_elastic_matches_oracle(cfg, form):
     sim.close()
 
 
+@pytest.mark.parametrize("cfg,fits", [
+    (W.C4.with_(nelem=(6, 5, 7), steps=4, tau=0.02, lam=0.8, mu=0.6, rho=1.3), True),
+    (W.C4.with_(nelem=(5, 6, 4), p=3, q=4, steps=3, tau=0.02, lam=2.0, mu=0.5, rho=0.9), True),
+    (W.C4.with_(nelem=(7, 5, 6), steps=4, tau=0.02, lam=0.8, mu=0.6, rho=1.3, bc="natural"), True),
+    (W.C4.with_(nelem=(9, 7, 5), p=4, q=5, steps=3, tau=0.02), True),
+    # 82 x 72 unknowns per plane: above the 4,608 the in-plane stage takes
+    (W.C4.with_(nelem=(80, 70, 3), steps=3, tau=0.01, bc="natural"), False),
+], ids=lambda c: f"{c.nelem}-p{c.p}-{c.bc}" if hasattr(c, "nelem") else str(c))
+def test_coupling_forms(cfg, fits):
+    """The couplings of the two stages (eq. pre, eq. corr) applied in the
+    input stage of the in-plane sweeps and by separate launches: each
+    against the oracle at every step (1e-12), the two forms within
+    rounding of each other; the library reports the form that ran (the
+    in-plane one only where the plane takes it)."""
+    _cuda()
+    el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
+    runs = {}
+    for fused in (True, False):
+        sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref), coupling=fused)
+        assert sim.coupling_fused == (fused and fits)
+        sim.factor()
+        for k in range(1, cfg.steps + 1):
+            sim.step(1)
+            u, v, _ = sim.get_state()
+            eu = rel_l2(u.cpu().numpy(), el.to_full(hist[k][0]))
+            ev = rel_l2(v.cpu().numpy(), el.to_full(hist[k][1]))
+            assert max(eu, ev) <= TOL, (fused, k, eu, ev)
+        runs[fused] = u.cpu().numpy()
+        sim.close()
+    assert rel_l2(runs[True], runs[False]) <= TOL
+
+
+def test_tuned_coupling_form_matches_oracle():
+    """ads_tune times both coupling forms on the mesh (a tall one with small
+    planes, where the in-plane form has many workgroups) and keeps one; the
+    step then matches the oracle (1e-12)."""
+    _cuda()
+    cfg = W.C4.with_(nelem=(6, 5, 40), steps=3, tau=0.02)
+    el, U0_ref, (_, hist) = oracle_elastic(cfg, cfg.steps, history=True)
+    sim, _ = gpu_sim(cfg, u0_full=el.to_full(U0_ref))
+    assert not sim.coupling_fused   # default: separate launches
+    sim.factor()
+    sim.tune()
+    print(f"tuned coupling form: {'in-plane' if sim.coupling_fused else 'separate'}", flush=True)
+    for k in range(1, cfg.steps + 1):
+        sim.step(1)
+        u, v, _ = sim.get_state()
+        assert max(rel_l2(u.cpu().numpy(), el.to_full(hist[k][0])),
+                   rel_l2(v.cpu().numpy(), el.to_full(hist[k][1]))) <= TOL, k
+    sim.close()
+
+
+def test_coupling_form_refused_for_pwave():
+    _cuda()
+    from paper_1911_08158_amd import AdsError
+    sim, _ = gpu_sim(W.C1.with_(nelem=(4, 4, 4), steps=1))
+    with pytest.raises(AdsError):
+        sim.set_coupling(False)
+    assert not sim.coupling_fused
+    sim.close()
+
+
 # Mixed mode (FP32 stiffness-type passes on FP64 differences, FP64 mass
 # channels, z-pass and update): relative L2 error of U^n against the FP64
 # oracle after the 100 steps of C4.
