@@ -385,10 +385,13 @@ ads_status ads_pool_step_times(ads_pool* pool, double* host_ms, int32_t cap, int
  * Kronecker form, and in mixed mode with one the MFMA x-stage (variant 4),
  * on the batch's own jobs; every sweep class times tile
  * widths of 4, 8 and 16 lines per wave (on a copy of its jobs that solves
- * in place with a plain store, so that no state changes).  Each class keeps
+ * in place with a plain store, so that no state changes); with elasticity
+ * in the batch, the two forms of the couplings (ads_set_coupling) over the
+ * batch's coupling and in-plane launches, for every pooled elasticity
+ * simulation at once.  Each class keeps
  * its fastest shape; the choices are cached per class and batch shape and
  * the graph is captured again at the next step.  *nchanged receives the
- * number of classes whose shape changed; host_shape (may be NULL; cap
+ * number of classes (and 1 for the coupling form) whose shape changed; host_shape (may be NULL; cap
  * entries, launch positions as in ads_pool_profile_read) the shape of each
  * launch: right-hand sides their variant, sweeps their tile width, other
  * launches 0, launches with no simulation in the batch -1. */

@@ -1701,6 +1701,9 @@ struct ads_pool {
   // default the Kronecker form (HBM-bound), and the quadrature's 14/13-row
   // tiles (variant 0) with a field; ads_pool_tune measures the others
   int var[kMaxP][2][2];
+  // elasticity couplings of every pooled simulation: separate launches or
+  // in the in-plane sweeps (ads_pool_tune times both on the batch)
+  bool couple_fused = false;
   std::vector<int> w_force;        // per launch class: sweep tile width chosen by the tuner (0: default)
   size_t tune_off = 0;             // table region for the tuner's timing launches
   std::map<std::string, int> tune_cache;   // launch class + batch shape -> choice
@@ -1770,13 +1773,22 @@ void pool_build_seq(ads_pool* P, int ncu) {
   P->tab_bytes = off;
 }
 
-// The pool chooses the P-wave right-hand-side variant per class: an active
-// simulation whose step was built with another (a wave-speed field set
-// after admission, or a class retuned) is rebuilt with the class's.
+// The pool chooses the P-wave right-hand-side variant per class and the
+// form of the elasticity couplings: an active simulation whose step was
+// built with another (a wave-speed field set after admission, or the pool
+// retuned) is rebuilt with the pool's.
 ads_status pool_align(ads_pool* P) {
   for (ads_pool::Slot& sl : P->slots) {
-    if (!sl.active || sl.sim->elastic || !quadrature_ok(sl.sim->p)) continue;
+    if (!sl.active) continue;
     ads_sim* s = sl.sim;
+    if (s->elastic) {
+      if (s->couple_fused == P->couple_fused) continue;
+      s->couple_fused = P->couple_fused;
+      ads_status st = build_launches(s);
+      if (st != ADS_OK) return st;
+      continue;
+    }
+    if (!quadrature_ok(s->p)) continue;
     const int want = P->var[s->p - 1][s->mixed ? 1 : 0][s->coef != nullptr ? 1 : 0];
     if (rhs_form_var(s->rhs_var, s->coef != nullptr, s->mixed) == want) continue;
     s->rhs_var = want;
@@ -2343,6 +2355,55 @@ ads_status ads_pool_tune(ads_pool* P, int32_t* nchanged, int32_t* host_shape, in
       }
       P->w_force[li] = best;
       if (best != before) ++*nchanged;
+      if ((st = pool_rebuild(P)) != ADS_OK) return st;
+    }
+  }
+  // elasticity couplings: separate launches or in the in-plane sweeps,
+  // timed over the batch's coupling and in-plane classes in both branches
+  // (they write only the step's temporaries); planes of every simulation
+  // share the in-plane launches, so the form can pay in a batch where it
+  // does not for one simulation
+  {
+    std::vector<std::string> shp;
+    for (const ads_pool::Slot& sl : P->slots)
+      if (sl.active && sl.sim->elastic && plane_couple_fits(sl.sim->nf[0], sl.sim->nf[1], sl.sim->p))
+        shp.push_back(std::to_string(sl.sim->p) + ":" + std::to_string(sl.sim->nf[0]) + "x" +
+                      std::to_string(sl.sim->nf[1]) + "x" + std::to_string(sl.sim->nf[2]));
+    if (!shp.empty()) {
+      std::sort(shp.begin(), shp.end());
+      std::string key = "C";
+      for (const std::string& x : shp) key += "/" + x;
+      const bool before = P->couple_fused;
+      int best = before ? 1 : 0;
+      auto it = P->tune_cache.find(key);
+      if (it != P->tune_cache.end()) {
+        best = it->second;
+      } else {
+        double ms[2] = {0.0, 0.0};
+        for (int f = 0; f < 2; ++f) {
+          P->couple_fused = f != 0;
+          if ((st = pool_rebuild(P)) != ADS_OK) return st;
+          auto go = [&]() -> hipError_t {
+            for (size_t li = 0; li < P->seq.size(); ++li) {
+              const PoolLaunch& L = P->seq[li];
+              if (L.kind != Launch::KRON && L.kind != Launch::PLANE) continue;
+              for (int b = 0; b < kPoolBranches; ++b) {
+                if (!P->nonempty[li * kPoolBranches + b]) continue;
+                const LaunchHdr* h = (const LaunchHdr*)(P->d_tab + L.off + b * L.boff);
+                const hipError_t e = L.kind == Launch::KRON ? launch_kron(h, L.grid, L.p, P->stream)
+                                                            : launch_planes(h, L.grid, L.lds, L.p, L.coupled, P->stream);
+                if (e != hipSuccess) return e;
+              }
+            }
+            return hipSuccess;
+          };
+          if ((st = timed(go, &ms[f])) != ADS_OK) return st;
+        }
+        best = ms[1] < ms[0] ? 1 : 0;
+        P->tune_cache[key] = best;
+      }
+      P->couple_fused = best != 0;
+      if (P->couple_fused != before) ++*nchanged;
       if ((st = pool_rebuild(P)) != ADS_OK) return st;
     }
   }

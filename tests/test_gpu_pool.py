@@ -376,3 +376,55 @@ def test_pool_tune_with_field_in_mixed_mode():
         e = rel_l2(u, pw.to_full(hist[-1][0]))
         assert 0 < e <= 1e-6, e
     pool.close()
+
+
+def test_pool_tune_chooses_coupling_form_bitwise_with_alone():
+    """The pool's tuner times the two forms of the elasticity couplings on
+    the batch (its in-plane launches hold the planes of every simulation)
+    and applies its choice to every pooled elasticity simulation; each then
+    runs bitwise as the same simulation alone that switches to that form
+    after ads_factor (the start, computed there, used the default form, as
+    in the pool), and the two elasticity runs stay within 1e-12 of the
+    oracle."""
+    _cuda()
+    import torch
+    from paper_1911_08158_amd import Pool
+    from runners import oracle_elastic
+    cfgs = [W.C4.with_(nelem=(6, 5, 40), tau=0.02, steps=4),
+            W.C4.with_(nelem=(5, 6, 30), p=3, q=4, tau=0.02, steps=4, lam=2.0, mu=0.5),
+            W.C1.with_(nelem=(9, 8, 7), tau=0.01, steps=4)]
+    pool = Pool(128 << 20, max_slots=4)
+    sims, refs = [], []
+    for c in cfgs:
+        s = pool.admit(c)
+        _setup(s, c)
+        pool.activate(s)
+        sims.append(s)
+    n, _ = pool.tune()
+    forms = [s.coupling_fused for s in sims]
+    print(f"pool coupling form: {'in-plane' if forms[0] else 'separate'} ({n} changed)", flush=True)
+    assert forms[0] == forms[1] and not forms[2]
+    n2, _ = pool.tune()
+    assert n2 == 0
+    pool.step(4)
+    pooled = [[t.cpu().numpy() for t in s.get_state() if t is not None] for s in sims]
+    pool.close()
+    for c, fused, got in zip(cfgs, forms, pooled):
+        sim, _ = gpu_sim(c)
+        sim.factor()
+        if c.problem == "elastic":
+            sim.set_coupling(fused)
+        sim.step(4)
+        want = [t.cpu().numpy() for t in sim.get_state() if t is not None]
+        sim.close()
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y)
+        if c.problem == "elastic":
+            el, U0, (_, hist) = oracle_elastic(c, c.steps, history=True)
+            sim, _ = gpu_sim(c, u0_full=el.to_full(U0), coupling=fused)
+            sim.factor()
+            sim.step(4)
+            u, v, _ = sim.get_state()
+            assert max(rel_l2(u.cpu().numpy(), el.to_full(hist[4][0])),
+                       rel_l2(v.cpu().numpy(), el.to_full(hist[4][1]))) <= 1e-12
+            sim.close()
