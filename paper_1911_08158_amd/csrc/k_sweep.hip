@@ -371,11 +371,10 @@ __global__ __launch_bounds__(kNT, 2) void sweep_kernel(const LaunchHdr* __restri
 // the x-lines' LDS accesses (lanes a row apart) and the y-lines' (lanes
 // adjacent) are free of bank conflicts.
 
-constexpr int kPT = 256;   // threads per plane workgroup
-// coupled input (plane_couple): plane positions per thread, and the
-// largest plane it takes
-constexpr int kCoupleNC = 18;
-constexpr int kCoupleMaxN = kCoupleNC * kPT;
+constexpr int kPT = 256;    // threads per plane workgroup
+constexpr int kPTC = 512;   // ... with coupling terms (more loads in flight)
+// coupled input (plane_couple): the largest plane it takes
+constexpr int kCoupleMaxN = 4608;
 
 __device__ __forceinline__ int find_job_plane(const PlaneJob* jobs, int njobs, int tile) {
   int lo = 0, hi = njobs - 1;
@@ -604,21 +603,22 @@ __device__ __forceinline__ void plane_y_p(int p, double* col, int PX, gmem<doubl
 // planes that reach z are combined with row z of T_z into A (terms with the
 // source and z-band of the term before them reuse its A), the x-band takes
 // A to B, and the y-band of B is accumulated into pl (which holds the base
-// input from the first term on).  A thread owns the positions tid + i kPT
+// input from the first term on).  A thread owns the positions tid + i NT
 // of the plane and takes them in groups of G, the loads of a group in
 // flight together.  Work space wk (after the factor rows): A [n], B [n],
 // the band rows of two terms [2][(nx + ny)(2p+1)] (double-buffered, so that
 // staging the next term's rows needs no barrier of its own).  Two barriers
 // per term.
-template <int P>
+template <int P, int NT>
 __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
   constexpr int B = 2 * P + 1;
-  constexpr int G = P <= 2 ? 6 : (P == 3 ? 4 : 3);   // positions per group (global loads)
+  constexpr int NC = (kCoupleMaxN + NT - 1) / NT;   // positions per thread
+  constexpr int G = P <= 2 ? 5 : 3;   // positions per group (global loads)
   constexpr int GL = 3;               // ... in the LDS passes
   const int nx = J.nx, ny = J.ny, nz = J.nz, n = nx * ny, PX = nx + 1;
   const int tid = threadIdx.x;
-  // (y, x) of position k + kPT from those of k
-  const int dy = kPT / nx, dx = kPT - dy * nx;
+  // (y, x) of position k + NT from those of k
+  const int dy = NT / nx, dx = NT - dy * nx;
   auto next = [&](int& y, int& x) {
     y += dy;
     x += dx;
@@ -638,16 +638,16 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
     {
       const gmem<double>* tx = gview(T.T[0]);
       const gmem<double>* ty = gview(T.T[1]);
-      for (int k0 = 0; k0 < tbs; k0 += 4 * kPT) {
+      for (int k0 = 0; k0 < tbs; k0 += 4 * NT) {
         double v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int k = min(k0 + tid + r * kPT, tbs - 1);
+          const int k = min(k0 + tid + r * NT, tbs - 1);
           v[r] = k < nx * B ? tx[k] : ty[k - nx * B];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (k0 + tid + r * kPT < tbs) tb[k0 + tid + r * kPT] = v[r];
+          if (k0 + tid + r * NT < tbs) tb[k0 + tid + r * NT] = v[r];
       }
     }
     if (t == 0 || T.src != J.term[t - 1].src || T.T[2] != J.term[t - 1].T[2]) {
@@ -670,25 +670,25 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
       }
       int y = ty0, x = tx0;
 #pragma unroll 1
-      for (int i0 = 0; i0 < kCoupleNC; i0 += G) {
-        const int kb = tid + i0 * kPT;
+      for (int i0 = 0; i0 < NC; i0 += G) {
+        const int kb = tid + i0 * NT;
         if (kb >= n) break;
         double a[G], b[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) {
           a[j] = 0.0;
-          b[j] = in != nullptr ? in[min(kb + j * kPT, n - 1)] : 0.0;
+          b[j] = in != nullptr ? in[min(kb + j * NT, n - 1)] : 0.0;
         }
 #pragma unroll
         for (int kk = 0; kk < B; ++kk) {
           const gmem<double>* sp = src + zo[kk];
 #pragma unroll
-          for (int j = 0; j < G; ++j) a[j] = fma(w[kk], sp[min(kb + j * kPT, n - 1)], a[j]);
+          for (int j = 0; j < G; ++j) a[j] = fma(w[kk], sp[min(kb + j * NT, n - 1)], a[j]);
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-          if (kb + j * kPT < n) {
-            A[kb + j * kPT] = a[j];
+          if (kb + j * NT < n) {
+            A[kb + j * NT] = a[j];
             if (t == 0) pl[y * PX + x] = b[j];
           }
           next(y, x);
@@ -701,12 +701,12 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
     {
       int y = ty0, x = tx0;
 #pragma unroll 1
-      for (int i0 = 0; i0 < kCoupleNC; i0 += GL) {
-        const int kb = tid + i0 * kPT;
+      for (int i0 = 0; i0 < NC; i0 += GL) {
+        const int kb = tid + i0 * NT;
         if (kb >= n) break;
 #pragma unroll
         for (int j = 0; j < GL; ++j) {
-          const int k = kb + j * kPT;
+          const int k = kb + j * NT;
           if (k < n) {
             const double* tr = tb + x * B;
             const double* ar = A + y * nx;
@@ -728,12 +728,12 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
       const double cf = T.coef;
       int y = ty0, x = tx0;
 #pragma unroll 1
-      for (int i0 = 0; i0 < kCoupleNC; i0 += GL) {
-        const int kb = tid + i0 * kPT;
+      for (int i0 = 0; i0 < NC; i0 += GL) {
+        const int kb = tid + i0 * NT;
         if (kb >= n) break;
 #pragma unroll
         for (int j = 0; j < GL; ++j) {
-          const int k = kb + j * kPT;
+          const int k = kb + j * NT;
           if (k < n) {
             const double* tr = tb + (nx + y) * B;
             double v = 0.0;
@@ -754,7 +754,7 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
   const double scale = J.scale;
   {
     int y = ty0, x = tx0;
-    for (int k = tid; k < n; k += kPT) {
+    for (int k = tid; k < n; k += NT) {
       pl[y * PX + x] *= scale;
       next(y, x);
     }
@@ -764,12 +764,12 @@ __device__ void plane_couple(const PlaneJob& J, int z, double* pl, double* wk) {
 template <bool HI>
 __device__ __forceinline__ void plane_couple_p(const PlaneJob& J, int z, double* pl, double* wk) {
   if constexpr (HI) {
-    if (J.p == 5) return plane_couple<5>(J, z, pl, wk);
-    if (J.p == 4) return plane_couple<4>(J, z, pl, wk);
+    if (J.p == 5) return plane_couple<5, kPTC>(J, z, pl, wk);
+    if (J.p == 4) return plane_couple<4, kPTC>(J, z, pl, wk);
   }
-  if (J.p == 1) plane_couple<1>(J, z, pl, wk);
-  else if (J.p == 2) plane_couple<2>(J, z, pl, wk);
-  else plane_couple<3>(J, z, pl, wk);
+  if (J.p == 1) plane_couple<1, kPTC>(J, z, pl, wk);
+  else if (J.p == 2) plane_couple<2, kPTC>(J, z, pl, wk);
+  else plane_couple<3, kPTC>(J, z, pl, wk);
 }
 
 // x-lines of a plane already in LDS (the coupled input): both passes in LDS
@@ -792,7 +792,8 @@ __device__ __forceinline__ void plane_x_lds_p(int p, double* col, int nx, const 
 // CPL: the launch holds jobs with coupling terms (a separate instantiation,
 // so that the plain in-plane sweeps keep their registers).
 template <bool HI, bool CPL>
-__global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __restrict__ hdr) {
+__global__ __launch_bounds__(CPL ? kPTC : kPT, 1) void sweep_plane_kernel(const LaunchHdr* __restrict__ hdr) {
+  constexpr int NT = CPL ? kPTC : kPT;
   extern __shared__ double lds[];
   const int njobs = hdr->njobs, total = hdr->total_tiles;
   const PlaneJob* __restrict__ jobs = hdr_jobs<PlaneJob>(hdr);
@@ -813,16 +814,16 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
       const gmem<double>* ly = gview(J.fy.L);
       const gmem<double>* uy = gview(J.fy.U);
       const gmem<double>* ry = gview(J.fy.rd);
-      for (int k = tid; k < nx * p; k += kPT) {
+      for (int k = tid; k < nx * p; k += NT) {
         fxl[k] = lx[k];
         fxl[nx * p + k] = ux[k];
       }
-      for (int k = tid; k < nx; k += kPT) fxl[2 * nx * p + k] = rx[k];
-      for (int k = tid; k < ny * p; k += kPT) {
+      for (int k = tid; k < nx; k += NT) fxl[2 * nx * p + k] = rx[k];
+      for (int k = tid; k < ny * p; k += NT) {
         fyl[k] = ly[k];
         fyl[ny * p + k] = uy[k];
       }
-      for (int k = tid; k < ny; k += kPT) fyl[2 * ny * p + k] = ry[k];
+      for (int k = tid; k < ny; k += NT) fyl[2 * ny * p + k] = ry[k];
       staged = jb;
       __syncthreads();
     }
@@ -832,14 +833,14 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
       // coupled input formed in LDS, then the x-lines in LDS
       plane_couple_p<HI>(J, t - J.tile0, pl, fyl + (2 * p + 1) * ny);
       __syncthreads();
-      for (int y = tid; y < ny; y += kPT) plane_x_lds_p<HI>(p, pl + y * PX, nx, fxl);
+      for (int y = tid; y < ny; y += NT) plane_x_lds_p<HI>(p, pl + y * PX, nx, fxl);
     } else {
       const gmem<double>* __restrict__ gin = gview(J.in) + gb;
       const double scale = J.scale;
       // x-lines: the forward pass reads the line from global memory (the
       // plane's loads overlap the recurrences), the backward pass works in
       // LDS; a thread per line, lanes a padded row apart
-      for (int y = tid; y < ny; y += kPT) {
+      for (int y = tid; y < ny; y += NT) {
         double* col = pl + y * PX;
         const gmem<double>* src = gin + (long long)y * nx;
         plane_x_p<HI>(p, src, scale, col, nx, fxl);
@@ -848,7 +849,7 @@ __global__ __launch_bounds__(kPT, 1) void sweep_plane_kernel(const LaunchHdr* __
     __syncthreads();
     // y-lines: forward pass in LDS, the backward pass stores each final
     // value (a row of adjacent lanes: coalesced) instead of writing it back
-    for (int x = tid; x < nx; x += kPT) {
+    for (int x = tid; x < nx; x += NT) {
       plane_y_p<HI>(p, pl + x, PX, gout + x, nx, ny, fyl);
     }
   }
@@ -865,7 +866,7 @@ static const void* plane_fn(int pmax) {
 int plane_blocks_per_cu(size_t lds_bytes, int pmax, bool coupled) {
   int n = 0;
   const void* k = coupled ? plane_fn<true>(pmax) : plane_fn<false>(pmax);
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kPT, lds_bytes);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, coupled ? kPTC : kPT, lds_bytes);
   const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds_bytes, 1));
   if (e != hipSuccess || n <= 0) n = by_lds;
   return std::max(1, std::min(n, by_lds));
@@ -877,8 +878,8 @@ hipError_t launch_planes(const LaunchHdr* d_hdr, int grid, size_t lds_bytes, int
   if (pmax < 1 || pmax > kMaxP) return hipErrorInvalidValue;
   const bool hi = hi_degree(pmax);
   if (coupled) {
-    if (hi) hipLaunchKernelGGL((sweep_plane_kernel<true, true>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
-    else hipLaunchKernelGGL((sweep_plane_kernel<false, true>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
+    if (hi) hipLaunchKernelGGL((sweep_plane_kernel<true, true>), dim3(grid), dim3(kPTC), lds_bytes, s, d_hdr);
+    else hipLaunchKernelGGL((sweep_plane_kernel<false, true>), dim3(grid), dim3(kPTC), lds_bytes, s, d_hdr);
   } else {
     if (hi) hipLaunchKernelGGL((sweep_plane_kernel<true, false>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
     else hipLaunchKernelGGL((sweep_plane_kernel<false, false>), dim3(grid), dim3(kPT), lds_bytes, s, d_hdr);
