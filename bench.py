@@ -62,7 +62,7 @@ TRAFFIC = {
     "rhs": {"sources": ["paper_1911_08158_amd/csrc/k_rhs_band.hip", "paper_1911_08158_amd/csrc/common.hpp"],
             "sha256": "271389f7f6887f3aa213f9b0ad3774af340dc51eb96fa4cbf3ff264da3bce267", "fetch_kib": 36047.5, "write_kib": 65536.0},
     "sweep_z": {"sources": ["paper_1911_08158_amd/csrc/k_sweep.hip", "paper_1911_08158_amd/csrc/common.hpp"],
-                "sha256": "9ef6f2f7d1359b1777cc74f89cf3d96457930709c581413ad99a6f119acc9a40", "fetch_kib": 98499.2, "write_kib": 196608.1},
+                "sha256": "9ef941a8a4493d444ea0c95fd4d37e6f3fa0d2633dae2002dfc6ebd3cbeb76f6", "fetch_kib": 98513.4, "write_kib": 196608.1},
     "fetch_scale": 2.0, "write_scale": 1.0,
     "batch": 4,
 }
