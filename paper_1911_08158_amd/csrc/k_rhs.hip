@@ -135,10 +135,15 @@ struct RhsGeom {
   static constexpr int NZW = WR * TXH;  // z-stage items of one wave
   static constexpr int NZ = (NZW + 63) / 64;
   static constexpr int NF = (NC + NT - 1) / NT;   // predictor loads per thread
-  // Gauss-row buffer: row r, column x at (r & 1) * H + (r >> 1) * TXH + x;
-  // H = 16 (mod 32) puts the two rows read by one half-wave on disjoint
-  // LDS banks
-  static constexpr int HR = (R / 2) * TXH;
+  // Gauss-row buffer: row r, column x at (r & 1) * H + (r >> 1) * RP + x;
+  // H = 16 (mod 32) puts the two rows read by one half-wave (rows r, r+1 of
+  // the x-stage) on disjoint LDS banks.  In FP32 the row pitch RP keeps
+  // rows r and r + q, which one half-wave of the y-stage stores, 16 banks
+  // apart as well: RP = 0 (mod 32) for odd q, RP = 8 (mod 16) for even q
+  static constexpr int RP = sizeof(T) != 4 ? TXH
+                            : (Q % 2) ? (TXH + 31) / 32 * 32
+                                      : (TXH + 7) / 16 * 16 + 8;
+  static constexpr int HR = (R / 2) * RP;
   static constexpr int H = HR + ((16 - HR % 32) + 32) % 32;
   static constexpr int SBC = 2 * H;     // one component plane
   static constexpr int TS = 2 * Q * P + (sizeof(T) == 4 ? (4 - (2 * Q * P) % 4) % 4 : 0);
@@ -167,6 +172,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
   const RhsJob* __restrict__ jobs = hdr_jobs<RhsJob>(hdr);
   using Gm = RhsGeom<T, P, Q, TY_, NT_, CF>;
   constexpr int p = Gm::p, TX = Gm::TX, TY = Gm::TY, TXH = Gm::TXH, TYH = Gm::TYH, NC = Gm::NC, EY = Gm::EY,
+                RP = Gm::RP,
                 NT = Gm::NT, NW = Gm::NW, WE = Gm::WE, NZW = Gm::NZW, NZ = Gm::NZ,
                 NF = Gm::NF, H = Gm::H, SBC = Gm::SBC, TS = Gm::TS;
   constexpr int NRW = WE * Q / 4;       // Gauss rows per row group
@@ -175,11 +181,11 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
   T* zcall = ring + P * NC;                    // [NW][Q][2][NZW]
   T* sb = zcall + NW * Q * 2 * NZW;            // [2][NCH][SBC]
   T* tyl = sb + 2 * Gm::NCH * SBC;             // [EY][TS]: N[Q][P] then D[Q][P] (My, Ky without a field)
-  auto rowpos = [](int r) { return (r & 1) * H + (r >> 1) * TXH; };
+  auto rowpos = [](int r) { return (r & 1) * H + (r >> 1) * RP; };
   // position of row r0 + k from that of row r0 (par = r0 & 1)
   auto rowstep = [](int pos0, int par, int k) {
-    const int even = (k & 1) * H + (k >> 1) * TXH;
-    const int odd = (k & 1) ? ((k + 1) >> 1) * TXH - H : (k >> 1) * TXH;
+    const int even = (k & 1) * H + (k >> 1) * RP;
+    const int odd = (k & 1) ? ((k + 1) >> 1) * RP - H : (k >> 1) * RP;
     return pos0 + (par ? odd : even);
   };
 
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
     xa = gy;   // without a field: the row's local y-slot
   }
   // x-stage rows of this row group: wave rows 4i + grp (same parity as
-  // grp, so row i sits 2i rows of TXH further on)
+  // grp, so row i sits 2i rows of RP further on)
   const int xrow0 = rowpos(wv * WE * Q + grp);
   // MFMA x-stage (variant MX): lane = 4 * (x-element slot mb) + mj, mj the
   // Gauss row of the group of four for the B operand and the output, and
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
         for (int i = 0; i < NRW; ++i) {
           if constexpr (MF) {
             // rows 4i + mj of the three channels, column of x-element mb
-            T* rm = sbb + xrowm0 + 2 * i * TXH;
+            T* rm = sbb + xrowm0 + 2 * i * RP;
             float cq[4];
 #pragma unroll
             for (int gx = 0; gx < 4; ++gx) cq[gx] = (gx < Q && cqok[i]) ? (float)cqr[i][gx < Q ? gx : 0] : 0.f;
@@ -726,7 +732,7 @@ __global__ __launch_bounds__(NT_, (sizeof(T) == 4 && P == 3) ? (CF ? 3 : (NT_ <=
             }
             continue;
           }
-          T* row = sbb + xrow0 + 2 * i * TXH;
+          T* row = sbb + xrow0 + 2 * i * RP;
           // wave-speed field: the lane's q points of this Gauss row (0 outside the mesh)
           T cq[Q];
           if constexpr (CF) {
