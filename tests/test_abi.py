@@ -23,8 +23,8 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     hdr = open(os.path.join(ROOT, "include", "ads.h")).read()
-    names = set(re.findall(r"^\s*(?:ads_status|const char\*)\s+(ads_\w+)\s*\(", hdr, re.M))
-    assert len(names) >= 14
+    names = set(re.findall(r"^\s*(?:ads_status|const char\*|int32_t)\s+(ads_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 14 and "ads_coupling_fused" in names
     for n in sorted(names):
         assert hasattr(lib, n), n
 
@@ -145,3 +145,14 @@ def test_gauss_rules_above_p_plus_one_accepted(lib):
     assert binding.workspace_bytes(b) > binding.workspace_bytes(a)
     xs = binding.quad_points(b, 0)
     assert xs.size == 4 * 5 and np.all(np.diff(xs) > 0)
+
+
+def test_coupling_form_host_checks(lib):
+    """ads_set_coupling refuses a NULL simulation; ads_coupling_fused of a
+    NULL simulation is 0 (host logic only, no device call)."""
+    lib.ads_set_coupling.restype = ctypes.c_int32
+    lib.ads_set_coupling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.ads_coupling_fused.restype = ctypes.c_int32
+    lib.ads_coupling_fused.argtypes = [ctypes.c_void_p]
+    assert lib.ads_set_coupling(None, 1) != 0
+    assert lib.ads_coupling_fused(None) == 0
