@@ -328,13 +328,18 @@ def measure_accuracy(cfg, steps):
             "v": "u'", "a": "u''", "oracle_seconds": round(t_oracle, 1), "errors": out}
 
 
-def measure_elastic(cfg, steps, warmup, precision="fp64"):
+def measure_elastic(cfg, steps, warmup, precision="fp64", coupling=None):
     """Elasticity (alternating-triangular step), one simulation, per-kernel
     launches.  The timed steps carry no events; kernel times per kind come
-    from a separate profiled pass."""
+    from a separate profiled pass.  coupling: None keeps the default form of
+    the couplings (separate launches), True / False sets it before the
+    factorization (ads_set_coupling)."""
     import torch
     from paper_1911_08158_amd import Sim
     sim = Sim(cfg, device="cuda:0", precision=precision)
+    if coupling is not None:
+        sim.set_coupling(coupling)
+    fused = sim.coupling_fused
     setup_sim(sim, cfg)
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -353,8 +358,9 @@ def measure_elastic(cfg, steps, warmup, precision="fp64"):
     for k, m in zip(kinds, ms):
         per[k] = round(per.get(k, 0.0) + float(m), 5)
     return {
-        "workload": f"elasticity {cfg.nelem[0]}^3 elements p={cfg.p} (3 x {cfg.n[0]}^3 DOFs) tau={cfg.tau}, "
-                    f"{precision}",
+        "workload": f"elasticity {'x'.join(map(str, cfg.nelem))} elements p={cfg.p} "
+                    f"(3 x {'x'.join(map(str, cfg.n))} DOFs) tau={cfg.tau}, {precision}",
+        "couplings": "in the in-plane sweeps" if fused else "separate launches",
         "dof_steps_per_s": cfg.dofs() * steps / wall,
         "ms_per_step": wall / steps * 1e3,
         "ms_per_step_by_kind": per,
@@ -564,7 +570,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving mix: number of requests")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "accuracy", "quadrature", "grid", "hbm"],
+    ap.add_argument("--only", choices=["plain", "batched", "serve", "elastic", "coupling", "accuracy", "quadrature",
+                                       "grid", "hbm"],
                     default=None,
                     help="time one form only (short profiling runs); prints that form's numbers")
     args = ap.parse_args()
@@ -592,6 +599,14 @@ def main():
         for prec in ("fp64", "mixed_fp32"):
             print(json.dumps({"form": f"elastic_{prec}", **measure_elastic(W.C4, args.steps, args.warmup, prec)}),
                   flush=True)
+        return
+    if args.only == "coupling":
+        # the two forms of the elasticity couplings, FP64: 64^3 (64 z-planes)
+        # and a tall mesh of small planes (254 z-planes of 14 x 14 free unknowns)
+        for c in (W.C4, W.C4.with_(nelem=(14, 14, 254))):
+            for fused in (False, True):
+                r = measure_elastic(c, args.steps, args.warmup, "fp64", coupling=fused)
+                print(json.dumps({"form": f"elastic_coupling_{'inplane' if fused else 'separate'}", **r}), flush=True)
         return
     if args.only == "quadrature":
         for prec in ("fp64", "mixed_fp32"):
