@@ -390,9 +390,13 @@ def test_pool_tune_chooses_coupling_form_bitwise_with_alone():
     import torch
     from paper_1911_08158_amd import Pool
     from runners import oracle_elastic
+    # the third elasticity mesh has planes of 82 x 72 unknowns, too large
+    # for the in-plane stage: it keeps separate launches, and its in-plane
+    # jobs share the launch class of the others' coupled ones
     cfgs = [W.C4.with_(nelem=(6, 5, 40), tau=0.02, steps=4),
             W.C4.with_(nelem=(5, 6, 30), p=3, q=4, tau=0.02, steps=4, lam=2.0, mu=0.5),
-            W.C1.with_(nelem=(9, 8, 7), tau=0.01, steps=4)]
+            W.C1.with_(nelem=(9, 8, 7), tau=0.01, steps=4),
+            W.C4.with_(nelem=(80, 70, 3), tau=0.01, steps=4, bc="natural")]
     pool = Pool(128 << 20, max_slots=4)
     sims, refs = [], []
     for c in cfgs:
@@ -403,7 +407,7 @@ def test_pool_tune_chooses_coupling_form_bitwise_with_alone():
     n, _ = pool.tune()
     forms = [s.coupling_fused for s in sims]
     print(f"pool coupling form: {'in-plane' if forms[0] else 'separate'} ({n} changed)", flush=True)
-    assert forms[0] == forms[1] and not forms[2]
+    assert forms[0] == forms[1] and not forms[2] and not forms[3]
     n2, _ = pool.tune()
     assert n2 == 0
     pool.step(4)
